@@ -1,0 +1,149 @@
+"""Pins of the oracle's dual function (Section 3, Appendix A1/A2) against
+closed forms, brute force, the paper's own normalised formulas and calculus."""
+import numpy as np
+import pytest
+
+from oracle import dual as D
+from oracle import ref
+from paper_2406_13191_amd import synth
+
+
+def _rand_multipliers(rng, K, scale=5.0, frac=0.3):
+    lam = float(rng.uniform(0, 80))
+    mu = rng.exponential(scale, 2 * K.n_line) * (rng.random(2 * K.n_line) < frac)
+    return lam, mu
+
+
+def test_inner_argmin_vs_grid():
+    rng = np.random.default_rng(1)
+    n = 400
+    lo = rng.uniform(-5, 5, n)
+    hi = lo + rng.uniform(0, 10, n)
+    a = rng.normal(0, 3, n)
+    a[:20] = 0.0
+    M = np.where(rng.random(n) < 0.5, 0.0, rng.uniform(0.01, 2, n))
+    x = D.inner_argmin(a, M, lo, hi)
+    grid = lo[:, None] + (hi - lo)[:, None] * np.linspace(0, 1, 20001)[None, :]
+    f = M[:, None] * grid ** 2 + a[:, None] * grid
+    fbest = f.min(axis=1)
+    fx = M * x * x + a * x
+    assert np.all(fx <= fbest + 1e-9)
+    assert np.all((x >= lo) & (x <= hi))
+    # ties of the linear case return the midpoint
+    lin0 = (M == 0) & (a == 0)
+    np.testing.assert_allclose(x[lin0], 0.5 * (lo + hi)[lin0])
+
+
+def test_dual_norm_identity():
+    # Appendix A2: min over [l, u] of r p = r m - sigma |r| (m midpoint,
+    # sigma half width), i.e. -||.||_1 on the unit infinity ball
+    rng = np.random.default_rng(2)
+    lo = rng.uniform(0, 50, 100)
+    hi = lo + rng.uniform(0, 100, 100)
+    r = rng.normal(0, 10, 100)
+    x = D.inner_argmin(r, np.zeros(100), lo, hi)
+    m, s = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    np.testing.assert_allclose(r * x, r * m - s * np.abs(r), rtol=1e-13, atol=1e-10)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_lp_dual_equals_paper_normalised_form(seed):
+    # Eq. (LP dual) on the data normalised per Appendix A1 (plus the constant
+    # the substitution moves out) equals the box-form dual function
+    p = synth.make_problem("tiny30", seed)
+    K = D.canonical(p)
+    rng = np.random.default_rng(seed)
+    for _ in range(20):
+        lam, mu = _rand_multipliers(rng, K)
+        g = D.dual_value(K, lam, mu).g
+        assert abs(g - D.g_l_paper(K, lam, mu)) <= 1e-9 * max(1.0, abs(g))
+
+
+def test_qp_dual_s_form():
+    # Eq. (QP_finalgamma): g_q(s*) equals the closed-form dual, and g_q(s) is
+    # no larger for any other s ("exactly agree" claim of Section 3.2)
+    net, p = synth.make_network("geo300q", 7)
+    K = D.canonical(p)
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        lam, mu = _rand_multipliers(rng, K)
+        g = D.dual_value(K, lam, mu).g
+        s = D.s_star(K, lam, mu)
+        assert abs(D.g_q_paper(K, lam, mu, s) - g) <= 1e-9 * abs(g)
+        for _ in range(5):
+            s2 = s + rng.normal(0, 1.0, s.size)
+            assert D.g_q_paper(K, lam, mu, s2) <= g + 1e-9 * abs(g)
+
+
+def test_supergradient_matches_central_differences_qp():
+    net, p = synth.make_network("geo300q", 7)
+    K = D.canonical(p)
+    rng = np.random.default_rng(4)
+    lam, mu = _rand_multipliers(rng, K, scale=2.0)
+    ev = D.dual_value(K, lam, mu)
+    h = 1e-4
+    gl = (D.dual_value(K, lam + h, mu).g - D.dual_value(K, lam - h, mu).g) / (2 * h)
+    assert abs(gl - ev.grad_lam) <= 1e-5 * max(1.0, abs(ev.grad_lam))
+    idx = rng.choice(mu.size, 40, replace=False)
+    mu = mu.copy()
+    mu[idx] = np.maximum(mu[idx], 1.0)  # interior points for a two-sided difference
+    ev = D.dual_value(K, lam, mu)
+    for i in idx:
+        e = np.zeros_like(mu)
+        e[i] = h
+        fd = (D.dual_value(K, lam, mu + e).g - D.dual_value(K, lam, mu - e).g) / (2 * h)
+        assert abs(fd - ev.grad_mu[i]) <= 1e-4 * max(1.0, abs(ev.grad_mu[i]))
+
+
+def test_supergradient_lp_where_smooth():
+    p = synth.make_problem("tiny30", 1)
+    K = D.canonical(p)
+    rng = np.random.default_rng(5)
+    lam, mu = _rand_multipliers(rng, K)
+    mu = mu + 1.0
+    ev = D.dual_value(K, lam, mu)
+    # |C| <= 1 entrywise, so a step h moves every reduced cost by at most h
+    # per coordinate: no generator switches when min |a| > h
+    h = 1e-4
+    assert np.min(np.abs(ev.a)) > 1e-3
+    gl = (D.dual_value(K, lam + h, mu).g - D.dual_value(K, lam - h, mu).g) / (2 * h)
+    assert abs(gl - ev.grad_lam) <= 1e-5 * max(1.0, abs(ev.grad_lam))
+    for i in range(mu.size):
+        e = np.zeros_like(mu)
+        e[i] = h
+        fd = (D.dual_value(K, lam, mu + e).g - D.dual_value(K, lam, mu - e).g) / (2 * h)
+        assert abs(fd - ev.grad_mu[i]) <= 1e-4 * max(1.0, abs(ev.grad_mu[i]))
+
+
+def test_concavity():
+    net, p = synth.make_network("geo300", 7)
+    K = D.canonical(p)
+    rng = np.random.default_rng(6)
+    for _ in range(10):
+        l1, m1 = _rand_multipliers(rng, K)
+        l2, m2 = _rand_multipliers(rng, K)
+        g1 = D.dual_value(K, l1, m1).g
+        g2 = D.dual_value(K, l2, m2).g
+        gm = D.dual_value(K, 0.5 * (l1 + l2), 0.5 * (m1 + m2)).g
+        assert gm >= 0.5 * (g1 + g2) - 1e-9 * abs(gm)
+
+
+@pytest.mark.parametrize("name,seed", [("tiny30", 1), ("geo300", 7)])
+def test_weak_duality(name, seed):
+    # Remarks 1-2: any mu >= 0, lambda gives a value <= every feasible cost
+    net, p = synth.make_network(name, seed)
+    K = D.canonical(p)
+    opt = ref.opt_ptdf(p, want_duals=False)["opt"]
+    rng = np.random.default_rng(seed)
+    for _ in range(30):
+        lam, mu = _rand_multipliers(rng, K, scale=float(rng.choice([0.1, 1, 10, 100])))
+        assert D.dual_value(K, lam, mu).g <= opt + 1e-9 * abs(opt)
+    # random feasible points: HiGHS optima of random objectives over the same set
+    import scipy.optimize as so
+    for _ in range(5):
+        cr = rng.normal(size=K.c.size)
+        r = so.linprog(cr, A_ub=K.C, b_ub=K.d, A_eq=-K.A, b_eq=-K.b,
+                       bounds=list(zip(K.lo, K.hi)), method="highs")
+        cost = float(K.c @ r.x + r.x @ (K.M * r.x))
+        lam, mu = _rand_multipliers(rng, K)
+        assert D.dual_value(K, lam, mu).g <= cost + 1e-9 * abs(cost)
