@@ -1,0 +1,143 @@
+"""Benchmark of the projected dual ascent (instance-iterations/s and time to a
+bound within 0.1 % of the FP64 optimum) on one MI355X.
+
+Workload: the 2000-bus single instance (3200 lines, 540 generators on 478
+distinct buses, linear costs), FP32 PTDF products with FP64 state, gradient
+with momentum.  A step is one ascent iteration (reduced costs, inner
+minimiser, residuals, step + projection).  Inputs are resident in HBM before
+the timed region; the iteration loop is replayed as captured HIP graphs.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "instance-iterations/s of dual ascent; time to bound within 0.1% of FP64 optimum"
+HBM_PEAK_GBS = 8000.0
+
+
+def panel_bytes(n_line, n_cols, n_gen):
+    """Algorithmic HBM bytes of one launch of each pass (FP32 panel read once,
+    every vector read or written once)."""
+    panel = 4.0 * n_line * n_cols
+    col = panel + 4 * n_line + 4 * n_cols + n_gen * (4 * 8 + 4) + 4 * (n_cols + 1)
+    # line pass: x, f_d, f_max, mu+-, velocity+- read; mu+-, velocity+-, v written
+    line = panel + 4 * n_cols + n_line * (6 * 8 + 4 * 8 + 4)
+    return col, line
+
+
+def cpu_baseline(p, alpha, rho, budget_s=15.0):
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import dual as D
+    K = D.canonical(p)
+    t = time.perf_counter()
+    D.ascent(K, 20, alpha=alpha, rho=rho)
+    per = (time.perf_counter() - t) / 20
+    n = int(max(50, min(20000, budget_s / per)))
+    t = time.perf_counter()
+    D.ascent(K, n, alpha=alpha, rho=rho)
+    dt = time.perf_counter() - t
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return dict(value=n / dt, unit="instance-iterations/s", cores=int(threads),
+                kind="oracle",
+                sample=f"{n} FP64 GDM iterations of the same 2000-bus instance "
+                       f"(numpy, {threads} BLAS threads), {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="bus2000")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the single-instance path does not shard "
+              "across GPUs (see the sharding note in the design document).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2406_13191_amd import _abi, synth
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    net, p = synth.make_network(args.workload, {"bus2000": 2000, "bus4600": 4600,
+                                                "bus10000": 10000}[args.workload])
+    r = synth.STEP_RULES[args.workload]
+    n_cols = len(np.unique(p.gen_bus))
+    kw = dict(rule="gdm", alpha=r["alpha"], rho=r["rho"], precision="fp32", panel="genbus",
+              graph_iters=100)
+    s = _abi.DualSolver(p, stream=stream.cuda_stream, **kw)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    value = args.steps / (ms / 1e3)
+    print(f"[bench] {args.steps} iterations in {ms:.2f} ms (wall {wall*1e3:.2f} ms)",
+          file=sys.stderr, flush=True)
+    # per-kernel durations (HIP events around each launch) for the roofline
+    ms_col, ms_line = s.time_phases(200)
+    s.close()
+    b_col, b_line = panel_bytes(p.n_line, n_cols, p.n_gen)
+    if ms_line >= ms_col:
+        kname, kms, kbytes = "linepass (F = P x - f_d, mu step)", ms_line, b_line
+    else:
+        kname, kms, kbytes = "colpass (w = P^T v, inner minimiser)", ms_col, b_col
+    achieved = kbytes / (kms * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=kname,
+                    kernel_ms=round(kms, 5), bytes_per_launch=int(kbytes),
+                    other_kernel_ms=round(min(ms_col, ms_line), 5))
+
+    # time to a bound within 0.1 % of the FP64 optimum (HiGHS reference)
+    ttb = None
+    cpu = None
+    if not args.no_cpu:
+        from oracle import ref
+        opt = ref.opt_btheta(net, p)["opt"]
+        with _abi.DualSolver(p, stream=stream.cuda_stream, **kw) as s2:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = s2.solve(opt=opt, gap_tol=1e-3, max_iters=args.steps, check_every=100)
+            dt = time.perf_counter() - t0
+        ttb = dict(reached=res["status"] == 1, iterations=int(res["iter_of_bound"]),
+                   seconds=round(dt, 5), gap=res["gap"], check_every=100,
+                   device_seconds=round(res["iter_of_bound"] * ms / args.steps / 1e3, 6))
+        cpu = cpu_baseline(p, r["alpha"], r["rho"])
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "instance-iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload} single instance: {p.n_bus} buses, "
+                               f"{p.n_line} lines, {p.n_gen} generators on {n_cols} buses, "
+                               f"{'quadratic' if p.is_qp else 'linear'} costs; FP32 PTDF "
+                               f"products, FP64 multipliers and bound; gradient with "
+                               f"momentum alpha={r['alpha']}, rho={r['rho']}",
+                   "iterations": args.steps, "time_to_bound": ttb},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

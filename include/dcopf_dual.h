@@ -1,0 +1,197 @@
+/*
+ * dcopf_dual.h - C ABI of the MI355X projected dual-ascent DCOPF library.
+ *
+ * The method (arXiv 2406.13191, "GPU-Accelerated DCOPF using Gradient-Based
+ * Optimization"): DC optimal power flow (Section 2, eq. DCOPF)
+ *
+ *     min_p  sum_g c_g p_g + q_g p_g^2
+ *     s.t.   1^T p = 1^T d                              (power balance)
+ *            -f_max <= H (C_g p - d) <= f_max           (PTDF line limits)
+ *            p_min <= p <= p_max                        (generator box)
+ *
+ * is solved through its Lagrange dual (Section 3, eqs. lagrangian, dual
+ * function, dual).  For multipliers lambda (balance, free) and mu+, mu- >= 0
+ * (the two sides of every line limit), the inner minimisation over the box
+ * has a closed form (Section 3.1 dual norm, eq. LP dual; Section 3.2, eq.
+ * QP_finalgamma maximised over s): every generator sits at p_min / p_max by
+ * the sign of its reduced cost r_g = c_g - lambda + (H^T (mu+ - mu-))[bus g]
+ * (linear cost; the midpoint when r_g == 0) or at clip(-r_g / (2 q_g))
+ * (quadratic cost).  The dual value
+ *
+ *     G = sum_g (r_g p*_g + q_g p*_g^2) + lambda 1^T d
+ *         - (mu+ - mu-)^T H d - (mu+ + mu-)^T f_max
+ *
+ * is a valid lower bound on the optimal cost for any lambda and mu >= 0
+ * (Remarks 1 and 2).  Its supergradient is the constraint residual at p*:
+ * d/dlambda = 1^T d - 1^T p*, d/dmu+- = +-H (C_g p* - d) - f_max.  The ascent
+ * (Section 3.3, Algorithm 1 and its Adam / AdaGrad variants) steps along it
+ * and projects mu onto mu >= 0.
+ *
+ * Sign convention: lambda here is the marginal price (the canonical form's
+ * A = -1^T), so the reduced cost is c - lambda 1 + C_g^T H^T (mu+ - mu-).
+ *
+ * All functions return a dcopf_status; on failure dcopf_last_error() gives a
+ * message (thread-local, valid until the next call on that thread).  No call
+ * throws across the ABI.  Handles are not thread-safe: use one handle from
+ * one thread at a time.  Device work is enqueued on the HIP stream given at
+ * create (NULL = the null stream); calls documented as "synchronises" wait
+ * for that stream.
+ */
+#ifndef DCOPF_DUAL_H
+#define DCOPF_DUAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DCOPF_OK = 0,
+  DCOPF_E_INVALID = -1,     /* bad argument; nothing was changed */
+  DCOPF_E_NOMEM = -2,       /* device or host allocation failed */
+  DCOPF_E_HIP = -3,         /* a HIP runtime call failed */
+  DCOPF_E_NONFINITE = -4,   /* a NaN/Inf appeared in the iterate or bound */
+  DCOPF_E_INFEASIBLE = -5,  /* the instance is certified infeasible */
+  DCOPF_E_STATE = -7        /* state buffer of the wrong length */
+} dcopf_status;
+
+/* One DCOPF instance in the paper's statement (Section 2, eq. DCOPF).
+ * All pointers are HOST memory; they are read during dcopf_dual_create and
+ * may be freed by the caller when it returns.                              */
+typedef struct {
+  int32_t n_bus;            /* buses, >= 2                                   */
+  int32_t n_line;           /* lines, >= 1                                   */
+  int32_t n_gen;            /* generators, >= 1                              */
+  int32_t slack;            /* slack bus index; column `slack` of H is zero  */
+  const double *H;          /* [n_line * n_bus] row-major PTDF H_a (Section 2:
+                               H = Omega E (E^T Omega E)^{-1} with a zero
+                               slack column)                                 */
+  const int32_t *gen_bus;   /* [n_gen] bus of each generator (C_g as a map)  */
+  const double *c;          /* [n_gen] linear cost, $/MWh                    */
+  const double *q;          /* [n_gen] quadratic cost $/MW^2h (>= 0); NULL =
+                               all zero (the LP of Section 3.1)              */
+  const double *p_min;      /* [n_gen] MW                                    */
+  const double *p_max;      /* [n_gen] MW, p_min <= p_max                    */
+  const double *d;          /* [n_bus] load, MW                              */
+  const double *f_max;      /* [n_line] symmetric line limit, MW, > 0        */
+} dcopf_problem;
+
+enum { DCOPF_RULE_GDM = 0, DCOPF_RULE_ADAM = 1, DCOPF_RULE_ADAGRAD = 2 };
+enum { DCOPF_PREC_FP64 = 0, DCOPF_PREC_FP32 = 1 };
+enum { DCOPF_PANEL_GENBUS = 0, DCOPF_PANEL_ALLBUS = 1 };
+
+/* Ascent options (Section 3.3).                                            */
+typedef struct {
+  int32_t rule;        /* DCOPF_RULE_*: gradient with momentum (Algorithm 1),
+                          Adam, AdaGrad                                     */
+  int32_t literal;     /* GDM only: 1 also applies Algorithm 1's separately
+                          listed gradient update theta += alpha grad after
+                          the velocity update; 0 = heavy-ball (velocity only) */
+  double alpha;        /* step size, > 0                                     */
+  double rho;          /* GDM momentum in [0, 1)                             */
+  double beta1, beta2; /* Adam moment decays in [0, 1)                       */
+  double eps;          /* Adam / AdaGrad denominator guard, > 0              */
+  double decay;        /* step decay: alpha_k = alpha / (1 + decay k), >= 0  */
+  int32_t precision;   /* DCOPF_PREC_FP64: every product in FP64.
+                          DCOPF_PREC_FP32: the two PTDF products per iteration
+                          in FP32 (FP32 accumulation); reduced costs, inner
+                          minimiser, residual subtraction, updates, lambda and
+                          the monitor gamma in FP64; dcopf_dual_bound always
+                          evaluates in FP64.                                */
+  int32_t panel;       /* DCOPF_PANEL_GENBUS: the products use only the H
+                          columns of buses that host a generator (the others
+                          multiply zero injections).  DCOPF_PANEL_ALLBUS: the
+                          full H in both products (literal bus-vector form).
+                          Both give the same dual values.                   */
+  int32_t graph_iters; /* iterations per captured HIP graph; 0 = direct
+                          launches                                          */
+} dcopf_opts;
+
+typedef struct dcopf_dual_s *dcopf_dual_t;
+
+/* Build the solver: validates the instance and options, uploads H, gathers
+ * the panel (FP32 and/or FP64, both orientations), forms H d in FP64, and
+ * sets the cold start lambda = mu = 0 and zero optimiser state (Algorithm 1
+ * initialisation).  `hip_stream` is a hipStream_t (NULL = null stream).
+ * Errors: DCOPF_E_INVALID (dimensions, indices, non-finite values, p_min >
+ * p_max, q < 0, f_max <= 0, nonzero slack column, bad options),
+ * DCOPF_E_INFEASIBLE (sum p_min > 1^T d or sum p_max < 1^T d),
+ * DCOPF_E_NOMEM, DCOPF_E_HIP.  On error *out is set to NULL. Synchronises. */
+dcopf_status dcopf_dual_create(const dcopf_problem *prob, const dcopf_opts *opts,
+                               void *hip_stream, dcopf_dual_t *out);
+
+/* Enqueue n_iters >= 0 ascent iterations (Algorithm 1 loop body: reduced
+ * costs, inner minimiser, residuals, step + projection; gamma_k of each
+ * iterate recorded).  Asynchronous.                                        */
+dcopf_status dcopf_dual_step(dcopf_dual_t h, int64_t n_iters);
+
+/* Exact FP64 dual value G at the current iterate (all products FP64); a
+ * valid lower bound on the optimal cost (Remarks 1 and 2).  The best value
+ * seen by this call is tracked (dcopf_dual_best).  Optional outputs (may be
+ * NULL): lambda (1), mu_plus / mu_minus ([n_line], host).  Synchronises.
+ * DCOPF_E_NONFINITE if the value or iterate is not finite.                  */
+dcopf_status dcopf_dual_bound(dcopf_dual_t h, double *value, double *lambda,
+                              double *mu_plus, double *mu_minus);
+
+/* Best exact bound recorded by dcopf_dual_bound / dcopf_dual_solve and the
+ * iteration at which it was evaluated (-inf / -1 if none yet).             */
+dcopf_status dcopf_dual_best(dcopf_dual_t h, double *value, int64_t *iteration);
+
+typedef struct {
+  double bound;          /* best exact FP64 lower bound                      */
+  double gamma_last;     /* monitor gamma of the last iterate                */
+  double gap;            /* (opt - bound) / |opt|, NaN when opt is NaN       */
+  int64_t iters;         /* iterations done by this handle in total          */
+  int64_t iter_of_bound; /* iteration at which `bound` was evaluated         */
+  int32_t status;        /* 1 gap reached, 2 |d gamma| < tol (Algorithm 1's
+                            stopping test), 3 max_iters, 0 otherwise          */
+} dcopf_result;
+
+/* Run the ascent until the exact bound is within gap_tol of `opt`
+ * (relative; ignored when opt is NaN), or |gamma_k - gamma_{k-1}| <
+ * dgamma_tol (ignored when <= 0), or max_iters more iterations; the exact
+ * bound is evaluated every `check_every` (>= 1) iterations and at the end.
+ * Returns DCOPF_E_INFEASIBLE when a bound exceeds the largest possible cost
+ * sum_g max_p (c_g p + q_g p^2) (the dual is then unbounded).  Synchronises. */
+dcopf_status dcopf_dual_solve(dcopf_dual_t h, double opt, double gap_tol,
+                              double dgamma_tol, int64_t max_iters,
+                              int64_t check_every, dcopf_result *out);
+
+/* Monitor values gamma_k (dual value at iterate k, from the products of the
+ * chosen precision) for iterations [first, first + count) of this handle;
+ * only the last 2^20 iterations are kept.  Synchronises.                   */
+dcopf_status dcopf_dual_gammas(dcopf_dual_t h, int64_t first, int64_t count,
+                               double *out);
+
+/* State (host doubles, length dcopf_dual_state_len): [iteration, lambda,
+ * lambda velocity / first moment, lambda second moment, 0, mu+ [n_line],
+ * mu- [n_line], velocity or first moment of mu+ and mu- [2 n_line], second
+ * moment of mu+ and mu- [2 n_line]].  set_state is a warm start or resume;
+ * mu must be >= 0 and finite (DCOPF_E_INVALID otherwise).  Synchronise.    */
+size_t dcopf_dual_state_len(dcopf_dual_t h);
+dcopf_status dcopf_dual_get_state(dcopf_dual_t h, double *buf, size_t len);
+dcopf_status dcopf_dual_set_state(dcopf_dual_t h, const double *buf, size_t len);
+
+/* Measurement: run n_iters >= 1 iterations with direct launches, recording a
+ * HIP event pair around every kernel on the handle's stream; ms_out[0] and
+ * ms_out[1] receive the average duration (ms) of the column pass (w = P^T v
+ * and the inner minimiser) and of the line pass (F = P x - f_d and the mu
+ * step).  The iterations are real ascent iterations.  Synchronises.        */
+dcopf_status dcopf_dual_time_phases(dcopf_dual_t h, int64_t n_iters, double *ms_out);
+
+/* Panel width (number of H columns the products use) and iterations done. */
+dcopf_status dcopf_dual_info(dcopf_dual_t h, int32_t *n_cols, int64_t *iters);
+
+/* Free all device and host memory of the handle.  NULL is a no-op.        */
+void dcopf_dual_destroy(dcopf_dual_t h);
+
+/* Message of the last failed call on this thread ("" if none).           */
+const char *dcopf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCOPF_DUAL_H */

@@ -1,0 +1,221 @@
+"""ctypes binding of libdcopf_dual.so (argument marshalling only).
+
+Every step of the ascent runs in the library's HIP kernels; this module only
+converts numpy arrays to the C structs of ``include/dcopf_dual.h`` and back.
+Importing it raises if the library has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdcopf_dual.so")
+
+DCOPF_OK = 0
+STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_HIP", -4: "E_NONFINITE",
+                -5: "E_INFEASIBLE", -7: "E_STATE"}
+RULES = {"gdm": 0, "adam": 1, "adagrad": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+PANELS = {"genbus": 0, "allbus": 1}
+
+
+class DcopfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Problem_C(C.Structure):
+    _fields_ = [("n_bus", C.c_int32), ("n_line", C.c_int32), ("n_gen", C.c_int32),
+                ("slack", C.c_int32), ("H", C.POINTER(C.c_double)),
+                ("gen_bus", C.POINTER(C.c_int32)), ("c", C.POINTER(C.c_double)),
+                ("q", C.POINTER(C.c_double)), ("p_min", C.POINTER(C.c_double)),
+                ("p_max", C.POINTER(C.c_double)), ("d", C.POINTER(C.c_double)),
+                ("f_max", C.POINTER(C.c_double))]
+
+
+class Opts_C(C.Structure):
+    _fields_ = [("rule", C.c_int32), ("literal", C.c_int32), ("alpha", C.c_double),
+                ("rho", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("decay", C.c_double), ("precision", C.c_int32),
+                ("panel", C.c_int32), ("graph_iters", C.c_int32)]
+
+
+class Result_C(C.Structure):
+    _fields_ = [("bound", C.c_double), ("gamma_last", C.c_double), ("gap", C.c_double),
+                ("iters", C.c_int64), ("iter_of_bound", C.c_int64), ("status", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -m paper_2406_13191_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    sig = {
+        "dcopf_dual_create": (C.c_int, [P(Problem_C), P(Opts_C), C.c_void_p, P(C.c_void_p)]),
+        "dcopf_dual_step": (C.c_int, [C.c_void_p, C.c_int64]),
+        "dcopf_dual_bound": (C.c_int, [C.c_void_p, P(C.c_double), P(C.c_double),
+                                       P(C.c_double), P(C.c_double)]),
+        "dcopf_dual_best": (C.c_int, [C.c_void_p, P(C.c_double), P(C.c_int64)]),
+        "dcopf_dual_solve": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double,
+                                       C.c_int64, C.c_int64, P(Result_C)]),
+        "dcopf_dual_gammas": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, P(C.c_double)]),
+        "dcopf_dual_state_len": (C.c_size_t, [C.c_void_p]),
+        "dcopf_dual_get_state": (C.c_int, [C.c_void_p, P(C.c_double), C.c_size_t]),
+        "dcopf_dual_set_state": (C.c_int, [C.c_void_p, P(C.c_double), C.c_size_t]),
+        "dcopf_dual_info": (C.c_int, [C.c_void_p, P(C.c_int32), P(C.c_int64)]),
+        "dcopf_dual_time_phases": (C.c_int, [C.c_void_p, C.c_int64, P(C.c_double)]),
+        "dcopf_dual_destroy": (None, [C.c_void_p]),
+        "dcopf_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return lib.dcopf_last_error().decode()
+
+
+def check(status: int):
+    if status != DCOPF_OK:
+        raise DcopfError(status, last_error())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def make_opts(rule="gdm", alpha=1e-3, rho=0.9, beta1=0.9, beta2=0.999, eps=1e-8,
+              decay=0.0, literal=False, precision="fp32", panel="genbus",
+              graph_iters=0) -> Opts_C:
+    return Opts_C(RULES[rule], int(bool(literal)), float(alpha), float(rho), float(beta1),
+                  float(beta2), float(eps), float(decay), PRECISIONS[precision],
+                  PANELS[panel], int(graph_iters))
+
+
+class DualSolver:
+    """One DCOPF instance on the GPU (``dcopf_dual_*``).
+
+    ``prob`` has the fields of the paper's statement: H [n_line, n_bus],
+    gen_bus, c, q, p_min, p_max, d, f_max, slack.  ``stream`` is a
+    hipStream_t handle as an int (e.g. torch.cuda.current_stream().cuda_stream)
+    or None for the null stream.
+    """
+
+    def __init__(self, prob, stream=None, **opts):
+        self._arrays = dict(
+            H=_f64(prob.H), gen_bus=np.ascontiguousarray(np.asarray(prob.gen_bus, np.int32)),
+            c=_f64(prob.c), q=None if prob.q is None else _f64(prob.q),
+            p_min=_f64(prob.p_min), p_max=_f64(prob.p_max), d=_f64(prob.d),
+            f_max=_f64(prob.f_max))
+        a = self._arrays
+        n_line, n_bus = a["H"].shape if a["H"].ndim == 2 else (len(a["f_max"]), len(a["d"]))
+        self.n_line, self.n_bus, self.n_gen = int(n_line), int(n_bus), int(a["c"].size)
+        pc = Problem_C(self.n_bus, self.n_line, self.n_gen, int(prob.slack), _dptr(a["H"]),
+                       a["gen_bus"].ctypes.data_as(C.POINTER(C.c_int32)), _dptr(a["c"]),
+                       _dptr(a["q"]) if a["q"] is not None else None, _dptr(a["p_min"]),
+                       _dptr(a["p_max"]), _dptr(a["d"]), _dptr(a["f_max"]))
+        self.opts = make_opts(**opts)
+        h = C.c_void_p()
+        check(lib.dcopf_dual_create(C.byref(pc), C.byref(self.opts),
+                                    C.c_void_p(stream or 0), C.byref(h)))
+        self._h = h
+        self._arrays = None  # inputs were copied by create
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.dcopf_dual_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- calls -------------------------------------------------------------
+    def step(self, n: int):
+        check(lib.dcopf_dual_step(self._h, int(n)))
+
+    def bound(self, want_multipliers=False):
+        v = C.c_double()
+        if want_multipliers:
+            lam = C.c_double()
+            mp = np.empty(self.n_line)
+            mm = np.empty(self.n_line)
+            check(lib.dcopf_dual_bound(self._h, C.byref(v), C.byref(lam), _dptr(mp), _dptr(mm)))
+            return v.value, lam.value, mp, mm
+        check(lib.dcopf_dual_bound(self._h, C.byref(v), None, None, None))
+        return v.value
+
+    def best(self):
+        v = C.c_double()
+        k = C.c_int64()
+        check(lib.dcopf_dual_best(self._h, C.byref(v), C.byref(k)))
+        return v.value, k.value
+
+    def solve(self, opt=math.nan, gap_tol=1e-3, dgamma_tol=0.0, max_iters=20000,
+              check_every=100):
+        r = Result_C()
+        check(lib.dcopf_dual_solve(self._h, float(opt), float(gap_tol), float(dgamma_tol),
+                                   int(max_iters), int(check_every), C.byref(r)))
+        return dict(bound=r.bound, gamma_last=r.gamma_last, gap=r.gap, iters=r.iters,
+                    iter_of_bound=r.iter_of_bound, status=r.status)
+
+    def gammas(self, first: int, count: int) -> np.ndarray:
+        out = np.empty(int(count))
+        check(lib.dcopf_dual_gammas(self._h, int(first), int(count), _dptr(out)))
+        return out
+
+    def state_len(self) -> int:
+        return int(lib.dcopf_dual_state_len(self._h))
+
+    def get_state(self) -> np.ndarray:
+        buf = np.empty(self.state_len())
+        check(lib.dcopf_dual_get_state(self._h, _dptr(buf), buf.size))
+        return buf
+
+    def set_state(self, buf):
+        buf = _f64(buf)
+        check(lib.dcopf_dual_set_state(self._h, _dptr(buf), buf.size))
+
+    def time_phases(self, n: int):
+        """Average (column pass, line pass) kernel durations in ms over n
+        real iterations, from HIP events around each launch."""
+        ms = np.zeros(2)
+        check(lib.dcopf_dual_time_phases(self._h, int(n), _dptr(ms)))
+        return float(ms[0]), float(ms[1])
+
+    def info(self):
+        nc = C.c_int32()
+        it = C.c_int64()
+        check(lib.dcopf_dual_info(self._h, C.byref(nc), C.byref(it)))
+        return dict(n_cols=nc.value, iters=it.value)
+
+    # -- state helpers -------------------------------------------------------
+    def split_state(self, buf):
+        nl = self.n_line
+        return dict(k=int(buf[0]), lam=buf[1], v_lam=buf[2], s_lam=buf[3],
+                    mu_p=buf[5:5 + nl], mu_m=buf[5 + nl:5 + 2 * nl],
+                    v_p=buf[5 + 2 * nl:5 + 3 * nl], v_m=buf[5 + 3 * nl:5 + 4 * nl],
+                    s_p=buf[5 + 4 * nl:5 + 5 * nl], s_m=buf[5 + 5 * nl:5 + 6 * nl])
