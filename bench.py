@@ -51,6 +51,65 @@ def cpu_baseline(p, alpha, rho, budget_s=15.0):
                        f"(numpy, {threads} BLAS threads), {dt:.1f} s")
 
 
+MIXED = [("bus4600", 4600, 512, 46_000_000), ("bus2000", 2000, 128, 20_000_000),
+         ("bus10000", 10000, 32, 100_000_000)]
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def bench_mixed(args, stream):
+    """The mixed batch: 512 scenarios of the 4600-bus network, 128 of the
+    2000-bus and 32 of the 10000-bus (QP) network in one batched launch per
+    phase, split-BF16 products, autotuned tiles, HIP-graph replay."""
+    import numpy as np
+    import torch
+
+    from paper_2406_13191_amd import _abi, synth
+    nets, shapes = [], []
+    for name, seed, B, seed0 in MIXED:
+        _, base = synth.make_network(name, seed)
+        Dm, Cc, Q = synth.make_scenarios(base, seed0, B, 0.1, 0.1)
+        r = synth.STEP_RULES[name]
+        nets.append(_abi.BatchNetwork(base, Dm, Cc, Q if base.is_qp else None,
+                                      alpha=r["alpha"], rho=r["rho"]))
+        shapes.append((name, base.n_line, len(np.unique(base.gen_bus)), B))
+    b = _abi.BatchSolver(nets, stream=stream.cuda_stream, autotune=True, graph_iters=20,
+                         gamma_cap=64)
+    n_total = b.n_total
+    b.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ms_w, ms_u, ms_f = b.time_phases(20)
+    tiles = [b.info(k) for k in range(len(nets))]
+    b.close()
+    useful = sum(2.0 * nl * nc * B for _, nl, nc, B in shapes)  # one product, FP32-equivalent
+    issued = 3 * useful
+    # HBM bytes of one iteration: both panels (BF16 hi+lo), the FP32 state
+    # (mu, velocity read+write, f_d read) and V hi/lo writes per (line, instance)
+    state = sum(B * nl * (4 * 4 + 4 * 4 + 4 + 4) for _, nl, nc, B in shapes)
+    panels = sum(2 * 4 * nl * nc for _, nl, nc, B in shapes)
+    dom = ("W product (W^T = V^T P, split-BF16 MFMA)", ms_w) if ms_w >= ms_f else \
+          ("F product (F^T = X^T P^T, split-BF16 MFMA, mu step)", ms_f)
+    achieved = issued / (dom[1] * 1e-3) / 1e12
+    return dict(
+        value=n_total * args.steps / (ms / 1e3), ms=ms, n_total=n_total,
+        roofline=dict(bound="mfma", achieved=round(achieved, 2), peak=BF16_PEAK_TFLOPS,
+                      unit="TFLOP/s", frac=round(achieved / BF16_PEAK_TFLOPS, 4),
+                      traffic=None, kernel=dom[0], kernel_ms=round(dom[1], 5),
+                      flops_per_launch=issued, useful_fp32_equiv_flops=useful,
+                      phase_ms=dict(w=round(ms_w, 5), units=round(ms_u, 5),
+                                    f=round(ms_f, 5)),
+                      hbm_bytes_per_iteration=int(state + panels),
+                      hbm_gbs_per_iteration=round((state + panels) / (ms / args.steps * 1e-3)
+                                                  / 1e9, 1)),
+        shapes=shapes, tiles=tiles)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +130,21 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.workload == "mixed":
+        r = bench_mixed(args, stream)
+        out = {
+            "metric": METRIC, "value": round(r["value"], 1), "unit": "instance-iterations/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": r["ms"] / args.steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
+            "config": {"workload": "mixed batch: " + ", ".join(
+                f"{B} x {n} ({nl} lines, {nc} generator buses)" for n, nl, nc, B in r["shapes"])
+                + "; split-BF16 MFMA products, FP32 line state, FP64 lambda and bound; GDM",
+                "instances": r["n_total"], "tiles": r["tiles"]},
+            "roofline": r["roofline"], "cpu_baseline": None,
+        }
+        print(json.dumps(out), flush=True)
+        return
     net, p = synth.make_network(args.workload, {"bus2000": 2000, "bus4600": 4600,
                                                 "bus10000": 10000}[args.workload])
     r = synth.STEP_RULES[args.workload]

@@ -1,0 +1,125 @@
+/*
+ * dcopf_batch.h - batched projected dual ascent: many DCOPF instances (load
+ * and cost scenarios) on one or more networks, advanced together.
+ *
+ * Every instance runs exactly the iteration of dcopf_dual.h (Section 3.3,
+ * Algorithm 1 and its Adam / AdaGrad variants on the Lagrange dual of
+ * Section 3; closed-form inner minimiser of Sections 3.1 / 3.2).  The paper
+ * leaves solving many instances in parallel to future work (Sections 1 and
+ * 5); here the instances of one network share its PTDF, so the two products
+ * per iteration become dense GEMMs:
+ *
+ *     W^T = V^T P   (V = mu+ - mu-, [instances x lines] . [lines x columns])
+ *     F^T = X^T P^T (X = injections at the generator buses)
+ *
+ * run on the matrix cores as split-BF16 products: each FP32 factor a is
+ * written a_hi + a_lo with a_hi = bf16(a), a_lo = bf16(a - a_hi); the product
+ * a b is formed as a_hi b_hi + a_hi b_lo + a_lo b_hi (optionally + a_lo b_lo)
+ * with FP32 accumulation.  Line multipliers and velocities are FP32; lambda,
+ * the reduced costs, the inner minimiser, the monitor gamma and the exact
+ * bound are FP64.  The exact bound (dcopf_batch_bound) evaluates the dual
+ * function with FP64 products (FP64 matrix cores).
+ *
+ * Errors, threading and stream semantics are those of dcopf_dual.h; the
+ * message of a failed call is in dcopf_last_error().
+ */
+#ifndef DCOPF_BATCH_H
+#define DCOPF_BATCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "dcopf_dual.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One network and the instances on it.  HOST pointers, copied at create.  */
+typedef struct {
+  int32_t n_bus, n_line, n_gen, slack;   /* as dcopf_problem                 */
+  const double *H;        /* [n_line * n_bus] row-major PTDF, zero slack col */
+  const int32_t *gen_bus; /* [n_gen]                                         */
+  const double *p_min;    /* [n_gen] shared by the instances                 */
+  const double *p_max;    /* [n_gen]                                         */
+  const double *f_max;    /* [n_line] symmetric limits, > 0                  */
+  int32_t n_inst;         /* instances on this network, >= 1                 */
+  const double *d;        /* [n_inst * n_bus] load of each instance          */
+  const double *c;        /* [n_inst * n_gen] linear cost of each instance   */
+  const double *q;        /* [n_inst * n_gen] quadratic cost (>= 0) or NULL  */
+  double alpha, rho;      /* step size (> 0) and GDM momentum for this
+                             network's instances                             */
+} dcopf_batch_network;
+
+typedef struct {
+  int32_t rule;           /* DCOPF_RULE_GDM / ADAM / ADAGRAD                 */
+  int32_t literal;        /* GDM reading, as dcopf_opts.literal              */
+  double beta1, beta2, eps, decay;   /* as dcopf_opts                        */
+  int32_t lolo;           /* 1: add the a_lo b_lo term (4 products)          */
+  int32_t graph_iters;    /* iterations per captured HIP graph (0: direct)   */
+  int32_t autotune;       /* 1: time the tile shapes at create and keep the
+                             fastest per network; 0: built-in defaults       */
+  int32_t gamma_cap;      /* monitor ring: last gamma_cap iterations are kept
+                             (power of two, 1..65536)                        */
+} dcopf_batch_opts;
+
+typedef struct dcopf_batch_s *dcopf_batch_t;
+
+/* Validates every network and instance like dcopf_dual_create (including
+ * the per-instance balance check: DCOPF_E_INFEASIBLE names the instance),
+ * uploads the PTDFs, builds the split-BF16 and FP64 panels, forms H d for
+ * every instance in FP64, and sets the cold start (lambda = mu = 0).
+ * Instance numbering is global: network 0's instances first.  Synchronises. */
+dcopf_status dcopf_batch_create(const dcopf_batch_network *nets, int32_t n_nets,
+                                const dcopf_batch_opts *opts, void *hip_stream,
+                                dcopf_batch_t *out);
+
+/* Enqueue n_iters >= 0 iterations of every instance.  Asynchronous.       */
+dcopf_status dcopf_batch_step(dcopf_batch_t b, int64_t n_iters);
+
+/* Exact FP64 dual value of every instance at its current iterate (valid
+ * lower bounds, Remarks 1 and 2) into values[n_total]; the best value per
+ * instance is tracked (dcopf_batch_best).  Synchronises.                    */
+dcopf_status dcopf_batch_bound(dcopf_batch_t b, double *values);
+
+/* Best exact bound per instance and the iteration it was evaluated at.     */
+dcopf_status dcopf_batch_best(dcopf_batch_t b, double *values, int64_t *iters);
+
+/* Iterate until every instance's best exact bound is within gap_tol of its
+ * opt[i] (relative), or max_iters; bounds are evaluated every check_every
+ * iterations.  first_hit[i] receives the iteration of the first bound within
+ * the gap (-1 if never); may be NULL.  Synchronises.                       */
+dcopf_status dcopf_batch_solve(dcopf_batch_t b, const double *opt, double gap_tol,
+                               int64_t max_iters, int64_t check_every, int64_t *first_hit);
+
+/* Monitor values gamma_k of iterations [first, first+count) for all
+ * instances: out[(k - first) * n_total + i].  Synchronises.                */
+dcopf_status dcopf_batch_gammas(dcopf_batch_t b, int64_t first, int64_t count, double *out);
+
+/* Multipliers of network `net` (host doubles): lambda[n_inst],
+ * mu_plus / mu_minus [n_inst * n_line].  get: any output may be NULL.
+ * set (warm start): mu >= 0 and finite; this network's optimiser state is
+ * reset to zero (other networks keep theirs) and the iteration counter of
+ * the whole batch restarts at 0.  Synchronise.                             */
+dcopf_status dcopf_batch_get_multipliers(dcopf_batch_t b, int32_t net, double *lambda,
+                                         double *mu_plus, double *mu_minus);
+dcopf_status dcopf_batch_set_multipliers(dcopf_batch_t b, int32_t net, const double *lambda,
+                                         const double *mu_plus, const double *mu_minus);
+
+/* Tile shapes in use for network `net`: cfg[0..3] = workgroup arrangement
+ * of the W product (waves along instances, along columns), its K split,
+ * and the arrangement code of the F product.                               */
+dcopf_status dcopf_batch_info(dcopf_batch_t b, int32_t net, int32_t *cfg, int64_t *iters);
+
+/* Measurement: run n_iters >= 1 iterations with an event pair around each
+ * launch; ms_out[0..2] = average ms of the W product, the unit pass (inner
+ * minimiser and lambda step) and the F product with the mu step.          */
+dcopf_status dcopf_batch_time_phases(dcopf_batch_t b, int64_t n_iters, double *ms_out);
+
+void dcopf_batch_destroy(dcopf_batch_t b);   /* NULL is a no-op              */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCOPF_BATCH_H */

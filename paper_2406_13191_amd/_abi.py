@@ -200,8 +200,9 @@ class DualSolver:
         check(lib.dcopf_dual_set_state(self._h, _dptr(buf), buf.size))
 
     def time_phases(self, n: int):
-        """Average (column pass, line pass) kernel durations in ms over n
-        real iterations, from HIP events around each launch."""
+        """Average (column pass, line pass) kernel durations in ms: each
+        pass launched n times back to back between one HIP event pair; the
+        iterate is restored afterwards."""
         ms = np.zeros(2)
         check(lib.dcopf_dual_time_phases(self._h, int(n), _dptr(ms)))
         return float(ms[0]), float(ms[1])
@@ -219,3 +220,163 @@ class DualSolver:
                     mu_p=buf[5:5 + nl], mu_m=buf[5 + nl:5 + 2 * nl],
                     v_p=buf[5 + 2 * nl:5 + 3 * nl], v_m=buf[5 + 3 * nl:5 + 4 * nl],
                     s_p=buf[5 + 4 * nl:5 + 5 * nl], s_m=buf[5 + 5 * nl:5 + 6 * nl])
+
+
+# ---------------------------------------------------------------------------
+# Batched instances (dcopf_batch.h)
+# ---------------------------------------------------------------------------
+class BatchNet_C(C.Structure):
+    _fields_ = [("n_bus", C.c_int32), ("n_line", C.c_int32), ("n_gen", C.c_int32),
+                ("slack", C.c_int32), ("H", C.POINTER(C.c_double)),
+                ("gen_bus", C.POINTER(C.c_int32)), ("p_min", C.POINTER(C.c_double)),
+                ("p_max", C.POINTER(C.c_double)), ("f_max", C.POINTER(C.c_double)),
+                ("n_inst", C.c_int32), ("d", C.POINTER(C.c_double)),
+                ("c", C.POINTER(C.c_double)), ("q", C.POINTER(C.c_double)),
+                ("alpha", C.c_double), ("rho", C.c_double)]
+
+
+class BatchOpts_C(C.Structure):
+    _fields_ = [("rule", C.c_int32), ("literal", C.c_int32), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double), ("decay", C.c_double),
+                ("lolo", C.c_int32), ("graph_iters", C.c_int32), ("autotune", C.c_int32),
+                ("gamma_cap", C.c_int32)]
+
+
+def _bind_batch():
+    P = C.POINTER
+    sig = {
+        "dcopf_batch_create": (C.c_int, [P(BatchNet_C), C.c_int32, P(BatchOpts_C), C.c_void_p,
+                                         P(C.c_void_p)]),
+        "dcopf_batch_step": (C.c_int, [C.c_void_p, C.c_int64]),
+        "dcopf_batch_bound": (C.c_int, [C.c_void_p, P(C.c_double)]),
+        "dcopf_batch_best": (C.c_int, [C.c_void_p, P(C.c_double), P(C.c_int64)]),
+        "dcopf_batch_solve": (C.c_int, [C.c_void_p, P(C.c_double), C.c_double, C.c_int64,
+                                        C.c_int64, P(C.c_int64)]),
+        "dcopf_batch_gammas": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, P(C.c_double)]),
+        "dcopf_batch_get_multipliers": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double),
+                                                  P(C.c_double), P(C.c_double)]),
+        "dcopf_batch_set_multipliers": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double),
+                                                  P(C.c_double), P(C.c_double)]),
+        "dcopf_batch_info": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int32), P(C.c_int64)]),
+        "dcopf_batch_time_phases": (C.c_int, [C.c_void_p, C.c_int64, P(C.c_double)]),
+        "dcopf_batch_destroy": (None, [C.c_void_p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+
+
+_bind_batch()
+
+
+class BatchNetwork:
+    """One network and its instances: ``base`` has the network fields
+    (H, gen_bus, p_min, p_max, f_max, slack); D [B, n_bus] loads,
+    Cc [B, n_gen] linear costs, Q [B, n_gen] quadratic costs (or None)."""
+
+    def __init__(self, base, D, Cc, Q=None, alpha=1e-4, rho=0.99):
+        self.base, self.alpha, self.rho = base, float(alpha), float(rho)
+        self.D = _f64(np.atleast_2d(D))
+        self.Cc = _f64(np.atleast_2d(Cc))
+        self.Q = None if Q is None else _f64(np.atleast_2d(Q))
+        self.B = self.D.shape[0]
+
+
+class BatchSolver:
+    """Many instances advanced together (``dcopf_batch_*``)."""
+
+    def __init__(self, networks, stream=None, rule="gdm", literal=False, beta1=0.9,
+                 beta2=0.999, eps=1e-8, decay=0.0, lolo=False, graph_iters=0, autotune=False,
+                 gamma_cap=4096):
+        self.networks = list(networks)
+        keep = []
+        arr = (BatchNet_C * len(self.networks))()
+        for k, n in enumerate(self.networks):
+            b = n.base
+            H = _f64(b.H)
+            gb = np.ascontiguousarray(np.asarray(b.gen_bus, np.int32))
+            pmin, pmax, fmax = _f64(b.p_min), _f64(b.p_max), _f64(b.f_max)
+            keep += [H, gb, pmin, pmax, fmax, n.D, n.Cc, n.Q]
+            arr[k] = BatchNet_C(H.shape[1], H.shape[0], gb.size, int(b.slack), _dptr(H),
+                                gb.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(pmin),
+                                _dptr(pmax), _dptr(fmax), n.B, _dptr(n.D), _dptr(n.Cc),
+                                _dptr(n.Q) if n.Q is not None else None, n.alpha, n.rho)
+        self.opts = BatchOpts_C(RULES[rule], int(bool(literal)), float(beta1), float(beta2),
+                                float(eps), float(decay), int(bool(lolo)), int(graph_iters),
+                                int(bool(autotune)), int(gamma_cap))
+        h = C.c_void_p()
+        check(lib.dcopf_batch_create(arr, len(self.networks), C.byref(self.opts),
+                                     C.c_void_p(stream or 0), C.byref(h)))
+        self._h = h
+        self.sizes = [n.B for n in self.networks]
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(int)
+        self.n_total = int(self.offsets[-1])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.dcopf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def step(self, n: int):
+        check(lib.dcopf_batch_step(self._h, int(n)))
+
+    def bound(self) -> np.ndarray:
+        out = np.empty(self.n_total)
+        check(lib.dcopf_batch_bound(self._h, _dptr(out)))
+        return out
+
+    def best(self):
+        v = np.empty(self.n_total)
+        k = np.empty(self.n_total, np.int64)
+        check(lib.dcopf_batch_best(self._h, _dptr(v), k.ctypes.data_as(C.POINTER(C.c_int64))))
+        return v, k
+
+    def solve(self, opt, gap_tol=1e-3, max_iters=5000, check_every=100) -> np.ndarray:
+        opt = _f64(opt)
+        hit = np.empty(self.n_total, np.int64)
+        check(lib.dcopf_batch_solve(self._h, _dptr(opt), float(gap_tol), int(max_iters),
+                                    int(check_every), hit.ctypes.data_as(C.POINTER(C.c_int64))))
+        return hit
+
+    def gammas(self, first: int, count: int) -> np.ndarray:
+        out = np.empty((int(count), self.n_total))
+        check(lib.dcopf_batch_gammas(self._h, int(first), int(count), _dptr(out)))
+        return out
+
+    def get_multipliers(self, net: int):
+        n = self.networks[net]
+        nl = np.asarray(n.base.f_max).size
+        lam = np.empty(n.B)
+        mp = np.empty((n.B, nl))
+        mm = np.empty((n.B, nl))
+        check(lib.dcopf_batch_get_multipliers(self._h, int(net), _dptr(lam), _dptr(mp),
+                                              _dptr(mm)))
+        return lam, mp, mm
+
+    def set_multipliers(self, net: int, lam, mu_p, mu_m):
+        lam, mu_p, mu_m = _f64(lam), _f64(mu_p), _f64(mu_m)
+        check(lib.dcopf_batch_set_multipliers(self._h, int(net), _dptr(lam), _dptr(mu_p),
+                                              _dptr(mu_m)))
+
+    def info(self, net: int):
+        cfg = np.zeros(4, np.int32)
+        it = C.c_int64()
+        check(lib.dcopf_batch_info(self._h, int(net), cfg.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   C.byref(it)))
+        return dict(w_arrangement=(int(cfg[0]), int(cfg[1])), w_split=int(cfg[2]),
+                    f_arrangement=(int(cfg[3]) // 10, int(cfg[3]) % 10), iters=it.value)
+
+    def time_phases(self, n: int):
+        ms = np.zeros(3)
+        check(lib.dcopf_batch_time_phases(self._h, int(n), _dptr(ms)))
+        return tuple(float(v) for v in ms)

@@ -1,0 +1,1199 @@
+// Batched projected dual ascent (many DCOPF instances) on CDNA4 matrix cores.
+//
+// Instances of one network share its generator-bus panel P (lines x columns)
+// and differ in loads d_i (hence f_d,i = H d_i) and costs c_i, q_i.  With the
+// instances as the M dimension, one iteration (Section 3.3, Algorithm 1 and
+// its variants, run for every instance) is three launches, each covering
+// every network through a tile table:
+//
+//   W product   W^T = V^T P   (M = instances, N = panel columns, K = lines)
+//               split-BF16 v_mfma_f32_32x32x16_bf16, FP32 accumulation,
+//               optional split over K for long-K / few-instance networks;
+//   unit pass   one workgroup per instance: w = sum of the K splits, reduced
+//               costs r = c - lambda + w (FP64), the closed-form inner
+//               minimiser (Sections 3.1 / 3.2), the column injections X
+//               (written as BF16 hi/lo), sum p* and sum phi, and the lambda
+//               step with the balance residual (FP64).  It also finishes the
+//               previous iteration's monitor value gamma;
+//   F product   F^T = X^T P^T (M = instances, N = lines, K = columns), whose
+//               epilogue forms F - f_d, the residuals +-F - f_max, the mu
+//               step and projection (FP32 state), the next V (BF16 hi/lo) and
+//               the line terms of gamma.
+//
+// Every operand is read with K contiguous (16-byte loads per lane) and every
+// state array is written coalesced along the N index of the output tile.
+// The exact bound uses FP64 products on v_mfma_f64_16x16x4f64.
+#include "common.h"
+#include "../../include/dcopf_batch.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+namespace dcopf {
+namespace {
+
+struct BNet {
+  int n_l, n_c, n_g, B, Bp, ldl, ldc, ncp, nlp, S, kchunk, inst0, ntl;
+  int wm_w, wn_w, wm_f, wn_f;
+  double alpha, rho;
+  const __bf16 *PT_hi, *PT_lo, *P_hi, *P_lo;
+  const double *P64T;
+  __bf16 *V_hi, *V_lo, *X_hi, *X_lo;
+  float *Wws;                                   // [S][Bp][ncp]
+  float *mu_p, *mu_m, *v_p, *v_m, *s_p, *s_m;   // [B][ldl]
+  const float *fd32;                            // [B][ldl]
+  const float *flim32;                          // [n_l]
+  const double *flim64, *fd64;                  // [n_l], [B][n_l]
+  const double *c, *q;                          // [B][n_g]
+  const double *pmin, *pmax;                    // [n_g]
+  const int *seg, *gperm;
+  double *lam, *vlam, *slam, *D, *genpart;      // [B]
+  double *linepart;                             // [ntl][Bp]
+  double *V64, *W64;                            // [Bp][ldl], [Bp][ncp]
+  double *bound;                                // [B]
+};
+
+struct BIter {
+  long long k;  // iteration index of this slot
+  int pending;  // gamma of iteration k - 1 not yet finished
+  int pad;
+};
+
+struct BScal {
+  BIter it[2];
+};
+
+struct BParams {
+  int rule, literal;
+  double beta1, beta2, eps, decay;
+};
+
+__device__ __forceinline__ double inner_min_b(double r, double q, double lo, double hi) {
+  if (q > 0.0) return fmin(fmax(-r / (2.0 * q), lo), hi);
+  if (r > 0.0) return lo;
+  if (r < 0.0) return hi;
+  return 0.5 * (lo + hi);
+}
+
+__device__ __forceinline__ void split_bf16(float v, __bf16 *hi, __bf16 *lo) {
+  const __bf16 h = (__bf16)v;
+  *hi = h;
+  *lo = (__bf16)(v - (float)h);
+}
+
+// Output element of v_mfma_f32_32x32x16: register j of lane l holds row
+// 8 (j / 4) + 4 (l / 32) + j % 4 and column l % 32.
+__device__ __forceinline__ int mfma32_row(int j, int lane) {
+  return 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+}
+
+// acc += (A_hi + A_lo)(B_hi + B_lo) over k in [kb, ke) (a multiple of 64):
+// four 16-deep steps per trip, all fragments loaded before the products.
+template <bool LOLO>
+__device__ __forceinline__ void split_mma(const __bf16 *__restrict__ ah,
+                                          const __bf16 *__restrict__ al,
+                                          const __bf16 *__restrict__ bh,
+                                          const __bf16 *__restrict__ bl, int kb, int ke,
+                                          f32x16 &acc) {
+  for (int k = kb; k < ke; k += 64) {
+    bf16x8 a0[4], a1[4], b0[4], b1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a0[u] = *reinterpret_cast<const bf16x8 *>(ah + k + 16 * u);
+      a1[u] = *reinterpret_cast<const bf16x8 *>(al + k + 16 * u);
+      b0[u] = *reinterpret_cast<const bf16x8 *>(bh + k + 16 * u);
+      b1[u] = *reinterpret_cast<const bf16x8 *>(bl + k + 16 * u);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[u], b0[u], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[u], b1[u], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[u], b0[u], acc, 0, 0, 0);
+      if (LOLO) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[u], b1[u], acc, 0, 0, 0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// W product: Wws[s][i][j] = sum_{l in split s} V[i][l] P[l][j]
+// ---------------------------------------------------------------------------
+template <bool LOLO>
+__global__ __launch_bounds__(256) void wgemm_kernel(const BNet *__restrict__ nets,
+                                                    const int4 *__restrict__ tiles) {
+  const int4 t = tiles[blockIdx.x];
+  const BNet &N = nets[t.x];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int mt = t.y + wave / N.wn_w, nt = t.z + wave % N.wn_w;
+  if (mt * 32 >= N.Bp || nt * 32 >= N.ncp) return;  // whole wavefront
+  const int kb = t.w * N.kchunk, ke = min(N.ldl, kb + N.kchunk);
+  const int r = lane & 31, koff = (lane >> 5) * 8;
+  const size_t arow = (size_t)(mt * 32 + r) * N.ldl + koff;
+  const size_t brow = (size_t)(nt * 32 + r) * N.ldl + koff;
+  const __bf16 *ah = N.V_hi + arow, *al = N.V_lo + arow;
+  const __bf16 *bh = N.PT_hi + brow, *bl = N.PT_lo + brow;
+  f32x16 acc;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+  split_mma<LOLO>(ah, al, bh, bl, kb, ke, acc);
+  float *out = N.Wws + ((size_t)t.w * N.Bp + mt * 32) * N.ncp + nt * 32 + r;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) out[(size_t)mfma32_row(j, lane) * N.ncp] = acc[j];
+}
+
+// gamma of the iteration before `it`: gen part minus the line terms.
+__device__ __forceinline__ void finish_gamma(const BNet &N, int i, long long k_prev,
+                                             double *gam_ring, long long gmask, int n_total,
+                                             double *red) {
+  double s = 0.0;
+  for (int t = threadIdx.x; t < N.ntl; t += blockDim.x) s += N.linepart[(size_t)t * N.Bp + i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0)
+    gam_ring[(size_t)(k_prev & gmask) * n_total + N.inst0 + i] = N.genpart[i] - s;
+}
+
+// ---------------------------------------------------------------------------
+// Unit pass: one workgroup per instance.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ nets,
+                                                    const int2 *__restrict__ inst_tab,
+                                                    BScal *sc, int par, BParams prm,
+                                                    double *__restrict__ gam_ring,
+                                                    long long gmask, int n_total) {
+  __shared__ double red[4];
+  const int2 e = inst_tab[blockIdx.x];
+  const BNet &N = nets[e.x];
+  const int i = e.y;
+  const BIter it = sc->it[par];
+  if (it.pending) finish_gamma(N, i, it.k - 1, gam_ring, gmask, n_total, red);
+  const double lam = N.lam[i];
+  const double *ci = N.c + (size_t)i * N.n_g, *qi = N.q + (size_t)i * N.n_g;
+  double psum = 0.0, phis = 0.0;
+  for (int j = threadIdx.x; j < N.n_c; j += blockDim.x) {
+    double w = 0.0;
+    for (int s = 0; s < N.S; ++s) w += (double)N.Wws[((size_t)s * N.Bp + i) * N.ncp + j];
+    double x = 0.0, ph = 0.0;
+    for (int u = N.seg[j]; u < N.seg[j + 1]; ++u) {
+      const int g = N.gperm[u];
+      const double r = ci[g] - lam + w;
+      const double p = inner_min_b(r, qi[g], N.pmin[g], N.pmax[g]);
+      ph += r * p + qi[g] * p * p;
+      x += p;
+    }
+    __bf16 hi, lo;
+    split_bf16((float)x, &hi, &lo);
+    N.X_hi[(size_t)i * N.ldc + j] = hi;
+    N.X_lo[(size_t)i * N.ldc + j] = lo;
+    psum += x;
+    phis += ph;
+  }
+  psum = block_sum(psum, red);
+  phis = block_sum(phis, red);
+  if (threadIdx.x == 0) {
+    const double D = N.D[i];
+    N.genpart[i] = phis + lam * D;
+    const double kk = (double)it.k;
+    const double a = N.alpha / (1.0 + prm.decay * kk);
+    const double g = D - psum;  // balance residual
+    if (prm.rule == DCOPF_RULE_GDM) {
+      const double v = N.rho * N.vlam[i] + a * g;
+      N.vlam[i] = v;
+      N.lam[i] = lam + v + (prm.literal ? a * g : 0.0);
+    } else if (prm.rule == DCOPF_RULE_ADAM) {
+      const double c1 = 1.0 - pow(prm.beta1, kk + 1.0), c2 = 1.0 - pow(prm.beta2, kk + 1.0);
+      const double m = prm.beta1 * N.vlam[i] + (1.0 - prm.beta1) * g;
+      const double s = prm.beta2 * N.slam[i] + (1.0 - prm.beta2) * g * g;
+      N.vlam[i] = m;
+      N.slam[i] = s;
+      N.lam[i] = lam + a * (m / c1) / (sqrt(s / c2) + prm.eps);
+    } else {
+      const double s = N.slam[i] + g * g;
+      N.slam[i] = s;
+      N.lam[i] = lam + a * g / (sqrt(s) + prm.eps);
+    }
+    if (blockIdx.x == 0) {
+      BIter nx;
+      nx.k = it.k + 1;
+      nx.pending = 1;
+      nx.pad = 0;
+      sc->it[par ^ 1] = nx;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// F product with the line update in its epilogue.
+// ---------------------------------------------------------------------------
+template <bool LOLO>
+__global__ __launch_bounds__(256) void fgemm_kernel(const BNet *__restrict__ nets,
+                                                    const int4 *__restrict__ tiles,
+                                                    const BScal *sc, int par, BParams prm) {
+  const int4 t = tiles[blockIdx.x];
+  const BNet &N = nets[t.x];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int mt = t.y + wave / N.wn_f, nt = t.z + wave % N.wn_f;
+  if (mt * 32 >= N.Bp || nt * 32 >= N.nlp) return;  // whole wavefront
+  const int r = lane & 31, koff = (lane >> 5) * 8;
+  const size_t arow = (size_t)(mt * 32 + r) * N.ldc + koff;
+  const size_t brow = (size_t)(nt * 32 + r) * N.ldc + koff;
+  const __bf16 *ah = N.X_hi + arow, *al = N.X_lo + arow;
+  const __bf16 *bh = N.P_hi + brow, *bl = N.P_lo + brow;
+  f32x16 acc;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+  split_mma<LOLO>(ah, al, bh, bl, 0, N.ldc, acc);
+  const long long k = sc->it[par].k;
+  const double kk = (double)k;
+  const float a = (float)(N.alpha / (1.0 + prm.decay * kk));
+  const float rho = (float)N.rho;
+  const float c1 = (float)(1.0 - pow(prm.beta1, kk + 1.0));
+  const float c2 = (float)(1.0 - pow(prm.beta2, kk + 1.0));
+  const float b1 = (float)prm.beta1, b2 = (float)prm.beta2, eps = (float)prm.eps;
+  const int line = nt * 32 + r;
+  const bool lvalid = line < N.n_l;
+  const float fl = lvalid ? N.flim32[line] : 0.f;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int i = mt * 32 + mfma32_row(j, lane);
+    double term = 0.0;
+    if (lvalid && i < N.B) {
+      const size_t idx = (size_t)i * N.ldl + line;
+      const float fd = N.fd32[idx];
+      const float F = acc[j] - fd;
+      const float gp = F - fl, gm = -F - fl;
+      const float mp = N.mu_p[idx], mm = N.mu_m[idx];
+      term = (double)(mp - mm) * (double)fd + (double)(mp + mm) * (double)fl;
+      float np_, nm_;
+      if (prm.rule == DCOPF_RULE_GDM) {
+        const float vp = rho * N.v_p[idx] + a * gp, vm = rho * N.v_m[idx] + a * gm;
+        N.v_p[idx] = vp;
+        N.v_m[idx] = vm;
+        np_ = mp + vp;
+        nm_ = mm + vm;
+        if (prm.literal) {
+          np_ += a * gp;
+          nm_ += a * gm;
+        }
+      } else if (prm.rule == DCOPF_RULE_ADAM) {
+        const float m1 = b1 * N.v_p[idx] + (1.f - b1) * gp;
+        const float m2 = b1 * N.v_m[idx] + (1.f - b1) * gm;
+        const float s1 = b2 * N.s_p[idx] + (1.f - b2) * gp * gp;
+        const float s2 = b2 * N.s_m[idx] + (1.f - b2) * gm * gm;
+        N.v_p[idx] = m1;
+        N.v_m[idx] = m2;
+        N.s_p[idx] = s1;
+        N.s_m[idx] = s2;
+        np_ = mp + a * (m1 / c1) / (sqrtf(s1 / c2) + eps);
+        nm_ = mm + a * (m2 / c1) / (sqrtf(s2 / c2) + eps);
+      } else {
+        const float s1 = N.s_p[idx] + gp * gp, s2 = N.s_m[idx] + gm * gm;
+        N.s_p[idx] = s1;
+        N.s_m[idx] = s2;
+        np_ = mp + a * gp / (sqrtf(s1) + eps);
+        nm_ = mm + a * gm / (sqrtf(s2) + eps);
+      }
+      np_ = fmaxf(np_, 0.f);
+      nm_ = fmaxf(nm_, 0.f);
+      N.mu_p[idx] = np_;
+      N.mu_m[idx] = nm_;
+      __bf16 hi, lo;
+      split_bf16(np_ - nm_, &hi, &lo);
+      N.V_hi[idx] = hi;
+      N.V_lo[idx] = lo;
+    }
+    // line terms of instance i summed over the 32 lines of this tile
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) term += __shfl_xor(term, off, kWave);
+    if (r == 0 && i < N.B) N.linepart[(size_t)nt * N.Bp + i] = term;
+  }
+}
+
+// Finish gamma of iteration k_prev for every instance (end of a step call).
+__global__ __launch_bounds__(256) void bfinal_kernel(const BNet *__restrict__ nets,
+                                                     const int2 *__restrict__ inst_tab,
+                                                     BScal *sc, int par, long long k_prev,
+                                                     double *__restrict__ gam_ring,
+                                                     long long gmask, int n_total) {
+  __shared__ double red[4];
+  const int2 e = inst_tab[blockIdx.x];
+  finish_gamma(nets[e.x], e.y, k_prev, gam_ring, gmask, n_total, red);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->it[par].pending = 0;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 products (exact bound, and f_d = H d at setup):
+// C[m][n] = sum_k A[m][k] B[n][k], A [Mp][ld], B [Np][ld], C [Mp][ldo];
+// Mp multiple of 64, Np multiple of 16, ld multiple of 4.  Four wavefronts
+// per workgroup along M, 16 x 16 tiles, v_mfma_f64_16x16x4f64.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void dgemm_nt_kernel(const double *__restrict__ A,
+                                                       const double *__restrict__ Bm,
+                                                       double *__restrict__ C, int ld,
+                                                       int ldo, int Mp) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m0 = (blockIdx.y * 4 + wave) * 16, n0 = blockIdx.x * 16;
+  if (m0 >= Mp) return;
+  const int r = lane & 15, kk = lane >> 4;
+  const double *a = A + (size_t)(m0 + r) * ld + kk;
+  const double *b = Bm + (size_t)(n0 + r) * ld + kk;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < ld; k += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k], b[k], acc, 0, 0, 0);
+  // register j of lane l holds row 4 j + l / 16, column l % 16
+#pragma unroll
+  for (int j = 0; j < 4; ++j) C[(size_t)(m0 + 4 * j + kk) * ldo + n0 + r] = acc[j];
+}
+
+// V64[i][l] = mu+ - mu- (FP64 from the FP32 state) for the exact bound.
+__global__ void make_v64_kernel(const float *mu_p, const float *mu_m, int B, int n_l, int ldl,
+                                double *V64) {
+  const int i = blockIdx.y;
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < n_l; l += gridDim.x * blockDim.x)
+    V64[(size_t)i * ldl + l] =
+        (double)mu_p[(size_t)i * ldl + l] - (double)mu_m[(size_t)i * ldl + l];
+}
+
+// Exact bound of instance i (one workgroup): sum over units of phi with the
+// FP64 w, plus lambda D, minus the FP64 line terms.
+__global__ __launch_bounds__(256) void bound_inst_kernel(BNet N) {
+  __shared__ double red[4];
+  const int i = blockIdx.x;
+  const double lam = N.lam[i];
+  const double *ci = N.c + (size_t)i * N.n_g, *qi = N.q + (size_t)i * N.n_g;
+  double phis = 0.0, lines = 0.0;
+  for (int j = threadIdx.x; j < N.n_c; j += blockDim.x) {
+    const double w = N.W64[(size_t)i * N.ncp + j];
+    for (int u = N.seg[j]; u < N.seg[j + 1]; ++u) {
+      const int g = N.gperm[u];
+      const double r = ci[g] - lam + w;
+      const double p = inner_min_b(r, qi[g], N.pmin[g], N.pmax[g]);
+      phis += r * p + qi[g] * p * p;
+    }
+  }
+  for (int l = threadIdx.x; l < N.n_l; l += blockDim.x) {
+    const double mp = N.mu_p[(size_t)i * N.ldl + l], mm = N.mu_m[(size_t)i * N.ldl + l];
+    lines += (mp - mm) * N.fd64[(size_t)i * N.n_l + l] + (mp + mm) * N.flim64[l];
+  }
+  phis = block_sum(phis, red);
+  lines = block_sum(lines, red);
+  if (threadIdx.x == 0) N.bound[i] = phis + lam * N.D[i] - lines;
+}
+
+// ---- setup -----------------------------------------------------------------
+// tmp[l][j] = H[l][cols[j]] (zero padded to [nlp][ldc]) in FP64.
+__global__ void bgather_kernel(const double *__restrict__ H, int n_bus, int n_l,
+                               const int *__restrict__ cols, int n_c, int ldc,
+                               double *__restrict__ out) {
+  const int l = blockIdx.y;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ldc; j += gridDim.x * blockDim.x)
+    out[(size_t)l * ldc + j] = (l < n_l && j < n_c) ? H[(size_t)l * n_bus + cols[j]] : 0.0;
+}
+
+// outT[j][l] = in[l][j] for j < rowsT, l < ldT (zero beyond the input).
+__global__ void btranspose_kernel(const double *__restrict__ in, int rows_in, int ld_in,
+                                  int rowsT, int ldT, double *__restrict__ outT) {
+  __shared__ double tile[32][33];
+  const int j0 = blockIdx.x * 32, l0 = blockIdx.y * 32;
+  for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+    const int l = l0 + r, j = j0 + threadIdx.x;
+    tile[r][threadIdx.x] = (l < rows_in && j < ld_in) ? in[(size_t)l * ld_in + j] : 0.0;
+  }
+  __syncthreads();
+  for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+    const int j = j0 + r, l = l0 + threadIdx.x;
+    if (j < rowsT && l < ldT) outT[(size_t)j * ldT + l] = tile[threadIdx.x][r];
+  }
+}
+
+__global__ void bsplit_kernel(const double *__restrict__ in, size_t n, __bf16 *__restrict__ hi,
+                              __bf16 *__restrict__ lo) {
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
+       t += (size_t)gridDim.x * blockDim.x) {
+    const double v = in[t];
+    const __bf16 h = (__bf16)v;
+    hi[t] = h;
+    lo[t] = (__bf16)(v - (double)(float)h);
+  }
+}
+
+// f_d from the FP64 product tmp [Bp][nlp16]: fd64 [B][n_l], fd32 [B][ldl]
+__global__ void bfd_kernel(const double *__restrict__ tmp, int ldt, int B, int n_l, int ldl,
+                           double *__restrict__ fd64, float *__restrict__ fd32) {
+  const int i = blockIdx.y;
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < n_l; l += gridDim.x * blockDim.x) {
+    const double v = tmp[(size_t)i * ldt + l];
+    fd64[(size_t)i * n_l + l] = v;
+    fd32[(size_t)i * ldl + l] = (float)v;
+  }
+}
+
+// V hi/lo from the FP32 state (after a warm start).
+__global__ void bmake_v_kernel(const float *mu_p, const float *mu_m, int B, int n_l, int ldl,
+                               __bf16 *V_hi, __bf16 *V_lo) {
+  const int i = blockIdx.y;
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < n_l; l += gridDim.x * blockDim.x) {
+    const size_t idx = (size_t)i * ldl + l;
+    split_bf16(mu_p[idx] - mu_m[idx], V_hi + idx, V_lo + idx);
+  }
+}
+
+}  // namespace
+}  // namespace dcopf
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+using namespace dcopf;
+
+namespace {
+
+struct HostNet {
+  BNet d{};  // device pointers (owned) and shapes
+  int n_bus = 0;
+  std::vector<void *> owned;
+  double best_dummy = 0;
+};
+
+template <typename T> T *balloc(std::vector<void *> &owned, size_t n, bool *ok) {
+  void *p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
+    *ok = false;
+    return nullptr;
+  }
+  owned.push_back(p);
+  return static_cast<T *>(p);
+}
+
+bool finite_all_b(const double *p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+struct dcopf_batch_s {
+  std::vector<HostNet> nets;
+  dcopf_batch_opts opts{};
+  BParams prm{};
+  hipStream_t stream = nullptr;
+  BNet *d_nets = nullptr;
+  int4 *d_wtiles = nullptr, *d_ftiles = nullptr;
+  int2 *d_inst = nullptr;
+  int n_wtiles = 0, n_ftiles = 0, n_total = 0;
+  BScal *sc = nullptr;
+  double *gam = nullptr;
+  long long gcap = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_iters = 0;
+  long long iters = 0;
+  std::vector<double> best;
+  std::vector<long long> best_iter;
+};
+
+namespace {
+
+void free_batch(dcopf_batch_s *b) {
+  if (!b) return;
+  if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto &n : b->nets)
+    for (void *p : n.owned) (void)hipFree(p);
+  void *ptrs[] = {b->d_nets, b->d_wtiles, b->d_ftiles, b->d_inst, b->sc, b->gam};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete b;
+}
+
+// tile tables from the per-network shapes; heavy (long-K) W tiles first
+void build_tables(const std::vector<HostNet> &nets, const std::vector<int> &which,
+                  std::vector<int4> *wt, std::vector<int4> *ft) {
+  wt->clear();
+  ft->clear();
+  std::vector<int> order = which;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return nets[a].d.kchunk > nets[b].d.kchunk;
+  });
+  for (int k : order) {
+    const BNet &N = nets[k].d;
+    const int Mt = N.Bp / 32, Nt = N.ncp / 32;
+    for (int m = 0; m < Mt; m += N.wm_w)
+      for (int n = 0; n < Nt; n += N.wn_w)
+        for (int s = 0; s < N.S; ++s) wt->push_back(make_int4(k, m, n, s));
+  }
+  for (int k : which) {
+    const BNet &N = nets[k].d;
+    const int Mt = N.Bp / 32, Nt = N.nlp / 32;
+    for (int m = 0; m < Mt; m += N.wm_f)
+      for (int n = 0; n < Nt; n += N.wn_f) ft->push_back(make_int4(k, m, n, 0));
+  }
+}
+
+void set_split(BNet &N, int S) {
+  const int kblocks = N.ldl / 64;
+  S = std::max(1, std::min(S, kblocks));
+  N.kchunk = (kblocks + S - 1) / S * 64;
+  N.S = (N.ldl + N.kchunk - 1) / N.kchunk;
+}
+
+void launch_w(dcopf_batch_s *b, hipStream_t s, const int4 *tiles, int n) {
+  if (n == 0) return;
+  if (b->opts.lolo)
+    wgemm_kernel<true><<<n, 256, 0, s>>>(b->d_nets, tiles);
+  else
+    wgemm_kernel<false><<<n, 256, 0, s>>>(b->d_nets, tiles);
+}
+
+void launch_u(dcopf_batch_s *b, hipStream_t s, int par) {
+  units_kernel<<<b->n_total, 256, 0, s>>>(b->d_nets, b->d_inst, b->sc, par, b->prm, b->gam,
+                                          b->gcap - 1, b->n_total);
+}
+
+void launch_f(dcopf_batch_s *b, hipStream_t s, const int4 *tiles, int n, int par) {
+  if (n == 0) return;
+  if (b->opts.lolo)
+    fgemm_kernel<true><<<n, 256, 0, s>>>(b->d_nets, tiles, b->sc, par, b->prm);
+  else
+    fgemm_kernel<false><<<n, 256, 0, s>>>(b->d_nets, tiles, b->sc, par, b->prm);
+}
+
+void launch_iters_b(dcopf_batch_s *b, hipStream_t s, long long first, int64_t n) {
+  for (int64_t t = 0; t < n; ++t) {
+    const int par = (int)((first + t) & 1);
+    launch_w(b, s, b->d_wtiles, b->n_wtiles);
+    launch_u(b, s, par);
+    launch_f(b, s, b->d_ftiles, b->n_ftiles, par);
+  }
+}
+
+void launch_final_b(dcopf_batch_s *b, hipStream_t s) {
+  if (b->iters <= 0) return;
+  const int par = (int)(b->iters & 1);
+  bfinal_kernel<<<b->n_total, 256, 0, s>>>(b->d_nets, b->d_inst, b->sc, par, b->iters - 1,
+                                           b->gam, b->gcap - 1, b->n_total);
+}
+
+// cold start (multipliers, optimiser state, V) of network `only`, or of
+// every network when only < 0; the batch's iteration counter restarts at k0
+hipError_t reset_state(dcopf_batch_s *b, long long k0, int only = -1) {
+  hipError_t e = hipSuccess;
+  for (size_t k = 0; k < b->nets.size(); ++k) {
+    if (only >= 0 && (int)k != only) continue;
+    BNet &N = b->nets[k].d;
+    const size_t st = (size_t)N.B * N.ldl * 4;
+    float *arrs[] = {N.mu_p, N.mu_m, N.v_p, N.v_m, N.s_p, N.s_m};
+    for (float *a : arrs)
+      if (e == hipSuccess) e = hipMemsetAsync(a, 0, st, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(N.V_hi, 0, (size_t)N.Bp * N.ldl * 2, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(N.V_lo, 0, (size_t)N.Bp * N.ldl * 2, b->stream);
+    double *d8[] = {N.lam, N.vlam, N.slam, N.genpart};
+    for (double *a : d8)
+      if (e == hipSuccess) e = hipMemsetAsync(a, 0, (size_t)N.B * 8, b->stream);
+  }
+  BScal s{};
+  s.it[k0 & 1].k = k0;
+  s.it[k0 & 1].pending = 0;
+  s.it[(k0 + 1) & 1].k = k0 + 1;
+  if (e == hipSuccess) e = hipMemcpyAsync(b->sc, &s, sizeof(s), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  b->iters = k0;
+  return e;
+}
+
+hipError_t upload_nets(dcopf_batch_s *b) {
+  std::vector<BNet> h(b->nets.size());
+  for (size_t k = 0; k < h.size(); ++k) h[k] = b->nets[k].d;
+  return hipMemcpy(b->d_nets, h.data(), h.size() * sizeof(BNet), hipMemcpyHostToDevice);
+}
+
+hipError_t upload_tables(dcopf_batch_s *b) {
+  std::vector<int> all(b->nets.size());
+  std::iota(all.begin(), all.end(), 0);
+  std::vector<int4> wt, ft;
+  build_tables(b->nets, all, &wt, &ft);
+  if (b->d_wtiles) (void)hipFree(b->d_wtiles);
+  if (b->d_ftiles) (void)hipFree(b->d_ftiles);
+  b->d_wtiles = b->d_ftiles = nullptr;
+  hipError_t e = hipMalloc(&b->d_wtiles, std::max<size_t>(1, wt.size()) * sizeof(int4));
+  if (e == hipSuccess) e = hipMalloc(&b->d_ftiles, std::max<size_t>(1, ft.size()) * sizeof(int4));
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_wtiles, wt.data(), wt.size() * sizeof(int4), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_ftiles, ft.data(), ft.size() * sizeof(int4), hipMemcpyHostToDevice);
+  b->n_wtiles = (int)wt.size();
+  b->n_ftiles = (int)ft.size();
+  return e;
+}
+
+// time `reps` launches of one phase for network k alone (ms per launch)
+float time_net(dcopf_batch_s *b, int k, bool wphase, int reps) {
+  std::vector<int4> wt, ft;
+  build_tables(b->nets, std::vector<int>{k}, &wt, &ft);
+  std::vector<int4> &tt = wphase ? wt : ft;
+  int4 *d = nullptr;
+  if (hipMalloc(&d, tt.size() * sizeof(int4)) != hipSuccess) return 1e30f;
+  (void)hipMemcpy(d, tt.data(), tt.size() * sizeof(int4), hipMemcpyHostToDevice);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  for (int w = 0; w < 2; ++w) {
+    if (wphase) launch_w(b, b->stream, d, (int)tt.size());
+    else launch_f(b, b->stream, d, (int)tt.size(), 0);
+  }
+  (void)hipEventRecord(e0, b->stream);
+  for (int r = 0; r < reps; ++r) {
+    if (wphase) launch_w(b, b->stream, d, (int)tt.size());
+    else launch_f(b, b->stream, d, (int)tt.size(), 0);
+  }
+  (void)hipEventRecord(e1, b->stream);
+  (void)hipEventSynchronize(e1);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(d);
+  return ms / reps;
+}
+
+// Autotuner: per network, the W arrangement x K split and the F arrangement
+// with the least measured time (each network timed alone).
+hipError_t autotune(dcopf_batch_s *b) {
+  const int arr[3][2] = {{4, 1}, {2, 2}, {1, 4}};
+  const int splits[] = {1, 2, 4, 8, 16, 32};
+  for (size_t k = 0; k < b->nets.size(); ++k) {
+    BNet &N = b->nets[k].d;
+    float bestw = 1e30f;
+    int bw = 0, bs = 1;
+    for (int a = 0; a < 3; ++a)
+      for (int S : splits) {
+        if (S > 1 && N.ldl / S < 256) continue;
+        N.wm_w = arr[a][0];
+        N.wn_w = arr[a][1];
+        set_split(N, S);
+        hipError_t e = upload_nets(b);
+        if (e != hipSuccess) return e;
+        const float t = time_net(b, (int)k, true, 5);
+        if (t < bestw) bestw = t, bw = a, bs = S;
+      }
+    N.wm_w = arr[bw][0];
+    N.wn_w = arr[bw][1];
+    set_split(N, bs);
+    float bestf = 1e30f;
+    int bf = 0;
+    for (int a = 0; a < 3; ++a) {
+      N.wm_f = arr[a][0];
+      N.wn_f = arr[a][1];
+      hipError_t e = upload_nets(b);
+      if (e != hipSuccess) return e;
+      const float t = time_net(b, (int)k, false, 5);
+      if (t < bestf) bestf = t, bf = a;
+    }
+    N.wm_f = arr[bf][0];
+    N.wn_f = arr[bf][1];
+  }
+  return upload_nets(b);
+}
+
+dcopf_status validate_net(const dcopf_batch_network &n, int idx, size_t inst0) {
+  const std::string tag = "network " + std::to_string(idx) + ": ";
+  if (n.n_bus < 2 || n.n_line < 1 || n.n_gen < 1 || n.n_inst < 1)
+    return set_error(tag + "need n_bus >= 2, n_line, n_gen, n_inst >= 1"), DCOPF_E_INVALID;
+  if (n.n_line > (1 << 20) || n.n_bus > (1 << 24) || n.n_inst > (1 << 16))
+    return set_error(tag + "too large"), DCOPF_E_INVALID;
+  if (n.slack < 0 || n.slack >= n.n_bus) return set_error(tag + "slack out of range"), DCOPF_E_INVALID;
+  if (!n.H || !n.gen_bus || !n.p_min || !n.p_max || !n.f_max || !n.d || !n.c)
+    return set_error(tag + "null data pointer"), DCOPF_E_INVALID;
+  const size_t nl = n.n_line, nb = n.n_bus, ng = n.n_gen, B = n.n_inst;
+  if ((double)nl * (double)nb > 4.0e9) return set_error(tag + "H too large"), DCOPF_E_INVALID;
+  for (size_t g = 0; g < ng; ++g)
+    if (n.gen_bus[g] < 0 || n.gen_bus[g] >= n.n_bus)
+      return set_error(tag + "gen_bus out of range"), DCOPF_E_INVALID;
+  if (!finite_all_b(n.H, nl * nb)) return set_error(tag + "H not finite"), DCOPF_E_INVALID;
+  if (!finite_all_b(n.p_min, ng) || !finite_all_b(n.p_max, ng) || !finite_all_b(n.f_max, nl) ||
+      !finite_all_b(n.d, B * nb) || !finite_all_b(n.c, B * ng) ||
+      (n.q && !finite_all_b(n.q, B * ng)))
+    return set_error(tag + "non-finite data"), DCOPF_E_INVALID;
+  for (size_t g = 0; g < ng; ++g)
+    if (n.p_min[g] > n.p_max[g]) return set_error(tag + "p_min > p_max"), DCOPF_E_INVALID;
+  if (n.q)
+    for (size_t t = 0; t < B * ng; ++t)
+      if (n.q[t] < 0) return set_error(tag + "q < 0"), DCOPF_E_INVALID;
+  for (size_t l = 0; l < nl; ++l)
+    if (!(n.f_max[l] > 0)) return set_error(tag + "f_max <= 0"), DCOPF_E_INVALID;
+  for (size_t l = 0; l < nl; ++l)
+    if (n.H[l * nb + n.slack] != 0.0)
+      return set_error(tag + "H column of the slack bus is not zero"), DCOPF_E_INVALID;
+  if (!(n.alpha > 0) || !std::isfinite(n.alpha) || !(n.rho >= 0 && n.rho < 1))
+    return set_error(tag + "alpha must be > 0 and rho in [0,1)"), DCOPF_E_INVALID;
+  double smin = 0, smax = 0;
+  for (size_t g = 0; g < ng; ++g) smin += n.p_min[g], smax += n.p_max[g];
+  for (size_t i = 0; i < B; ++i) {
+    double D = 0;
+    for (size_t bb = 0; bb < nb; ++bb) D += n.d[i * nb + bb];
+    if (D < smin - 1e-9 * std::max(1.0, std::fabs(D)) ||
+        D > smax + 1e-9 * std::max(1.0, std::fabs(D)))
+      return set_error(tag + "instance " + std::to_string(inst0 + i) +
+                       ": total load outside [sum p_min, sum p_max]"),
+             DCOPF_E_INFEASIBLE;
+  }
+  return DCOPF_OK;
+}
+
+dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network &n, int inst0) {
+  BNet &N = hn.d;
+  auto &own = hn.owned;
+  bool ok = true;
+  const int nb = n.n_bus, nl = n.n_line, ng = n.n_gen, B = n.n_inst;
+  std::vector<int> cols(n.gen_bus, n.gen_bus + ng);
+  std::sort(cols.begin(), cols.end());
+  cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+  const int nc = (int)cols.size();
+  std::vector<int> col_of_bus(nb, -1);
+  for (int j = 0; j < nc; ++j) col_of_bus[cols[j]] = j;
+  std::vector<int> gperm(ng);
+  std::iota(gperm.begin(), gperm.end(), 0);
+  std::stable_sort(gperm.begin(), gperm.end(), [&](int a, int c) {
+    return col_of_bus[n.gen_bus[a]] < col_of_bus[n.gen_bus[c]];
+  });
+  std::vector<int> seg(nc + 1, 0);
+  for (int g = 0; g < ng; ++g) seg[col_of_bus[n.gen_bus[g]] + 1]++;
+  for (int j = 0; j < nc; ++j) seg[j + 1] += seg[j];
+  hn.n_bus = nb;
+  N.n_l = nl;
+  N.n_c = nc;
+  N.n_g = ng;
+  N.B = B;
+  N.Bp = (int)round_up(B, 64);  // multiple of 64 for the FP64 bound product
+  N.ldl = (int)round_up(nl, 64);
+  N.ldc = (int)round_up(nc, 64);
+  N.ncp = (int)round_up(nc, 32);
+  N.nlp = (int)round_up(nl, 32);
+  N.ntl = N.nlp / 32;
+  N.inst0 = inst0;
+  N.alpha = n.alpha;
+  N.rho = n.rho;
+  // default shapes: instances along the workgroup when there are many
+  N.wm_w = N.Bp >= 128 ? 4 : 1;
+  N.wn_w = 4 / N.wm_w;
+  N.wm_f = N.wm_w;
+  N.wn_f = N.wn_w;
+  set_split(N, N.Bp >= 256 ? 1 : std::max(1, N.ldl / 2048));
+  const size_t Bp = N.Bp, ldl = N.ldl, ldc = N.ldc, ncp = N.ncp, nlp = N.nlp;
+  __bf16 *PT_hi = balloc<__bf16>(own, ncp * ldl, &ok), *PT_lo = balloc<__bf16>(own, ncp * ldl, &ok);
+  __bf16 *P_hi = balloc<__bf16>(own, nlp * ldc, &ok), *P_lo = balloc<__bf16>(own, nlp * ldc, &ok);
+  double *P64T = balloc<double>(own, ncp * ldl, &ok);
+  N.V_hi = balloc<__bf16>(own, Bp * ldl, &ok);
+  N.V_lo = balloc<__bf16>(own, Bp * ldl, &ok);
+  N.X_hi = balloc<__bf16>(own, Bp * ldc, &ok);
+  N.X_lo = balloc<__bf16>(own, Bp * ldc, &ok);
+  N.Wws = balloc<float>(own, (size_t)32 * Bp * ncp, &ok);
+  float **st[] = {&N.mu_p, &N.mu_m, &N.v_p, &N.v_m, &N.s_p, &N.s_m};
+  for (float **a : st) *a = balloc<float>(own, (size_t)B * ldl, &ok);
+  float *fd32 = balloc<float>(own, (size_t)B * ldl, &ok);
+  float *fl32 = balloc<float>(own, nl, &ok);
+  double *fl64 = balloc<double>(own, nl, &ok);
+  double *fd64 = balloc<double>(own, (size_t)B * nl, &ok);
+  double *c = balloc<double>(own, (size_t)B * ng, &ok), *q = balloc<double>(own, (size_t)B * ng, &ok);
+  double *pmin = balloc<double>(own, ng, &ok), *pmax = balloc<double>(own, ng, &ok);
+  int *dseg = balloc<int>(own, nc + 1, &ok), *dgperm = balloc<int>(own, ng, &ok);
+  N.lam = balloc<double>(own, B, &ok);
+  N.vlam = balloc<double>(own, B, &ok);
+  N.slam = balloc<double>(own, B, &ok);
+  N.genpart = balloc<double>(own, B, &ok);
+  double *D = balloc<double>(own, B, &ok);
+  N.linepart = balloc<double>(own, (size_t)N.ntl * Bp, &ok);
+  N.V64 = balloc<double>(own, Bp * ldl, &ok);
+  N.W64 = balloc<double>(own, Bp * ncp, &ok);
+  N.bound = balloc<double>(own, B, &ok);
+  if (!ok) return set_error("device allocation failed"), DCOPF_E_NOMEM;
+  N.PT_hi = PT_hi;
+  N.PT_lo = PT_lo;
+  N.P_hi = P_hi;
+  N.P_lo = P_lo;
+  N.P64T = P64T;
+  N.fd32 = fd32;
+  N.flim32 = fl32;
+  N.flim64 = fl64;
+  N.fd64 = fd64;
+  N.c = c;
+  N.q = q;
+  N.pmin = pmin;
+  N.pmax = pmax;
+  N.seg = dseg;
+  N.gperm = dgperm;
+  N.D = D;
+  hipStream_t s = b->stream;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t r) {
+    if (r != hipSuccess && e == hipSuccess) e = r;
+  };
+  // temporaries: H (padded rows for the f_d product), loads, gathered panel
+  const size_t ldb = (size_t)round_up(nb, 4), nlp16 = (size_t)round_up(nl, 16);
+  double *Hd = nullptr, *Dm = nullptr, *tmp = nullptr, *fdt = nullptr;
+  int *dcols = nullptr;
+  chk(hipMalloc(&Hd, nlp16 * ldb * 8));
+  chk(hipMalloc(&Dm, Bp * ldb * 8));
+  chk(hipMalloc(&tmp, nlp * ldc * 8));
+  chk(hipMalloc(&fdt, Bp * nlp16 * 8));
+  chk(hipMalloc(&dcols, (size_t)nc * 4));
+  if (e == hipSuccess) {
+    chk(hipMemsetAsync(Hd, 0, nlp16 * ldb * 8, s));
+    chk(hipMemcpy2DAsync(Hd, ldb * 8, n.H, (size_t)nb * 8, (size_t)nb * 8, nl,
+                         hipMemcpyHostToDevice, s));
+    chk(hipMemsetAsync(Dm, 0, Bp * ldb * 8, s));
+    chk(hipMemcpy2DAsync(Dm, ldb * 8, n.d, (size_t)nb * 8, (size_t)nb * 8, B,
+                         hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(dcols, cols.data(), (size_t)nc * 4, hipMemcpyHostToDevice, s));
+    // panel: gather, split; transpose to FP64 P^T, split
+    dim3 gg((unsigned)std::min<size_t>(64, (ldc + 255) / 256), (unsigned)nlp);
+    bgather_kernel<<<gg, 256, 0, s>>>(Hd, (int)ldb, nl, dcols, nc, (int)ldc, tmp);
+    bsplit_kernel<<<2048, 256, 0, s>>>(tmp, nlp * ldc, P_hi, P_lo);
+    dim3 tg((unsigned)(ncp / 32), (unsigned)(ldl / 32));
+    btranspose_kernel<<<tg, dim3(32, 8), 0, s>>>(tmp, nl, (int)ldc, (int)ncp, (int)ldl, P64T);
+    bsplit_kernel<<<2048, 256, 0, s>>>(P64T, ncp * ldl, PT_hi, PT_lo);
+    // f_d = H d for every instance (FP64 matrix cores)
+    dim3 dg((unsigned)(nlp16 / 16), (unsigned)(Bp / 64));
+    dgemm_nt_kernel<<<dg, 256, 0, s>>>(Dm, Hd, fdt, (int)ldb, (int)nlp16, (int)Bp);
+    dim3 fg((unsigned)std::min<size_t>(64, (nl + 255) / 256), (unsigned)B);
+    chk(hipMemsetAsync(fd32, 0, (size_t)B * ldl * 4, s));
+    bfd_kernel<<<fg, 256, 0, s>>>(fdt, (int)nlp16, B, nl, (int)ldl, fd64, fd32);
+    chk(hipGetLastError());
+    // data
+    std::vector<float> f32(n.f_max, n.f_max + nl);
+    std::vector<double> qh((size_t)B * ng, 0.0), Dh(B, 0.0);
+    if (n.q) std::copy(n.q, n.q + (size_t)B * ng, qh.begin());
+    for (int i = 0; i < B; ++i)
+      for (int bb = 0; bb < nb; ++bb) Dh[i] += n.d[(size_t)i * nb + bb];
+    chk(hipMemcpyAsync(fl32, f32.data(), nl * 4, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(fl64, n.f_max, nl * 8, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(c, n.c, (size_t)B * ng * 8, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(q, qh.data(), (size_t)B * ng * 8, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(pmin, n.p_min, ng * 8, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(pmax, n.p_max, ng * 8, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(dseg, seg.data(), (nc + 1) * 4, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(dgperm, gperm.data(), ng * 4, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(D, Dh.data(), B * 8, hipMemcpyHostToDevice, s));
+    chk(hipMemsetAsync(N.X_hi, 0, Bp * ldc * 2, s));
+    chk(hipMemsetAsync(N.X_lo, 0, Bp * ldc * 2, s));
+    chk(hipMemsetAsync(N.V64, 0, Bp * ldl * 8, s));
+    chk(hipMemsetAsync(N.linepart, 0, (size_t)N.ntl * Bp * 8, s));
+    chk(hipStreamSynchronize(s));
+  }
+  if (Hd) (void)hipFree(Hd);
+  if (Dm) (void)hipFree(Dm);
+  if (tmp) (void)hipFree(tmp);
+  if (fdt) (void)hipFree(fdt);
+  if (dcols) (void)hipFree(dcols);
+  if (e != hipSuccess)
+    return set_error(std::string("HIP error in batch setup: ") + hipGetErrorString(e)),
+           DCOPF_E_HIP;
+  return DCOPF_OK;
+}
+
+dcopf_status eval_bounds(dcopf_batch_s *b) {
+  hipStream_t s = b->stream;
+  for (auto &hn : b->nets) {
+    const BNet &N = hn.d;
+    dim3 vg((unsigned)std::min(64, (N.n_l + 255) / 256), (unsigned)N.B);
+    make_v64_kernel<<<vg, 256, 0, s>>>(N.mu_p, N.mu_m, N.B, N.n_l, N.ldl, N.V64);
+    dim3 dg((unsigned)(N.ncp / 16), (unsigned)(N.Bp / 64));
+    dgemm_nt_kernel<<<dg, 256, 0, s>>>(N.V64, N.P64T, N.W64, N.ldl, N.ncp, N.Bp);
+    bound_inst_kernel<<<N.B, 256, 0, s>>>(N);
+  }
+  DCOPF_HIP_TRY(hipGetLastError());
+  DCOPF_HIP_TRY(hipStreamSynchronize(s));
+  return DCOPF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dcopf_status dcopf_batch_create(const dcopf_batch_network *nets, int32_t n_nets,
+                                const dcopf_batch_opts *opts, void *hip_stream,
+                                dcopf_batch_t *out) {
+  if (!out) return set_error("out is NULL"), DCOPF_E_INVALID;
+  *out = nullptr;
+  set_error("");
+  if (!nets || n_nets < 1 || n_nets > 64 || !opts)
+    return set_error("need 1..64 networks and options"), DCOPF_E_INVALID;
+  const dcopf_batch_opts &o = *opts;
+  if (o.rule < 0 || o.rule > 2) return set_error("unknown rule"), DCOPF_E_INVALID;
+  if (o.rule == DCOPF_RULE_ADAM &&
+      !(o.beta1 >= 0 && o.beta1 < 1 && o.beta2 >= 0 && o.beta2 < 1))
+    return set_error("beta1, beta2 must be in [0,1)"), DCOPF_E_INVALID;
+  if (o.rule != DCOPF_RULE_GDM && !(o.eps > 0)) return set_error("eps must be > 0"), DCOPF_E_INVALID;
+  if (!(o.decay >= 0) || !std::isfinite(o.decay)) return set_error("decay must be >= 0"), DCOPF_E_INVALID;
+  if (o.graph_iters < 0 || o.graph_iters > 4096)
+    return set_error("graph_iters must be in [0, 4096]"), DCOPF_E_INVALID;
+  if (o.gamma_cap < 1 || o.gamma_cap > 65536 || (o.gamma_cap & (o.gamma_cap - 1)))
+    return set_error("gamma_cap must be a power of two in [1, 65536]"), DCOPF_E_INVALID;
+  size_t total = 0;
+  for (int k = 0; k < n_nets; ++k) {
+    dcopf_status st = validate_net(nets[k], k, total);
+    if (st != DCOPF_OK) return st;
+    total += nets[k].n_inst;
+  }
+  if (total > (1u << 20)) return set_error("too many instances"), DCOPF_E_INVALID;
+  auto *b = new dcopf_batch_s();
+  b->opts = o;
+  b->prm = BParams{o.rule, o.literal, o.beta1, o.beta2, o.eps, o.decay};
+  b->stream = (hipStream_t)hip_stream;
+  b->nets.resize(n_nets);
+  b->n_total = (int)total;
+  int inst0 = 0;
+  for (int k = 0; k < n_nets; ++k) {
+    dcopf_status st = setup_net(b, b->nets[k], nets[k], inst0);
+    if (st != DCOPF_OK) {
+      free_batch(b);
+      return st;
+    }
+    inst0 += nets[k].n_inst;
+  }
+  std::vector<int2> inst;
+  for (int k = 0; k < n_nets; ++k)
+    for (int i = 0; i < nets[k].n_inst; ++i) inst.push_back(make_int2(k, i));
+  b->gcap = o.gamma_cap;
+  hipError_t e = hipMalloc(&b->d_nets, n_nets * sizeof(BNet));
+  if (e == hipSuccess) e = hipMalloc(&b->d_inst, inst.size() * sizeof(int2));
+  if (e == hipSuccess) e = hipMalloc(&b->sc, sizeof(BScal));
+  if (e == hipSuccess) e = hipMalloc(&b->gam, (size_t)b->gcap * total * 8);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_inst, inst.data(), inst.size() * sizeof(int2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(b->gam, 0, (size_t)b->gcap * total * 8);
+  if (e == hipSuccess) e = upload_nets(b);
+  if (e == hipSuccess) e = reset_state(b, 0);
+  if (e == hipSuccess && o.autotune) e = autotune(b);
+  if (e == hipSuccess) e = upload_tables(b);
+  if (e == hipSuccess) e = reset_state(b, 0);
+  if (e != hipSuccess) {
+    set_error(std::string("HIP error in batch create: ") + hipGetErrorString(e));
+    free_batch(b);
+    return DCOPF_E_HIP;
+  }
+  b->best.assign(total, -INFINITY);
+  b->best_iter.assign(total, -1);
+  b->graph_iters = (o.graph_iters + 1) / 2 * 2;
+  if (b->graph_iters > 0) {
+    hipStream_t cs = nullptr;
+    hipError_t ce = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (ce == hipSuccess) ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (ce == hipSuccess) {
+      launch_iters_b(b, cs, 0, b->graph_iters);
+      ce = hipStreamEndCapture(cs, &b->graph);
+    }
+    if (ce == hipSuccess) ce = hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (ce != hipSuccess) {
+      set_error(std::string("graph capture failed: ") + hipGetErrorString(ce));
+      free_batch(b);
+      return DCOPF_E_HIP;
+    }
+  }
+  *out = b;
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_step(dcopf_batch_t b, int64_t n) {
+  if (!b || n < 0) return set_error("null handle or n < 0"), DCOPF_E_INVALID;
+  if (n == 0) return DCOPF_OK;
+  int64_t left = n;
+  if (b->graph_exec) {
+    if (b->iters & 1) {
+      launch_iters_b(b, b->stream, b->iters, 1);
+      b->iters += 1;
+      left -= 1;
+    }
+    while (left >= b->graph_iters) {
+      DCOPF_HIP_TRY(hipGraphLaunch(b->graph_exec, b->stream));
+      b->iters += b->graph_iters;
+      left -= b->graph_iters;
+    }
+  }
+  launch_iters_b(b, b->stream, b->iters, left);
+  b->iters += left;
+  launch_final_b(b, b->stream);
+  DCOPF_HIP_TRY(hipGetLastError());
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_bound(dcopf_batch_t b, double *values) {
+  if (!b || !values) return set_error("null argument"), DCOPF_E_INVALID;
+  dcopf_status st = eval_bounds(b);
+  if (st != DCOPF_OK) return st;
+  bool finite = true;
+  for (auto &hn : b->nets) {
+    const BNet &N = hn.d;
+    DCOPF_HIP_TRY(hipMemcpy(values + N.inst0, N.bound, (size_t)N.B * 8, hipMemcpyDeviceToHost));
+  }
+  for (int i = 0; i < b->n_total; ++i) {
+    if (!std::isfinite(values[i])) finite = false;
+    if (values[i] > b->best[i]) {
+      b->best[i] = values[i];
+      b->best_iter[i] = b->iters;
+    }
+  }
+  if (!finite) return set_error("non-finite dual value"), DCOPF_E_NONFINITE;
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_best(dcopf_batch_t b, double *values, int64_t *iters) {
+  if (!b) return set_error("null handle"), DCOPF_E_INVALID;
+  for (int i = 0; i < b->n_total; ++i) {
+    if (values) values[i] = b->best[i];
+    if (iters) iters[i] = b->best_iter[i];
+  }
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_solve(dcopf_batch_t b, const double *opt, double gap_tol,
+                               int64_t max_iters, int64_t check_every, int64_t *first_hit) {
+  if (!b || !opt || max_iters < 0 || check_every < 1)
+    return set_error("bad arguments"), DCOPF_E_INVALID;
+  std::vector<double> vals(b->n_total);
+  std::vector<int64_t> hit(b->n_total, -1);
+  int64_t done = 0;
+  dcopf_status st = dcopf_batch_bound(b, vals.data());
+  if (st != DCOPF_OK) return st;
+  while (true) {
+    int open = 0;
+    for (int i = 0; i < b->n_total; ++i) {
+      if (hit[i] < 0 && opt[i] - b->best[i] <= gap_tol * std::fabs(opt[i])) hit[i] = b->best_iter[i];
+      if (hit[i] < 0) ++open;
+    }
+    if (open == 0 || done >= max_iters) break;
+    const int64_t n = std::min<int64_t>(check_every, max_iters - done);
+    st = dcopf_batch_step(b, n);
+    if (st != DCOPF_OK) return st;
+    done += n;
+    st = dcopf_batch_bound(b, vals.data());
+    if (st != DCOPF_OK) return st;
+  }
+  if (first_hit) std::copy(hit.begin(), hit.end(), first_hit);
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_gammas(dcopf_batch_t b, int64_t first, int64_t count, double *out) {
+  if (!b || !out || first < 0 || count < 0) return set_error("bad arguments"), DCOPF_E_INVALID;
+  if (first + count > b->iters || first < b->iters - b->gcap)
+    return set_error("requested iterations not recorded"), DCOPF_E_INVALID;
+  DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
+  for (int64_t t = 0; t < count; ++t) {
+    const int64_t k = (first + t) & (b->gcap - 1);
+    DCOPF_HIP_TRY(hipMemcpy(out + t * b->n_total, b->gam + (size_t)k * b->n_total,
+                            (size_t)b->n_total * 8, hipMemcpyDeviceToHost));
+  }
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_get_multipliers(dcopf_batch_t b, int32_t net, double *lambda,
+                                         double *mu_plus, double *mu_minus) {
+  if (!b || net < 0 || net >= (int)b->nets.size()) return set_error("bad network"), DCOPF_E_INVALID;
+  DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
+  const BNet &N = b->nets[net].d;
+  if (lambda) DCOPF_HIP_TRY(hipMemcpy(lambda, N.lam, (size_t)N.B * 8, hipMemcpyDeviceToHost));
+  std::vector<float> tmp((size_t)N.B * N.ldl);
+  float *src[2] = {N.mu_p, N.mu_m};
+  double *dst[2] = {mu_plus, mu_minus};
+  for (int s = 0; s < 2; ++s) {
+    if (!dst[s]) continue;
+    DCOPF_HIP_TRY(hipMemcpy(tmp.data(), src[s], tmp.size() * 4, hipMemcpyDeviceToHost));
+    for (int i = 0; i < N.B; ++i)
+      for (int l = 0; l < N.n_l; ++l) dst[s][(size_t)i * N.n_l + l] = tmp[(size_t)i * N.ldl + l];
+  }
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_set_multipliers(dcopf_batch_t b, int32_t net, const double *lambda,
+                                         const double *mu_plus, const double *mu_minus) {
+  if (!b || net < 0 || net >= (int)b->nets.size() || !lambda || !mu_plus || !mu_minus)
+    return set_error("bad arguments"), DCOPF_E_INVALID;
+  const BNet &N = b->nets[net].d;
+  const size_t n = (size_t)N.B * N.n_l;
+  if (!finite_all_b(lambda, N.B) || !finite_all_b(mu_plus, n) || !finite_all_b(mu_minus, n))
+    return set_error("non-finite multipliers"), DCOPF_E_INVALID;
+  for (size_t t = 0; t < n; ++t)
+    if (mu_plus[t] < 0 || mu_minus[t] < 0) return set_error("mu must be >= 0"), DCOPF_E_INVALID;
+  DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
+  // this network's optimiser state restarts; the batch's iteration counter
+  // (step decay, Adam bias correction) restarts at 0 for every network
+  DCOPF_HIP_TRY(reset_state(b, 0, net));
+  std::vector<float> tmp((size_t)N.B * N.ldl, 0.f);
+  const double *srcs[2] = {mu_plus, mu_minus};
+  float *dsts[2] = {N.mu_p, N.mu_m};
+  for (int s = 0; s < 2; ++s) {
+    for (int i = 0; i < N.B; ++i)
+      for (int l = 0; l < N.n_l; ++l) tmp[(size_t)i * N.ldl + l] = (float)srcs[s][(size_t)i * N.n_l + l];
+    DCOPF_HIP_TRY(hipMemcpy(dsts[s], tmp.data(), tmp.size() * 4, hipMemcpyHostToDevice));
+  }
+  DCOPF_HIP_TRY(hipMemcpy(N.lam, lambda, (size_t)N.B * 8, hipMemcpyHostToDevice));
+  dim3 vg((unsigned)std::min(64, (N.n_l + 255) / 256), (unsigned)N.B);
+  bmake_v_kernel<<<vg, 256, 0, b->stream>>>(N.mu_p, N.mu_m, N.B, N.n_l, N.ldl, N.V_hi, N.V_lo);
+  DCOPF_HIP_TRY(hipGetLastError());
+  DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
+  std::fill(b->best.begin(), b->best.end(), -INFINITY);
+  std::fill(b->best_iter.begin(), b->best_iter.end(), -1);
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_info(dcopf_batch_t b, int32_t net, int32_t *cfg, int64_t *iters) {
+  if (!b || net < 0 || net >= (int)b->nets.size()) return set_error("bad network"), DCOPF_E_INVALID;
+  const BNet &N = b->nets[net].d;
+  if (cfg) {
+    cfg[0] = N.wm_w;
+    cfg[1] = N.wn_w;
+    cfg[2] = N.S;
+    cfg[3] = N.wm_f * 10 + N.wn_f;
+  }
+  if (iters) *iters = b->iters;
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_time_phases(dcopf_batch_t b, int64_t n, double *ms_out) {
+  if (!b || !ms_out || n < 1) return set_error("bad arguments"), DCOPF_E_INVALID;
+  std::vector<hipEvent_t> ev(6 * (size_t)n, nullptr);
+  for (auto &e : ev) DCOPF_HIP_TRY(hipEventCreate(&e));
+  for (int64_t t = 0; t < n; ++t) {
+    const int par = (int)((b->iters + t) & 1);
+    hipEvent_t *E = &ev[6 * t];
+    DCOPF_HIP_TRY(hipEventRecord(E[0], b->stream));
+    launch_w(b, b->stream, b->d_wtiles, b->n_wtiles);
+    DCOPF_HIP_TRY(hipEventRecord(E[1], b->stream));
+    DCOPF_HIP_TRY(hipEventRecord(E[2], b->stream));
+    launch_u(b, b->stream, par);
+    DCOPF_HIP_TRY(hipEventRecord(E[3], b->stream));
+    DCOPF_HIP_TRY(hipEventRecord(E[4], b->stream));
+    launch_f(b, b->stream, b->d_ftiles, b->n_ftiles, par);
+    DCOPF_HIP_TRY(hipEventRecord(E[5], b->stream));
+  }
+  b->iters += n;
+  launch_final_b(b, b->stream);
+  DCOPF_HIP_TRY(hipGetLastError());
+  DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
+  double acc[3] = {0, 0, 0};
+  for (int64_t t = 0; t < n; ++t)
+    for (int p = 0; p < 3; ++p) {
+      float ms = 0.f;
+      DCOPF_HIP_TRY(hipEventElapsedTime(&ms, ev[6 * t + 2 * p], ev[6 * t + 2 * p + 1]));
+      acc[p] += ms;
+    }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  for (int p = 0; p < 3; ++p) ms_out[p] = acc[p] / n;
+  return DCOPF_OK;
+}
+
+void dcopf_batch_destroy(dcopf_batch_t b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  free_batch(b);
+}
+
+}  // extern "C"

@@ -38,16 +38,23 @@ thread_local std::string g_err;
 void set_error(const std::string &m) { g_err = m; }
 const char *get_error() { return g_err.c_str(); }
 
-// Scalars shared by the kernels of one handle (device memory).
+// Scalars of one iteration.  Two slots, indexed by the parity of the
+// iteration, so a kernel can read the previous iteration's slot while its
+// workgroup 0 writes the current one.
+struct IterSlot {
+  double lam, v_lam, s_lam;  // balance multiplier (and optimiser state) used
+                             // by this iteration
+  double alpha, c1, c2;      // step size and Adam bias corrections
+  long long k;               // iteration index (-1 before the first)
+  int pending;               // partial sums of this iteration not yet folded
+  int pad;
+};
+
 struct DevScalars {
-  double lam, v_lam, s_lam;   // balance multiplier and its optimiser state
-  double psum, gamma_gen;     // column pass: sum p*, sum phi + lambda D
-  double alpha_k, c1, c2;     // step size of this iteration, Adam corrections
-  double gamma_last;          // monitor value of the last finished iterate
-  double D;                   // 1^T d
+  IterSlot slot[2];
+  double D;                  // 1^T d
+  double gamma_last;         // monitor value of the last folded iterate
   double bound_gen, bound_value;
-  long long k;                // iterations done
-  long long pad;
 };
 
 struct StepParams {
@@ -63,17 +70,66 @@ __device__ __forceinline__ double inner_min(double r, double q, double lo, doubl
   return 0.5 * (lo + hi);
 }
 
-// Dot product of one row (length ld, multiple of 64 elements, 16-byte
-// aligned) with a vector, by one wavefront.  Two independent accumulators
-// keep two 16-byte loads in flight per lane.
+// Finish iteration `prev` from its summed partials: its dual value
+// gamma = sum phi + lambda D - line terms, and the lambda step with the
+// balance residual D - sum p* (Algorithm 1 / Adam / AdaGrad).  Returns the
+// slot of the next iteration (not yet pending).
+__device__ __forceinline__ IterSlot fold(const IterSlot &prev, double psum, double phisum,
+                                         double lines, double D, const StepParams &prm,
+                                         double *gamma) {
+  *gamma = phisum + prev.lam * D - lines;
+  const double g = D - psum;
+  const double a = prev.alpha;
+  IterSlot n = prev;
+  if (prm.rule == DCOPF_RULE_GDM) {
+    n.v_lam = prm.rho * prev.v_lam + a * g;
+    n.lam = prev.lam + n.v_lam;
+    if (prm.literal) n.lam += a * g;
+  } else if (prm.rule == DCOPF_RULE_ADAM) {
+    n.v_lam = prm.beta1 * prev.v_lam + (1.0 - prm.beta1) * g;
+    n.s_lam = prm.beta2 * prev.s_lam + (1.0 - prm.beta2) * g * g;
+    n.lam = prev.lam + a * (n.v_lam / prev.c1) / (sqrt(n.s_lam / prev.c2) + prm.eps);
+  } else {
+    n.s_lam = prev.s_lam + g * g;
+    n.lam = prev.lam + a * g / (sqrt(n.s_lam) + prm.eps);
+  }
+  n.pending = 0;
+  return n;
+}
+
+// Step size and bias corrections of iteration k.
+__device__ __forceinline__ void set_step(IterSlot &s, long long k, const StepParams &prm) {
+  const double kk = (double)k;
+  s.k = k;
+  s.alpha = prm.alpha / (1.0 + prm.decay * kk);
+  s.c1 = 1.0 - pow(prm.beta1, kk + 1.0);
+  s.c2 = 1.0 - pow(prm.beta2, kk + 1.0);
+}
+
+// Sum (in index order, deterministic) the partials the previous iteration
+// left: column-pass (sum p*, sum phi) pairs and line-pass line terms.
+__device__ __forceinline__ void sum_partials(const double *pa, int ga, const double *pb, int gb,
+                                             double *red, double *ps, double *phis,
+                                             double *lines) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int b = threadIdx.x; b < ga; b += blockDim.x) {
+    s0 += pa[2 * b];
+    s1 += pa[2 * b + 1];
+  }
+  for (int b = threadIdx.x; b < gb; b += blockDim.x) s2 += pb[b];
+  *ps = block_sum(s0, red);
+  *phis = block_sum(s1, red);
+  *lines = block_sum(s2, red);
+}
+
+// Per-lane share of a row dot product: lane `lane` covers the 16-byte
+// chunks lane, lane + 64, ... of a row of `nv` chunks.
 template <typename T>
-__device__ __forceinline__ T row_dot(const T *__restrict__ row, const T *__restrict__ x,
-                                     int ld, int lane) {
+__device__ __forceinline__ T lane_dot(const T *__restrict__ row, const T *__restrict__ x, int nv,
+                                      int lane) {
   using V = typename Vec16<T>::type;
-  constexpr int NV = Vec16<T>::n;
   const V *r = reinterpret_cast<const V *>(row);
   const V *xv = reinterpret_cast<const V *>(x);
-  const int nv = ld / NV;
   T a0 = 0, a1 = 0;
   int i = lane;
   for (; i + kWave < nv; i += 2 * kWave) {
@@ -83,190 +139,339 @@ __device__ __forceinline__ T row_dot(const T *__restrict__ row, const T *__restr
     a1 = fma_vec(p1, xv[i + kWave], a1);
   }
   if (i < nv) a0 = fma_vec(__builtin_nontemporal_load(r + i), xv[i], a0);
-  return wave_sum(a0 + a1);
+  return a0 + a1;
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_vec(T *dst, const T *src, int ld) {
+  using V = typename Vec16<T>::type;
+  constexpr int NV = Vec16<T>::n;
+  for (int i = threadIdx.x; i < ld / NV; i += blockDim.x)
+    reinterpret_cast<V *>(dst)[i] = reinterpret_cast<const V *>(src)[i];
+}
+
+// Generators of panel column j handled lane-parallel: r, p*, phi per unit,
+// wave sums of p* (the column injection) and phi.  Every lane gets the sums.
+// Unit data is stored column-sorted: the units of column j are
+// seg[j] .. seg[j+1] - 1.
+__device__ __forceinline__ void column_units(int j, double w, double lam,
+                                             const int *__restrict__ seg,
+                                             const double *__restrict__ c,
+                                             const double *__restrict__ q,
+                                             const double *__restrict__ pmin,
+                                             const double *__restrict__ pmax, int lane,
+                                             double *xj, double *phij) {
+  const int g0 = seg[j], g1 = seg[j + 1];
+  double xs = 0.0, ph = 0.0;
+  for (int t = g0 + lane; t < g1; t += kWave) {
+    const double r = c[t] - lam + w;
+    const double p = inner_min(r, q[t], pmin[t], pmax[t]);
+    ph += r * p + q[t] * p * p;
+    xs += p;
+  }
+  *xj = wave_sum(xs);
+  *phij = wave_sum(ph);
 }
 
 // ---------------------------------------------------------------------------
-// Column pass.  ITER: part of an ascent iteration (updates lambda); otherwise
-// the exact-bound evaluation (writes bound_gen only).  STAGE: vector in LDS.
+// Column pass of iteration k (parity par = k & 1).  A workgroup owns CB
+// panel columns; its four wavefronts each stream one quarter of those rows
+// of P^T (the matching quarter of v is read into registers once), and the
+// quarter sums meet in LDS in a fixed order.  Every workgroup also folds
+// iteration k-1 (identically, from its partials) to obtain the lambda of
+// iteration k; workgroup 0 records it.  Wavefront c then handles the units
+// of column c lane-parallel and writes the injection x_j.
 // ---------------------------------------------------------------------------
-template <typename T, bool ITER, bool STAGE>
+template <typename T, int CB>
 __global__ __launch_bounds__(256) void colpass_kernel(
     const T *__restrict__ PT, int n_cols, int ldl, const T *__restrict__ vvec,
-    const int *__restrict__ seg, const int *__restrict__ gperm,
-    const double *__restrict__ c, const double *__restrict__ q,
-    const double *__restrict__ pmin, const double *__restrict__ pmax,
-    DevScalars *sc, T *__restrict__ x_out, double *__restrict__ part,
-    unsigned *counter, StepParams prm) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int *__restrict__ seg, const double *__restrict__ c, const double *__restrict__ q,
+    const double *__restrict__ pmin, const double *__restrict__ pmax, DevScalars *sc, int par,
+    T *__restrict__ x_out, double *__restrict__ part_a, int ga, const double *__restrict__ part_b,
+    int gb, StepParams prm, double *__restrict__ gam_buf, long long gam_mask) {
+  using V = typename Vec16<T>::type;
   __shared__ double red[4];
-  __shared__ bool last_flag;
-  const T *vs = vvec;
-  if (STAGE) {
-    T *vl = reinterpret_cast<T *>(smem_raw);
-    using V = typename Vec16<T>::type;
-    constexpr int NV = Vec16<T>::n;
-    for (int i = threadIdx.x; i < ldl / NV; i += blockDim.x)
-      reinterpret_cast<V *>(vl)[i] = reinterpret_cast<const V *>(vvec)[i];
-    __syncthreads();
-    vs = vl;
-  }
-  const double lam = sc->lam;
+  __shared__ double lam_s;
+  __shared__ T dots[4][CB];
+  __shared__ double colsum[2][4];
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  const int nw = blockDim.x / kWave;
-  double psum = 0.0, phisum = 0.0;
-  for (int j = blockIdx.x * nw + wave; j < n_cols; j += gridDim.x * nw) {
-    T w = row_dot<T>(PT + (size_t)j * ldl, vs, ldl, lane);
-    if (lane == 0) {
-      const double wd = (double)w;
-      double xj = 0.0;
-      for (int k = seg[j]; k < seg[j + 1]; ++k) {
-        const int g = gperm[k];
-        const double r = c[g] - lam + wd;
-        const double p = inner_min(r, q[g], pmin[g], pmax[g]);
-        phisum += r * p + q[g] * p * p;
-        psum += p;
-        xj += p;
+  const IterSlot prev = sc->slot[par ^ 1];
+  // the previous iteration's partials: loads issued now, summed after the products
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (prev.pending) {
+    const double *pa = part_a + (size_t)(par ^ 1) * 2 * ga;
+    const double *pb = part_b + (size_t)(par ^ 1) * gb;
+    for (int b = threadIdx.x; b < ga; b += blockDim.x) {
+      s0 += pa[2 * b];
+      s1 += pa[2 * b + 1];
+    }
+    for (int b = threadIdx.x; b < gb; b += blockDim.x) s2 += pb[b];
+  }
+  // quarter of every owned row: chunks [cb, ce) of nv 16-byte chunks
+  const int nv = ldl / Vec16<T>::n;
+  const int quarter = (nv + 3) / 4;
+  const int cb = wave * quarter, ce = min(nv, cb + quarter);
+  const int j0 = blockIdx.x * CB;
+  const V *vv = reinterpret_cast<const V *>(vvec);
+  T acc[CB], acc2[CB];
+#pragma unroll
+  for (int u = 0; u < CB; ++u) acc[u] = acc2[u] = (T)0;
+  int i = cb + lane;
+  for (; i + kWave < ce; i += 2 * kWave) {
+    const V x0 = vv[i], x1 = vv[i + kWave];
+#pragma unroll
+    for (int u = 0; u < CB; ++u)
+      if (j0 + u < n_cols) {
+        const V *row = reinterpret_cast<const V *>(PT + (size_t)(j0 + u) * ldl);
+        acc[u] = fma_vec(__builtin_nontemporal_load(row + i), x0, acc[u]);
+        acc2[u] = fma_vec(__builtin_nontemporal_load(row + i + kWave), x1, acc2[u]);
       }
-      if (ITER) x_out[j] = (T)xj;
+  }
+  if (i < ce) {
+    const V x0 = vv[i];
+#pragma unroll
+    for (int u = 0; u < CB; ++u)
+      if (j0 + u < n_cols) {
+        const V *row = reinterpret_cast<const V *>(PT + (size_t)(j0 + u) * ldl);
+        acc[u] = fma_vec(__builtin_nontemporal_load(row + i), x0, acc[u]);
+      }
+  }
+#pragma unroll
+  for (int u = 0; u < CB; ++u) {
+    const T d = wave_sum(acc[u] + acc2[u]);
+    if (lane == 0) dots[wave][u] = d;
+  }
+  double ps = 0.0, phis = 0.0, lines = 0.0;
+  if (prev.pending) {
+    ps = block_sum(s0, red);
+    phis = block_sum(s1, red);
+    lines = block_sum(s2, red);
+  }
+  if (threadIdx.x == 0) {
+    IterSlot cur = prev;
+    double gam = 0.0;
+    if (prev.pending) cur = fold(prev, ps, phis, lines, sc->D, prm, &gam);
+    set_step(cur, prev.k + 1, prm);
+    cur.pending = 1;
+    lam_s = cur.lam;
+    if (blockIdx.x == 0) {
+      sc->slot[par] = cur;
+      if (prev.pending) {
+        gam_buf[prev.k & gam_mask] = gam;
+        sc->gamma_last = gam;
+      }
     }
   }
-  const double bp = block_sum(psum, red);
-  const double bphi = block_sum(phisum, red);
+  __syncthreads();
+  double xsum = 0.0, phsum = 0.0;
+  if (wave < CB && j0 + wave < n_cols) {
+    const int j = j0 + wave;
+    const double w = (double)(((dots[0][wave] + dots[1][wave]) + dots[2][wave]) + dots[3][wave]);
+    double xj, phij;
+    column_units(j, w, lam_s, seg, c, q, pmin, pmax, lane, &xj, &phij);
+    if (lane == 0) x_out[j] = (T)xj;
+    xsum = xj;
+    phsum = phij;
+  }
+  if (lane == 0) {
+    colsum[0][wave] = xsum;
+    colsum[1][wave] = phsum;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    store_agent(part + 2 * blockIdx.x, bp);
-    store_agent(part + 2 * blockIdx.x + 1, bphi);
+    part_a[(size_t)par * 2 * ga + 2 * blockIdx.x] =
+        ((colsum[0][0] + colsum[0][1]) + colsum[0][2]) + colsum[0][3];
+    part_a[(size_t)par * 2 * ga + 2 * blockIdx.x + 1] =
+        ((colsum[1][0] + colsum[1][1]) + colsum[1][2]) + colsum[1][3];
   }
-  if (!last_block_done(counter, &last_flag)) return;
-  double tp = 0.0, tphi = 0.0;
-  for (int b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
-    tp += load_agent(part + 2 * b);
-    tphi += load_agent(part + 2 * b + 1);
-  }
-  tp = block_sum(tp, red);
-  tphi = block_sum(tphi, red);
-  if (threadIdx.x != 0) return;
-  const double D = sc->D;
-  if (!ITER) {
-    sc->bound_gen = tphi + lam * D;
-    return;
-  }
-  sc->psum = tp;
-  sc->gamma_gen = tphi + lam * D;
-  // step size and Adam bias corrections of this iteration
-  const double kk = (double)sc->k;
-  const double a = prm.alpha / (1.0 + prm.decay * kk);
-  const double c1 = 1.0 - pow(prm.beta1, kk + 1.0);
-  const double c2 = 1.0 - pow(prm.beta2, kk + 1.0);
-  sc->alpha_k = a;
-  sc->c1 = c1;
-  sc->c2 = c2;
-  const double g = D - tp;  // balance residual: supergradient in lambda
-  double lamn = lam;
-  if (prm.rule == DCOPF_RULE_GDM) {
-    const double v = prm.rho * sc->v_lam + a * g;
-    sc->v_lam = v;
-    lamn = lam + v;
-    if (prm.literal) lamn += a * g;
-  } else if (prm.rule == DCOPF_RULE_ADAM) {
-    const double m = prm.beta1 * sc->v_lam + (1.0 - prm.beta1) * g;
-    const double s = prm.beta2 * sc->s_lam + (1.0 - prm.beta2) * g * g;
-    sc->v_lam = m;
-    sc->s_lam = s;
-    lamn = lam + a * (m / c1) / (sqrt(s / c2) + prm.eps);
-  } else {
-    const double s = sc->s_lam + g * g;
-    sc->s_lam = s;
-    lamn = lam + a * g / (sqrt(s) + prm.eps);
-  }
-  sc->lam = lamn;
 }
 
 // ---------------------------------------------------------------------------
-// Line pass: F = P x - f_d, residuals, mu step + projection, next v.
+// Line pass of iteration k: F = P x - f_d for RW lines per wavefront (their
+// loads interleaved), then lane t < RW applies the step and projection to
+// line t (its state was prefetched before the products), writes the next v,
+// and the line terms of gamma_k go to a per-workgroup partial.
 // ---------------------------------------------------------------------------
-template <typename T, bool STAGE>
+template <typename T, bool STAGE, int RW, int XR>
 __global__ __launch_bounds__(256) void linepass_kernel(
     const T *__restrict__ P, int n_lines, int ldc, const T *__restrict__ x_in,
     const double *__restrict__ fd, const double *__restrict__ flim,
     double *__restrict__ mu_p, double *__restrict__ mu_m, double *__restrict__ v_p,
     double *__restrict__ v_m, double *__restrict__ s_p, double *__restrict__ s_m,
-    T *__restrict__ v_out, DevScalars *sc, double *__restrict__ part, unsigned *counter,
-    StepParams prm, double *__restrict__ gam_buf, long long gam_mask) {
+    T *__restrict__ v_out, const DevScalars *sc, int par, double *__restrict__ part_b, int gb,
+    StepParams prm) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[4];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  const int base = (blockIdx.x * nw + wave) * RW;
+  // prefetch the state of line base + lane
+  const int l = base + lane;
+  const bool mine = lane < RW && l < n_lines;
+  double fdl = 0, fl = 0, mp = 0, mm = 0, vp = 0, vm = 0, sp = 0, sm = 0;
+  if (mine) {
+    fdl = fd[l];
+    fl = flim[l];
+    mp = mu_p[l];
+    mm = mu_m[l];
+    vp = v_p[l];
+    vm = v_m[l];
+    if (prm.rule != DCOPF_RULE_GDM) {
+      sp = s_p[l];
+      sm = s_m[l];
+    }
+  }
+  const IterSlot cur = sc->slot[par];
+  const int nv = ldc / Vec16<T>::n;
+  T acc[RW];
+  if (XR > 0) {
+    // narrow panel: the x chunks this lane needs (the same for every row)
+    // are held in registers, no LDS staging and no barrier
+    using V = typename Vec16<T>::type;
+    const V *xv = reinterpret_cast<const V *>(x_in);
+    V xr[XR > 0 ? XR : 1];
+#pragma unroll
+    for (int u = 0; u < XR; ++u) {
+      const int idx = lane + u * kWave;
+      if (idx < nv) xr[u] = xv[idx];
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      T a = (T)0;
+      if (base + r < n_lines) {
+        const V *row = reinterpret_cast<const V *>(P + (size_t)(base + r) * ldc);
+#pragma unroll
+        for (int u = 0; u < XR; ++u) {
+          const int idx = lane + u * kWave;
+          if (idx < nv) a = fma_vec(__builtin_nontemporal_load(row + idx), xr[u], a);
+        }
+      }
+      acc[r] = a;
+    }
+  } else {
+    const T *xs = x_in;
+    if (STAGE) {
+      stage_vec(reinterpret_cast<T *>(smem_raw), x_in, ldc);
+      __syncthreads();
+      xs = reinterpret_cast<const T *>(smem_raw);
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+      acc[r] = (base + r < n_lines) ? lane_dot<T>(P + (size_t)(base + r) * ldc, xs, nv, lane)
+                                    : (T)0;
+  }
+  double dot = 0.0;
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    const T s = wave_sum(acc[r]);
+    if (lane == r) dot = (double)s;
+  }
+  double term = 0.0;
+  if (mine) {
+    const double F = dot - fdl;
+    const double gp = F - fl, gm = -F - fl;
+    term = (mp - mm) * fdl + (mp + mm) * fl;
+    const double a = cur.alpha;
+    double np_, nm_;
+    if (prm.rule == DCOPF_RULE_GDM) {
+      vp = prm.rho * vp + a * gp;
+      vm = prm.rho * vm + a * gm;
+      v_p[l] = vp;
+      v_m[l] = vm;
+      np_ = mp + vp;
+      nm_ = mm + vm;
+      if (prm.literal) {
+        np_ += a * gp;
+        nm_ += a * gm;
+      }
+    } else if (prm.rule == DCOPF_RULE_ADAM) {
+      vp = prm.beta1 * vp + (1.0 - prm.beta1) * gp;
+      vm = prm.beta1 * vm + (1.0 - prm.beta1) * gm;
+      sp = prm.beta2 * sp + (1.0 - prm.beta2) * gp * gp;
+      sm = prm.beta2 * sm + (1.0 - prm.beta2) * gm * gm;
+      v_p[l] = vp;
+      v_m[l] = vm;
+      s_p[l] = sp;
+      s_m[l] = sm;
+      np_ = mp + a * (vp / cur.c1) / (sqrt(sp / cur.c2) + prm.eps);
+      nm_ = mm + a * (vm / cur.c1) / (sqrt(sm / cur.c2) + prm.eps);
+    } else {
+      sp += gp * gp;
+      sm += gm * gm;
+      s_p[l] = sp;
+      s_m[l] = sm;
+      np_ = mp + a * gp / (sqrt(sp) + prm.eps);
+      nm_ = mm + a * gm / (sqrt(sm) + prm.eps);
+    }
+    np_ = fmax(np_, 0.0);
+    nm_ = fmax(nm_, 0.0);
+    mu_p[l] = np_;
+    mu_m[l] = nm_;
+    v_out[l] = (T)(np_ - nm_);
+  }
+  const double bl = block_sum(term, red);
+  if (threadIdx.x == 0) part_b[(size_t)par * gb + blockIdx.x] = bl;
+}
+
+// Fold the last iteration of a step() call (one workgroup).
+__global__ __launch_bounds__(256) void finalize_kernel(DevScalars *sc, int par,
+                                                       const double *__restrict__ part_a, int ga,
+                                                       const double *__restrict__ part_b, int gb,
+                                                       StepParams prm,
+                                                       double *__restrict__ gam_buf,
+                                                       long long gam_mask) {
+  __shared__ double red[4];
+  const IterSlot s = sc->slot[par];
+  if (!s.pending) return;
+  double ps, phis, lines;
+  sum_partials(part_a + (size_t)par * 2 * ga, ga, part_b + (size_t)par * gb, gb, red, &ps,
+               &phis, &lines);
+  if (threadIdx.x == 0) {
+    double gam = 0.0;
+    IterSlot n = fold(s, ps, phis, lines, sc->D, prm, &gam);
+    sc->slot[par] = n;  // same iteration index, lambda advanced, not pending
+    gam_buf[s.k & gam_mask] = gam;
+    sc->gamma_last = gam;
+  }
+}
+
+// Exact bound, column part (FP64): sum over units of phi at the multipliers
+// (lambda from `lam`, v = mu+ - mu- in vvec), plus lambda D; last workgroup
+// finishes.
+template <bool STAGE>
+__global__ __launch_bounds__(256) void bound_col_kernel(
+    const double *__restrict__ PT, int n_cols, int ldl, const double *__restrict__ vvec,
+    const int *__restrict__ seg, const double *__restrict__ c,
+    const double *__restrict__ q, const double *__restrict__ pmin,
+    const double *__restrict__ pmax, DevScalars *sc, int par, double *__restrict__ part,
+    unsigned *counter) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[4];
   __shared__ bool last_flag;
-  const T *xs = x_in;
-  if (STAGE) {
-    T *xl = reinterpret_cast<T *>(smem_raw);
-    using V = typename Vec16<T>::type;
-    constexpr int NV = Vec16<T>::n;
-    for (int i = threadIdx.x; i < ldc / NV; i += blockDim.x)
-      reinterpret_cast<V *>(xl)[i] = reinterpret_cast<const V *>(x_in)[i];
-    __syncthreads();
-    xs = xl;
-  }
-  const double a = sc->alpha_k, c1 = sc->c1, c2 = sc->c2;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
-  double lsum = 0.0;
-  for (int l = blockIdx.x * nw + wave; l < n_lines; l += gridDim.x * nw) {
-    T f = row_dot<T>(P + (size_t)l * ldc, xs, ldc, lane);
-    if (lane == 0) {
-      const double F = (double)f - fd[l];
-      const double gp = F - flim[l], gm = -F - flim[l];
-      const double mp = mu_p[l], mm = mu_m[l];
-      lsum += (mp - mm) * fd[l] + (mp + mm) * flim[l];
-      double np_, nm_;
-      if (prm.rule == DCOPF_RULE_GDM) {
-        const double vp = prm.rho * v_p[l] + a * gp;
-        const double vm = prm.rho * v_m[l] + a * gm;
-        v_p[l] = vp;
-        v_m[l] = vm;
-        np_ = mp + vp;
-        nm_ = mm + vm;
-        if (prm.literal) {
-          np_ += a * gp;
-          nm_ += a * gm;
-        }
-      } else if (prm.rule == DCOPF_RULE_ADAM) {
-        const double m1 = prm.beta1 * v_p[l] + (1.0 - prm.beta1) * gp;
-        const double m2 = prm.beta1 * v_m[l] + (1.0 - prm.beta1) * gm;
-        const double s1 = prm.beta2 * s_p[l] + (1.0 - prm.beta2) * gp * gp;
-        const double s2 = prm.beta2 * s_m[l] + (1.0 - prm.beta2) * gm * gm;
-        v_p[l] = m1;
-        v_m[l] = m2;
-        s_p[l] = s1;
-        s_m[l] = s2;
-        np_ = mp + a * (m1 / c1) / (sqrt(s1 / c2) + prm.eps);
-        nm_ = mm + a * (m2 / c1) / (sqrt(s2 / c2) + prm.eps);
-      } else {
-        const double s1 = s_p[l] + gp * gp, s2 = s_m[l] + gm * gm;
-        s_p[l] = s1;
-        s_m[l] = s2;
-        np_ = mp + a * gp / (sqrt(s1) + prm.eps);
-        nm_ = mm + a * gm / (sqrt(s2) + prm.eps);
-      }
-      np_ = fmax(np_, 0.0);
-      nm_ = fmax(nm_, 0.0);
-      mu_p[l] = np_;
-      mu_m[l] = nm_;
-      v_out[l] = (T)(np_ - nm_);
-    }
+  const double lam = sc->slot[par].lam;
+  const double *vs = vvec;
+  if (STAGE) {
+    stage_vec(reinterpret_cast<double *>(smem_raw), vvec, ldl);
+    __syncthreads();
+    vs = reinterpret_cast<const double *>(smem_raw);
   }
-  const double bl = block_sum(lsum, red);
-  if (threadIdx.x == 0) store_agent(part + blockIdx.x, bl);
+  const int nv = ldl / 2;
+  double phisum = 0.0;
+  for (int j = blockIdx.x * nw + wave; j < n_cols; j += gridDim.x * nw) {
+    const double w = wave_sum(lane_dot<double>(PT + (size_t)j * ldl, vs, nv, lane));
+    double xj, phij;
+    column_units(j, w, lam, seg, c, q, pmin, pmax, lane, &xj, &phij);
+    if (lane == 0) phisum += phij;
+  }
+  const double bphi = block_sum(phisum, red);
+  if (threadIdx.x == 0) store_agent(part + blockIdx.x, bphi);
   if (!last_block_done(counter, &last_flag)) return;
   double t = 0.0;
   for (int b = threadIdx.x; b < gridDim.x; b += blockDim.x) t += load_agent(part + b);
   t = block_sum(t, red);
-  if (threadIdx.x == 0) {
-    const double gam = sc->gamma_gen - t;
-    const long long k = sc->k;
-    gam_buf[k & gam_mask] = gam;
-    sc->gamma_last = gam;
-    sc->k = k + 1;
-  }
+  if (threadIdx.x == 0) sc->bound_gen = t + lam * sc->D;
 }
 
 // Line terms of the exact bound: sum_l (mu+ - mu-) f_d + (mu+ + mu-) f_max.
@@ -384,7 +589,8 @@ struct dcopf_dual_s {
          *s_m = nullptr;
   void *vbuf = nullptr, *xbuf = nullptr;  // loop precision vectors (padded)
   double *v64b = nullptr;                 // FP64 v for the exact bound
-  double *part_a = nullptr, *part_b = nullptr, *part_c = nullptr;
+  double *part_a = nullptr, *part_b = nullptr;  // iteration partials [2][...] by parity
+  double *part_c = nullptr, *part_d = nullptr;  // exact-bound partials
   unsigned *counters = nullptr;
   DevScalars *sc = nullptr;
   double *gam = nullptr;
@@ -392,9 +598,12 @@ struct dcopf_dual_s {
   int grid_col = 0, grid_line = 0, grid_bnd_col = 0, grid_bnd_line = 0;
   size_t lds_col = 0, lds_line = 0, lds_bnd = 0;
   bool stage_col = false, stage_line = false, stage_bnd = false;
-  // graph of graph_iters iterations
+  int col_cb = 1;   // panel columns per workgroup in the column pass
+  int line_xr = 0;  // x chunks per lane held in registers (0: LDS / global)
+  // graph of graph_iters iterations (even), starting at an even iteration
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  int graph_iters = 0;
   // host bookkeeping
   long long iters = 0;
   double best = -INFINITY;
@@ -404,48 +613,62 @@ struct dcopf_dual_s {
 
 namespace {
 
-template <typename T>
-void launch_colpass(dcopf_dual_s *h, hipStream_t s) {
+constexpr int kLineRows = 4;  // lines per wavefront in the line pass
+
+template <typename T, int CB>
+void launch_colpass_cb(dcopf_dual_s *h, hipStream_t s, int par) {
   T *PT = std::is_same<T, float>::value ? (T *)h->P32T : (T *)h->P64T;
-  T *v = (T *)h->vbuf, *x = (T *)h->xbuf;
-  if (h->stage_col)
-    colpass_kernel<T, true, true><<<h->grid_col, 256, h->lds_col, s>>>(
-        PT, h->n_cols, h->ldl, v, h->seg, h->gperm, h->c, h->q, h->pmin, h->pmax, h->sc, x,
-        h->part_a, h->counters + 0, h->prm);
-  else
-    colpass_kernel<T, true, false><<<h->grid_col, 256, 0, s>>>(
-        PT, h->n_cols, h->ldl, v, h->seg, h->gperm, h->c, h->q, h->pmin, h->pmax, h->sc, x,
-        h->part_a, h->counters + 0, h->prm);
+  colpass_kernel<T, CB><<<h->grid_col, 256, 0, s>>>(
+      PT, h->n_cols, h->ldl, (T *)h->vbuf, h->seg, h->c, h->q, h->pmin, h->pmax, h->sc, par,
+      (T *)h->xbuf, h->part_a, h->grid_col, h->part_b, h->grid_line, h->prm, h->gam,
+      kGamCap - 1);
 }
 
 template <typename T>
-void launch_linepass(dcopf_dual_s *h, hipStream_t s) {
+void launch_colpass(dcopf_dual_s *h, hipStream_t s, int par) {
+  if (h->col_cb == 1) launch_colpass_cb<T, 1>(h, s, par);
+  else if (h->col_cb == 2) launch_colpass_cb<T, 2>(h, s, par);
+  else launch_colpass_cb<T, 4>(h, s, par);
+}
+
+template <typename T>
+void launch_linepass(dcopf_dual_s *h, hipStream_t s, int par) {
   T *P = std::is_same<T, float>::value ? (T *)h->P32 : (T *)h->P64;
   T *v = (T *)h->vbuf, *x = (T *)h->xbuf;
-  if (h->stage_line)
-    linepass_kernel<T, true><<<h->grid_line, 256, h->lds_line, s>>>(
-        P, h->n_lines, h->ldc, x, h->fd, h->fmax, h->mu_p, h->mu_m, h->v_p, h->v_m, h->s_p,
-        h->s_m, v, h->sc, h->part_b, h->counters + 1, h->prm, h->gam, kGamCap - 1);
-  else
-    linepass_kernel<T, false><<<h->grid_line, 256, 0, s>>>(
-        P, h->n_lines, h->ldc, x, h->fd, h->fmax, h->mu_p, h->mu_m, h->v_p, h->v_m, h->s_p,
-        h->s_m, v, h->sc, h->part_b, h->counters + 1, h->prm, h->gam, kGamCap - 1);
+#define DCOPF_LINEPASS(STAGE, XR, LDS)                                                      \
+  linepass_kernel<T, STAGE, kLineRows, XR><<<h->grid_line, 256, LDS, s>>>(                  \
+      P, h->n_lines, h->ldc, x, h->fd, h->fmax, h->mu_p, h->mu_m, h->v_p, h->v_m, h->s_p,     \
+      h->s_m, v, h->sc, par, h->part_b, h->grid_line, h->prm)
+  if (h->line_xr == 2) DCOPF_LINEPASS(false, 2, 0);
+  else if (h->line_xr == 4) DCOPF_LINEPASS(false, 4, 0);
+  else if (h->stage_line) DCOPF_LINEPASS(true, 0, h->lds_line);
+  else DCOPF_LINEPASS(false, 0, 0);
+#undef DCOPF_LINEPASS
 }
 
-void launch_phase(dcopf_dual_s *h, hipStream_t s, int phase) {
+void launch_phase(dcopf_dual_s *h, hipStream_t s, int phase, int par) {
   const bool fp32 = h->opts.precision == DCOPF_PREC_FP32;
   if (phase == 0) {
-    if (fp32) launch_colpass<float>(h, s); else launch_colpass<double>(h, s);
+    if (fp32) launch_colpass<float>(h, s, par); else launch_colpass<double>(h, s, par);
   } else {
-    if (fp32) launch_linepass<float>(h, s); else launch_linepass<double>(h, s);
+    if (fp32) launch_linepass<float>(h, s, par); else launch_linepass<double>(h, s, par);
   }
 }
 
-void launch_iters(dcopf_dual_s *h, hipStream_t s, int64_t n) {
+// n iterations starting at iteration index `first` (parity from the index)
+void launch_iters(dcopf_dual_s *h, hipStream_t s, long long first, int64_t n) {
   for (int64_t i = 0; i < n; ++i) {
-    launch_phase(h, s, 0);
-    launch_phase(h, s, 1);
+    const int par = (int)((first + i) & 1);
+    launch_phase(h, s, 0, par);
+    launch_phase(h, s, 1, par);
   }
+}
+
+// Fold the partials of the last launched iteration (no-op when none pending).
+void launch_finalize(dcopf_dual_s *h, hipStream_t s) {
+  const int par = (int)((h->iters - 1) & 1);
+  finalize_kernel<<<1, 256, 0, s>>>(h->sc, par, h->part_a, h->grid_col, h->part_b,
+                                    h->grid_line, h->prm, h->gam, kGamCap - 1);
 }
 
 void refresh_v(dcopf_dual_s *h) {
@@ -458,6 +681,13 @@ void refresh_v(dcopf_dual_s *h) {
                                                           h->ldl, (double *)h->vbuf);
 }
 
+// Host copy of the scalars; the folded state of iteration iters - 1.
+dcopf_status read_scalars(dcopf_dual_s *h, DevScalars *out) {
+  DCOPF_HIP_TRY(hipStreamSynchronize(h->stream));
+  DCOPF_HIP_TRY(hipMemcpy(out, h->sc, sizeof(DevScalars), hipMemcpyDeviceToHost));
+  return DCOPF_OK;
+}
+
 dcopf_status validate(const dcopf_problem *p, const dcopf_opts *o) {
   if (!p || !o) return set_error("null problem or options"), DCOPF_E_INVALID;
   if (p->n_bus < 2 || p->n_line < 1 || p->n_gen < 1)
@@ -467,6 +697,8 @@ dcopf_status validate(const dcopf_problem *p, const dcopf_opts *o) {
   if (!p->H || !p->gen_bus || !p->c || !p->p_min || !p->p_max || !p->d || !p->f_max)
     return set_error("null data pointer"), DCOPF_E_INVALID;
   const size_t nl = p->n_line, nb = p->n_bus, ng = p->n_gen;
+  if (nl > (1u << 20) || nb > (1u << 24))
+    return set_error("at most 2^20 lines and 2^24 buses"), DCOPF_E_INVALID;
   if ((double)nl * (double)nb > 4.0e9)
     return set_error("H larger than 4e9 entries"), DCOPF_E_INVALID;
   for (size_t g = 0; g < ng; ++g)
@@ -521,7 +753,7 @@ void free_handle(dcopf_dual_s *h) {
   void *ptrs[] = {h->P32, h->P32T, h->P64, h->P64T, h->fd, h->fmax, h->c, h->q,
                   h->pmin, h->pmax, h->seg, h->gperm, h->mu_p, h->mu_m, h->v_p, h->v_m,
                   h->s_p, h->s_m, h->vbuf, h->xbuf, h->v64b, h->part_a, h->part_b,
-                  h->part_c, h->counters, h->sc, h->gam};
+                  h->part_c, h->part_d, h->counters, h->sc, h->gam};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete h;
@@ -582,8 +814,15 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   const size_t esz = fp32 ? 4 : 8;
 
   // launch shapes: 4 wavefronts per workgroup
-  h->grid_col = grid_for(nc, 4, 4096);
-  h->grid_line = grid_for(nl, 8, 4096);
+  // column pass: enough workgroups to cover the chip (one to four columns
+  // each); line pass: x in registers when a row has at most 4 chunks per lane
+  h->col_cb = nc >= 2048 ? 4 : (nc >= 1024 ? 2 : 1);
+  h->grid_col = (nc + h->col_cb - 1) / h->col_cb;
+  {
+    const int nvc = h->ldc / (fp32 ? 4 : 2);
+    h->line_xr = nvc <= 128 ? 2 : (nvc <= 256 ? 4 : 0);
+  }
+  h->grid_line = grid_for(nl, 4 * kLineRows, 65536);
   h->grid_bnd_col = grid_for(nc, 4, 4096);
   h->grid_bnd_line = grid_for(nl, 256, 1024);
   h->lds_col = (size_t)h->ldl * esz;
@@ -615,9 +854,10 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   h->vbuf = dalloc<unsigned char>((size_t)h->ldl * esz, &st);
   h->xbuf = dalloc<unsigned char>((size_t)h->ldc * esz, &st);
   h->v64b = dalloc<double>(h->ldl, &st);
-  h->part_a = dalloc<double>(2 * (size_t)std::max(h->grid_col, h->grid_bnd_col), &st);
-  h->part_b = dalloc<double>((size_t)h->grid_line, &st);
+  h->part_a = dalloc<double>(4 * (size_t)h->grid_col, &st);
+  h->part_b = dalloc<double>(2 * (size_t)h->grid_line, &st);
   h->part_c = dalloc<double>((size_t)h->grid_bnd_line, &st);
+  h->part_d = dalloc<double>((size_t)h->grid_bnd_col, &st);
   h->counters = dalloc<unsigned>(8, &st);
   h->sc = dalloc<DevScalars>(1, &st);
   h->gam = dalloc<double>(kGamCap, &st);
@@ -645,12 +885,19 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   chk(hipMemcpyAsync(Hd, p->H, (size_t)nl * nb * 8, hipMemcpyHostToDevice, s));
   chk(hipMemcpyAsync(dd, p->d, (size_t)nb * 8, hipMemcpyHostToDevice, s));
   chk(hipMemcpyAsync(dcols, cols.data(), (size_t)nc * 4, hipMemcpyHostToDevice, s));
-  std::vector<double> qh(ng, 0.0);
-  if (p->q) std::copy(p->q, p->q + ng, qh.begin());
-  chk(hipMemcpyAsync(h->c, p->c, ng * 8, hipMemcpyHostToDevice, s));
-  chk(hipMemcpyAsync(h->q, qh.data(), ng * 8, hipMemcpyHostToDevice, s));
-  chk(hipMemcpyAsync(h->pmin, p->p_min, ng * 8, hipMemcpyHostToDevice, s));
-  chk(hipMemcpyAsync(h->pmax, p->p_max, ng * 8, hipMemcpyHostToDevice, s));
+  // unit data in column-sorted order (unit t of the panel = generator gperm[t])
+  std::vector<double> cs(ng), qs(ng, 0.0), lo(ng), hi(ng);
+  for (int t = 0; t < ng; ++t) {
+    const int g = gperm[t];
+    cs[t] = p->c[g];
+    qs[t] = p->q ? p->q[g] : 0.0;
+    lo[t] = p->p_min[g];
+    hi[t] = p->p_max[g];
+  }
+  chk(hipMemcpyAsync(h->c, cs.data(), ng * 8, hipMemcpyHostToDevice, s));
+  chk(hipMemcpyAsync(h->q, qs.data(), ng * 8, hipMemcpyHostToDevice, s));
+  chk(hipMemcpyAsync(h->pmin, lo.data(), ng * 8, hipMemcpyHostToDevice, s));
+  chk(hipMemcpyAsync(h->pmax, hi.data(), ng * 8, hipMemcpyHostToDevice, s));
   chk(hipMemcpyAsync(h->fmax, p->f_max, nl * 8, hipMemcpyHostToDevice, s));
   chk(hipMemcpyAsync(h->seg, seg.data(), (nc + 1) * 4, hipMemcpyHostToDevice, s));
   chk(hipMemcpyAsync(h->gperm, gperm.data(), ng * 4, hipMemcpyHostToDevice, s));
@@ -662,6 +909,10 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   double D = 0.0;
   for (int b = 0; b < nb; ++b) D += p->d[b];
   sch.D = D;
+  // cold start (Algorithm 1): lambda = 0, no iteration done; the slot of
+  // iteration -1 (parity 1) is what iteration 0 reads
+  sch.slot[1].k = -1;
+  sch.slot[0].k = -2;
   chk(hipMemcpyAsync(h->sc, &sch, sizeof(sch), hipMemcpyHostToDevice, s));
   // panels
   {
@@ -705,8 +956,10 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
     ub += std::max(a, b);
   }
   h->cost_ub = ub;
-  // capture graph_iters iterations into a HIP graph (on a private stream)
-  if (o->graph_iters > 0) {
+  // capture graph_iters (rounded up to even) iterations, starting at an even
+  // iteration, into a HIP graph (on a private stream)
+  h->graph_iters = (o->graph_iters + 1) / 2 * 2;
+  if (h->graph_iters > 0) {
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
       free_handle(h);
@@ -714,7 +967,7 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
     }
     hipError_t ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (ce == hipSuccess) {
-      launch_iters(h, cs, o->graph_iters);
+      launch_iters(h, cs, 0, h->graph_iters);
       ce = hipStreamEndCapture(cs, &h->graph);
     }
     if (ce == hipSuccess) ce = hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0);
@@ -731,42 +984,50 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
 
 dcopf_status dcopf_dual_step(dcopf_dual_t h, int64_t n) {
   if (!h || n < 0) return set_error("null handle or n < 0"), DCOPF_E_INVALID;
+  if (n == 0) return DCOPF_OK;
   int64_t left = n;
   if (h->graph_exec) {
-    const int gi = h->opts.graph_iters;
+    if (h->iters & 1) {  // the graph starts at an even iteration
+      launch_iters(h, h->stream, h->iters, 1);
+      h->iters += 1;
+      left -= 1;
+    }
+    const int gi = h->graph_iters;
     while (left >= gi) {
       DCOPF_HIP_TRY(hipGraphLaunch(h->graph_exec, h->stream));
+      h->iters += gi;
       left -= gi;
     }
   }
-  launch_iters(h, h->stream, left);
+  launch_iters(h, h->stream, h->iters, left);
+  h->iters += left;
+  launch_finalize(h, h->stream);
   DCOPF_HIP_TRY(hipGetLastError());
-  h->iters += n;
   return DCOPF_OK;
 }
 
 static dcopf_status eval_bound(dcopf_dual_t h, double *value) {
   hipStream_t s = h->stream;
   const int blocks = (int)std::min<int64_t>(1024, (h->ldl + 255) / 256);
+  const int par = (int)((h->iters - 1) & 1);  // slot holding the current lambda
   make_v_kernel<double><<<blocks, 256, 0, s>>>(h->mu_p, h->mu_m, h->n_lines, h->ldl, h->v64b);
-  StepParams none = h->prm;
   if (h->stage_bnd)
-    colpass_kernel<double, false, true><<<h->grid_bnd_col, 256, h->lds_bnd, s>>>(
-        h->P64T, h->n_cols, h->ldl, h->v64b, h->seg, h->gperm, h->c, h->q, h->pmin, h->pmax,
-        h->sc, nullptr, h->part_a, h->counters + 2, none);
+    bound_col_kernel<true><<<h->grid_bnd_col, 256, h->lds_bnd, s>>>(
+        h->P64T, h->n_cols, h->ldl, h->v64b, h->seg, h->c, h->q, h->pmin, h->pmax,
+        h->sc, par, h->part_d, h->counters + 2);
   else
-    colpass_kernel<double, false, false><<<h->grid_bnd_col, 256, 0, s>>>(
-        h->P64T, h->n_cols, h->ldl, h->v64b, h->seg, h->gperm, h->c, h->q, h->pmin, h->pmax,
-        h->sc, nullptr, h->part_a, h->counters + 2, none);
+    bound_col_kernel<false><<<h->grid_bnd_col, 256, 0, s>>>(
+        h->P64T, h->n_cols, h->ldl, h->v64b, h->seg, h->c, h->q, h->pmin, h->pmax,
+        h->sc, par, h->part_d, h->counters + 2);
   bound_lines_kernel<<<h->grid_bnd_line, 256, 0, s>>>(h->mu_p, h->mu_m, h->fd, h->fmax,
                                                        h->n_lines, h->sc, h->part_c,
                                                        h->counters + 3);
   DCOPF_HIP_TRY(hipGetLastError());
   DevScalars sch;
-  DCOPF_HIP_TRY(hipMemcpyAsync(&sch, h->sc, sizeof(sch), hipMemcpyDeviceToHost, s));
-  DCOPF_HIP_TRY(hipStreamSynchronize(s));
+  dcopf_status st = read_scalars(h, &sch);
+  if (st != DCOPF_OK) return st;
   *value = sch.bound_value;
-  if (!std::isfinite(sch.bound_value) || !std::isfinite(sch.lam))
+  if (!std::isfinite(sch.bound_value) || !std::isfinite(sch.slot[par].lam))
     return set_error("non-finite dual value or multiplier"), DCOPF_E_NONFINITE;
   if (sch.bound_value > h->best) {
     h->best = sch.bound_value;
@@ -783,8 +1044,9 @@ dcopf_status dcopf_dual_bound(dcopf_dual_t h, double *value, double *lambda, dou
   if (value) *value = v;
   if (lambda) {
     DevScalars sch;
-    DCOPF_HIP_TRY(hipMemcpy(&sch, h->sc, sizeof(sch), hipMemcpyDeviceToHost));
-    *lambda = sch.lam;
+    dcopf_status s2 = read_scalars(h, &sch);
+    if (s2 != DCOPF_OK) return s2;
+    *lambda = sch.slot[(h->iters - 1) & 1].lam;
   }
   if (mu_plus) DCOPF_HIP_TRY(hipMemcpy(mu_plus, h->mu_p, h->n_lines * 8, hipMemcpyDeviceToHost));
   if (mu_minus)
@@ -853,7 +1115,8 @@ dcopf_status dcopf_dual_solve(dcopf_dual_t h, double opt, double gap_tol, double
     }
   }
   DevScalars sch;
-  DCOPF_HIP_TRY(hipMemcpy(&sch, h->sc, sizeof(sch), hipMemcpyDeviceToHost));
+  st = read_scalars(h, &sch);
+  if (st != DCOPF_OK) return st;
   res->bound = h->best;
   res->gamma_last = sch.gamma_last;
   res->gap = use_opt ? (opt - h->best) / std::fabs(opt) : NAN;
@@ -868,13 +1131,14 @@ size_t dcopf_dual_state_len(dcopf_dual_t h) { return h ? 5 + 6 * (size_t)h->n_li
 dcopf_status dcopf_dual_get_state(dcopf_dual_t h, double *buf, size_t len) {
   if (!h || !buf) return set_error("null argument"), DCOPF_E_INVALID;
   if (len != dcopf_dual_state_len(h)) return set_error("state length mismatch"), DCOPF_E_STATE;
-  DCOPF_HIP_TRY(hipStreamSynchronize(h->stream));
   DevScalars sch;
-  DCOPF_HIP_TRY(hipMemcpy(&sch, h->sc, sizeof(sch), hipMemcpyDeviceToHost));
-  buf[0] = (double)sch.k;
-  buf[1] = sch.lam;
-  buf[2] = sch.v_lam;
-  buf[3] = sch.s_lam;
+  dcopf_status st = read_scalars(h, &sch);
+  if (st != DCOPF_OK) return st;
+  const IterSlot &sl = sch.slot[(h->iters - 1) & 1];
+  buf[0] = (double)h->iters;
+  buf[1] = sl.lam;
+  buf[2] = sl.v_lam;
+  buf[3] = sl.s_lam;
   buf[4] = 0.0;
   const size_t nl = h->n_lines;
   double *arrs[] = {h->mu_p, h->mu_m, h->v_p, h->v_m, h->s_p, h->s_m};
@@ -890,20 +1154,26 @@ dcopf_status dcopf_dual_set_state(dcopf_dual_t h, const double *buf, size_t len)
   const size_t nl = h->n_lines;
   for (size_t i = 0; i < 2 * nl; ++i)
     if (buf[5 + i] < 0.0) return set_error("mu must be >= 0"), DCOPF_E_INVALID;
-  if (buf[0] < 0 || buf[0] != std::floor(buf[0]))
+  if (buf[0] < 0 || buf[0] != std::floor(buf[0]) || buf[0] > 1e15)
     return set_error("iteration must be a nonnegative integer"), DCOPF_E_INVALID;
-  DCOPF_HIP_TRY(hipStreamSynchronize(h->stream));
   DevScalars sch;
-  DCOPF_HIP_TRY(hipMemcpy(&sch, h->sc, sizeof(sch), hipMemcpyDeviceToHost));
-  sch.k = (long long)buf[0];
-  sch.lam = buf[1];
-  sch.v_lam = buf[2];
-  sch.s_lam = buf[3];
+  dcopf_status st = read_scalars(h, &sch);
+  if (st != DCOPF_OK) return st;
+  const long long k0 = (long long)buf[0];
+  IterSlot sl{};
+  sl.lam = buf[1];
+  sl.v_lam = buf[2];
+  sl.s_lam = buf[3];
+  sl.k = k0 - 1;
+  sl.pending = 0;
+  sch.slot[(k0 - 1) & 1] = sl;
+  sch.slot[k0 & 1] = IterSlot{};
+  sch.slot[k0 & 1].k = k0 - 2;
   DCOPF_HIP_TRY(hipMemcpy(h->sc, &sch, sizeof(sch), hipMemcpyHostToDevice));
   double *arrs[] = {h->mu_p, h->mu_m, h->v_p, h->v_m, h->s_p, h->s_m};
   for (int i = 0; i < 6; ++i)
     DCOPF_HIP_TRY(hipMemcpy(arrs[i], buf + 5 + i * nl, nl * 8, hipMemcpyHostToDevice));
-  h->iters = sch.k;
+  h->iters = k0;
   refresh_v(h);
   DCOPF_HIP_TRY(hipGetLastError());
   DCOPF_HIP_TRY(hipStreamSynchronize(h->stream));
@@ -912,28 +1182,48 @@ dcopf_status dcopf_dual_set_state(dcopf_dual_t h, const double *buf, size_t len)
 
 dcopf_status dcopf_dual_time_phases(dcopf_dual_t h, int64_t n, double *ms_out) {
   if (!h || !ms_out || n < 1) return set_error("bad arguments"), DCOPF_E_INVALID;
-  std::vector<hipEvent_t> ev(4 * (size_t)n, nullptr);
+  // Each pass is launched n times back to back between one event pair.  The
+  // column pass is idempotent when repeated on one parity (it re-folds the
+  // same previous iteration); the line pass advances mu, so the mutable
+  // state is saved first and restored afterwards: the iterate is unchanged.
+  const size_t nl = h->n_lines;
+  const size_t esz = h->opts.precision == DCOPF_PREC_FP32 ? 4 : 8;
+  double *save = nullptr;
+  void *vsave = nullptr;
+  DevScalars *ssave = nullptr;
+  DCOPF_HIP_TRY(hipMalloc(&save, 6 * nl * 8));
+  DCOPF_HIP_TRY(hipMalloc(&vsave, (size_t)h->ldl * esz));
+  DCOPF_HIP_TRY(hipMalloc(&ssave, sizeof(DevScalars)));
+  double *arrs[] = {h->mu_p, h->mu_m, h->v_p, h->v_m, h->s_p, h->s_m};
+  hipStream_t s = h->stream;
+  for (int i = 0; i < 6; ++i)
+    DCOPF_HIP_TRY(hipMemcpyAsync(save + i * nl, arrs[i], nl * 8, hipMemcpyDeviceToDevice, s));
+  DCOPF_HIP_TRY(hipMemcpyAsync(vsave, h->vbuf, (size_t)h->ldl * esz, hipMemcpyDeviceToDevice, s));
+  DCOPF_HIP_TRY(hipMemcpyAsync(ssave, h->sc, sizeof(DevScalars), hipMemcpyDeviceToDevice, s));
+  const int par = (int)(h->iters & 1);
+  hipEvent_t ev[4];
   for (auto &e : ev) DCOPF_HIP_TRY(hipEventCreate(&e));
-  for (int64_t i = 0; i < n; ++i) {
-    for (int phase = 0; phase < 2; ++phase) {
-      DCOPF_HIP_TRY(hipEventRecord(ev[4 * i + 2 * phase], h->stream));
-      launch_phase(h, h->stream, phase);
-      DCOPF_HIP_TRY(hipEventRecord(ev[4 * i + 2 * phase + 1], h->stream));
-    }
+  for (int phase = 0; phase < 2; ++phase) {
+    launch_phase(h, s, phase, par);  // warm
+    DCOPF_HIP_TRY(hipEventRecord(ev[2 * phase], s));
+    for (int64_t i = 0; i < n; ++i) launch_phase(h, s, phase, par);
+    DCOPF_HIP_TRY(hipEventRecord(ev[2 * phase + 1], s));
   }
+  for (int i = 0; i < 6; ++i)
+    DCOPF_HIP_TRY(hipMemcpyAsync(arrs[i], save + i * nl, nl * 8, hipMemcpyDeviceToDevice, s));
+  DCOPF_HIP_TRY(hipMemcpyAsync(h->vbuf, vsave, (size_t)h->ldl * esz, hipMemcpyDeviceToDevice, s));
+  DCOPF_HIP_TRY(hipMemcpyAsync(h->sc, ssave, sizeof(DevScalars), hipMemcpyDeviceToDevice, s));
   DCOPF_HIP_TRY(hipGetLastError());
-  DCOPF_HIP_TRY(hipStreamSynchronize(h->stream));
-  double acc[2] = {0.0, 0.0};
-  for (int64_t i = 0; i < n; ++i)
-    for (int phase = 0; phase < 2; ++phase) {
-      float ms = 0.f;
-      DCOPF_HIP_TRY(hipEventElapsedTime(&ms, ev[4 * i + 2 * phase], ev[4 * i + 2 * phase + 1]));
-      acc[phase] += ms;
-    }
+  DCOPF_HIP_TRY(hipStreamSynchronize(s));
+  for (int phase = 0; phase < 2; ++phase) {
+    float ms = 0.f;
+    DCOPF_HIP_TRY(hipEventElapsedTime(&ms, ev[2 * phase], ev[2 * phase + 1]));
+    ms_out[phase] = ms / n;
+  }
   for (auto &e : ev) (void)hipEventDestroy(e);
-  ms_out[0] = acc[0] / n;
-  ms_out[1] = acc[1] / n;
-  h->iters += n;
+  (void)hipFree(save);
+  (void)hipFree(vsave);
+  (void)hipFree(ssave);
   return DCOPF_OK;
 }
 
