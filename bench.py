@@ -47,7 +47,7 @@ def cpu_baseline(p, alpha, rho, budget_s=15.0):
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     return dict(value=n / dt, unit="instance-iterations/s", cores=int(threads),
                 kind="oracle",
-                sample=f"{n} FP64 GDM iterations of the same 2000-bus instance "
+                sample=f"{n} FP64 GDM iterations of the same {p.n_bus}-bus instance "
                        f"(numpy, {threads} BLAS threads), {dt:.1f} s")
 
 
@@ -110,6 +110,71 @@ def bench_mixed(args, stream):
         shapes=shapes, tiles=tiles)
 
 
+def _highs_opt(args):
+    from oracle import ref
+    net, prob = args
+    o = ref.opt_btheta(net, prob)
+    return float("nan") if o["opt"] is None else o["opt"]
+
+
+def bench_warmstart(args, stream):
+    """Learned warm start on the 2000-bus network: training scenarios with
+    per-bus load multipliers exp(N(0, 0.15^2)), targets from cold batched
+    solves, training with the library's kernels, evaluation on held-out
+    scenarios against HiGHS optima (reference leg) with the cold fallback."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import torch
+
+    from oracle import mlp as R  # He initialisation of the weights only
+    from paper_2406_13191_amd import _abi, synth
+    from paper_2406_13191_amd import warmstart as W
+    log = lambda m: print("[warm]", m, file=sys.stderr, flush=True)  # noqa: E731
+    net, base = synth.make_network("bus2000", 2000)
+    r = synth.STEP_RULES["bus2000"]
+    Dtr, _, _ = synth.make_scenarios(base, 5_000_000, args.train, 0.15, 0.0)
+    Dev, _, _ = synth.make_scenarios(base, 6_000_000, args.eval, 0.15, 0.0)
+    (T, tb), t_data = W.timed(W.cold_solve, base, Dtr, args.target_iters, r["alpha"], r["rho"],
+                              stream.cuda_stream)
+    cost_ub = float(np.sum(np.maximum(base.c * base.p_min, base.c * base.p_max)))
+    ok = np.isfinite(tb) & (tb <= cost_ub) & np.all(np.isfinite(T), axis=1)
+    log(f"targets: {ok.sum()} of {ok.size} scenarios kept, {t_data:.1f} s")
+    Dtr, T = Dtr[ok], T[ok]
+    sx, st = W.Standardizer.fit(Dtr), W.Standardizer.fit(T)
+    X = torch.tensor(sx.apply(Dtr), dtype=torch.float32, device="cuda")
+    Y = torch.tensor(st.apply(T), dtype=torch.float32, device="cuda")
+    dims = (base.n_bus, 1024, 1024, 2 * base.n_line + 1)
+    model = _abi.MLP(*dims, max_batch=256, stream=stream.cuda_stream)
+    model.set_params([p.astype(np.float32) for p in
+                      R.init_params(np.random.default_rng(0), dims)])
+    ms_step = model.time_train(X[:256].data_ptr(), Y[:256].data_ptr(), 256, 20)
+    losses, t_train = W.timed(W.train, model, X, Y, args.epochs, 256, 1e-3, 0, 0.9, log)
+    start = W.predict(model, Dev, sx, st, base.n_line)
+    model.close()
+    with mp.get_context("spawn").Pool(16) as pool:
+        opt = np.array(pool.map(_highs_opt, [(net, base.replace(d=Dev[i]))
+                                             for i in range(Dev.shape[0])]))
+    keep = np.isfinite(opt)
+    Dev, opt = Dev[keep], opt[keep]
+    start = tuple(a[keep] for a in start)
+    (hc, pc), t_cold = W.timed(W.run_to_gap, base, Dev, opt, r["alpha"], r["rho"], None,
+                               args.max_iters, 10, 100, stream.cuda_stream)
+    (hw, pw), t_warm = W.timed(W.run_to_gap, base, Dev, opt, r["alpha"], r["rho"], start,
+                               args.max_iters, 10, 100, stream.cuda_stream)
+    hf, used = W.combine_with_fallback(hc, pc, hw, pw, 100)
+    flops = 6.0 * 256 * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
+    return dict(
+        n_train=int(ok.sum()), n_eval=int(keep.sum()), data_seconds=t_data,
+        train_seconds=t_train, epochs=args.epochs, final_loss=losses[-1], first_loss=losses[0],
+        train_step_ms=ms_step, train_tflops=flops / (ms_step * 1e-3) / 1e12,
+        median_iters_cold=W.median_iters(hc, args.max_iters),
+        median_iters_warm=W.median_iters(hw, args.max_iters),
+        median_iters_warm_fallback=W.median_iters(hf, args.max_iters),
+        reached_cold=float((hc >= 0).mean()), reached_warm_fallback=float((hf >= 0).mean()),
+        warm_kept=float(used.mean()), solve_seconds_cold=t_cold, solve_seconds_warm=t_warm)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +182,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="bus2000")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--panel", default="genbus", choices=["genbus", "allbus"])
+    ap.add_argument("--train", type=int, default=50000)
+    ap.add_argument("--eval", type=int, default=4096)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--target-iters", type=int, default=5000)
+    ap.add_argument("--max-iters", type=int, default=5000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the single-instance path does not shard "
@@ -130,6 +201,22 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.workload == "warmstart":
+        r = bench_warmstart(args, stream)
+        out = {
+            "metric": "median iterations to a bound within 0.1% of the FP64 optimum, "
+                      "learned warm start vs cold start",
+            "value": r["median_iters_warm_fallback"], "unit": "iterations",
+            "n_gpus": 1, "steps": args.max_iters, "warmup": 0, "ms_per_step": None,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": f"warm start on the 2000-bus network: MLP 2000-1024-1024-6401 "
+                                   f"trained on {r['n_train']} cold-solve duals, evaluated on "
+                                   f"{r['n_eval']} held-out scenarios", **r},
+            "roofline": None, "cpu_baseline": None,
+        }
+        print(json.dumps(out), flush=True)
+        return
     if args.workload == "mixed":
         r = bench_mixed(args, stream)
         out = {
@@ -149,8 +236,10 @@ def main():
                                                 "bus10000": 10000}[args.workload])
     r = synth.STEP_RULES[args.workload]
     n_cols = len(np.unique(p.gen_bus))
-    kw = dict(rule="gdm", alpha=r["alpha"], rho=r["rho"], precision="fp32", panel="genbus",
+    kw = dict(rule="gdm", alpha=r["alpha"], rho=r["rho"], precision="fp32", panel=args.panel,
               graph_iters=100)
+    if args.panel == "allbus":
+        n_cols = p.n_bus
     s = _abi.DualSolver(p, stream=stream.cuda_stream, **kw)
     s.step(args.warmup)
     torch.cuda.synchronize()
@@ -166,7 +255,7 @@ def main():
     value = args.steps / (ms / 1e3)
     print(f"[bench] {args.steps} iterations in {ms:.2f} ms (wall {wall*1e3:.2f} ms)",
           file=sys.stderr, flush=True)
-    # per-kernel durations (HIP events around each launch) for the roofline
+    # per-kernel durations (back-to-back launches between HIP events) for the roofline
     ms_col, ms_line = s.time_phases(200)
     s.close()
     b_col, b_line = panel_bytes(p.n_line, n_cols, p.n_gen)
@@ -185,13 +274,13 @@ def main():
     cpu = None
     if not args.no_cpu:
         from oracle import ref
-        opt = ref.opt_btheta(net, p)["opt"]
+        opt = ref.opt_btheta(net, p)["opt"] if not p.is_qp else float("nan")
         with _abi.DualSolver(p, stream=stream.cuda_stream, **kw) as s2:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             res = s2.solve(opt=opt, gap_tol=1e-3, max_iters=args.steps, check_every=100)
             dt = time.perf_counter() - t0
-        ttb = dict(reached=res["status"] == 1, iterations=int(res["iter_of_bound"]),
+        ttb = None if p.is_qp else dict(reached=res["status"] == 1, iterations=int(res["iter_of_bound"]),
                    seconds=round(dt, 5), gap=res["gap"], check_every=100,
                    device_seconds=round(res["iter_of_bound"] * ms / args.steps / 1e3, 6))
         cpu = cpu_baseline(p, r["alpha"], r["rho"])
@@ -203,7 +292,9 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload} single instance: {p.n_bus} buses, "
                                f"{p.n_line} lines, {p.n_gen} generators on {n_cols} buses, "
-                               f"{'quadratic' if p.is_qp else 'linear'} costs; FP32 PTDF "
+                               f"{'quadratic' if p.is_qp else 'linear'} costs; "
+                               f"{'full-PTDF' if args.panel == 'allbus' else 'generator-bus'} "
+                               f"panel; FP32 PTDF "
                                f"products, FP64 multipliers and bound; gradient with "
                                f"momentum alpha={r['alpha']}, rho={r['rho']}",
                    "iterations": args.steps, "time_to_bound": ttb},

@@ -43,7 +43,8 @@ typedef struct {
   const double *p_min;    /* [n_gen] shared by the instances                 */
   const double *p_max;    /* [n_gen]                                         */
   const double *f_max;    /* [n_line] symmetric limits, > 0                  */
-  int32_t n_inst;         /* instances on this network, >= 1                 */
+  int32_t n_inst;         /* instances on this network, >= 1; n_inst times
+                             n_line (both padded) stays below 2^30           */
   const double *d;        /* [n_inst * n_bus] load of each instance          */
   const double *c;        /* [n_inst * n_gen] linear cost of each instance   */
   const double *q;        /* [n_inst * n_gen] quadratic cost (>= 0) or NULL  */
@@ -106,14 +107,16 @@ dcopf_status dcopf_batch_get_multipliers(dcopf_batch_t b, int32_t net, double *l
 dcopf_status dcopf_batch_set_multipliers(dcopf_batch_t b, int32_t net, const double *lambda,
                                          const double *mu_plus, const double *mu_minus);
 
-/* Tile shapes in use for network `net`: cfg[0..3] = workgroup arrangement
- * of the W product (waves along instances, along columns), its K split,
- * and the arrangement code of the F product.                               */
+/* Tile shapes in use for network `net`: cfg[0], cfg[1] = instances x
+ * columns of one W-product workgroup tile, cfg[2] = its K split,
+ * cfg[3] = instances * 1000 + lines of one F-product tile.                 */
 dcopf_status dcopf_batch_info(dcopf_batch_t b, int32_t net, int32_t *cfg, int64_t *iters);
 
-/* Measurement: run n_iters >= 1 iterations with an event pair around each
- * launch; ms_out[0..2] = average ms of the W product, the unit pass (inner
- * minimiser and lambda step) and the F product with the mu step.          */
+/* Measurement: run n_iters >= 1 real iterations (they advance the batch)
+ * with events attached to each dispatch (start and end of that kernel
+ * alone); ms_out[0..2] = average ms of the W product, the unit pass (inner
+ * minimiser, lambda step of the previous iteration) and the F product with
+ * the mu step.  Synchronises.                                              */
 dcopf_status dcopf_batch_time_phases(dcopf_batch_t b, int64_t n_iters, double *ms_out);
 
 void dcopf_batch_destroy(dcopf_batch_t b);   /* NULL is a no-op              */

@@ -174,11 +174,12 @@ size_t dcopf_dual_state_len(dcopf_dual_t h);
 dcopf_status dcopf_dual_get_state(dcopf_dual_t h, double *buf, size_t len);
 dcopf_status dcopf_dual_set_state(dcopf_dual_t h, const double *buf, size_t len);
 
-/* Measurement: the column pass (w = P^T v and the inner minimiser) and the
- * line pass (F = P x - f_d and the mu step) are each launched n_iters >= 1
- * times back to back between one HIP event pair on the handle's stream;
- * ms_out[0], ms_out[1] receive the average ms per launch.  The iterate and
- * the iteration count are restored afterwards.  Synchronises.              */
+/* Measurement: n_iters >= 1 real iterations from the current iterate (column
+ * pass and line pass alternating as in dcopf_dual_step), each launch with
+ * start/stop events attached to its dispatch (the kernel's own timestamps);
+ * ms_out[0], ms_out[1] receive the average ms of the column pass (w = P^T v
+ * and the inner minimiser) and of the line pass (F = P x - f_d and the mu
+ * step).  The iterate and iteration count are restored.  Synchronises.     */
 dcopf_status dcopf_dual_time_phases(dcopf_dual_t h, int64_t n_iters, double *ms_out);
 
 /* Panel width (number of H columns the products use) and iterations done. */

@@ -55,6 +55,14 @@ def _load():
         raise ImportError(
             f"{LIB_PATH} is missing: build the HIP library first "
             "(python -m paper_2406_13191_amd.build)")
+    # PyTorch ships its own HIP runtime under the same soname as ROCm's.  Load
+    # it first (when installed) so that this library binds to the same
+    # runtime and stream handles from torch are valid here; loading ours first
+    # would leave torch with a second, conflicting runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     P = C.POINTER
     sig = {
@@ -373,10 +381,121 @@ class BatchSolver:
         it = C.c_int64()
         check(lib.dcopf_batch_info(self._h, int(net), cfg.ctypes.data_as(C.POINTER(C.c_int32)),
                                    C.byref(it)))
-        return dict(w_arrangement=(int(cfg[0]), int(cfg[1])), w_split=int(cfg[2]),
-                    f_arrangement=(int(cfg[3]) // 10, int(cfg[3]) % 10), iters=it.value)
+        return dict(w_tile=(int(cfg[0]), int(cfg[1])), w_split=int(cfg[2]),
+                    f_tile=(int(cfg[3]) // 1000, int(cfg[3]) % 1000), iters=it.value)
 
     def time_phases(self, n: int):
         ms = np.zeros(3)
         check(lib.dcopf_batch_time_phases(self._h, int(n), _dptr(ms)))
         return tuple(float(v) for v in ms)
+
+
+# ---------------------------------------------------------------------------
+# Warm-start network (dcopf_mlp.h)
+# ---------------------------------------------------------------------------
+class MlpConfig_C(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("h1", C.c_int32), ("h2", C.c_int32),
+                ("n_out", C.c_int32), ("max_batch", C.c_int32), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double)]
+
+
+def _bind_mlp():
+    P = C.POINTER
+    sig = {
+        "dcopf_mlp_create": (C.c_int, [P(MlpConfig_C), C.c_void_p, P(C.c_void_p)]),
+        "dcopf_mlp_param_count": (C.c_size_t, [C.c_void_p]),
+        "dcopf_mlp_get_params": (C.c_int, [C.c_void_p, P(C.c_float), C.c_size_t]),
+        "dcopf_mlp_set_params": (C.c_int, [C.c_void_p, P(C.c_float), C.c_size_t]),
+        "dcopf_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+        "dcopf_mlp_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                           C.c_double, P(C.c_double)]),
+        "dcopf_mlp_get_grads": (C.c_int, [C.c_void_p, P(C.c_float), C.c_size_t]),
+        "dcopf_mlp_time_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                           C.c_int32, P(C.c_double)]),
+        "dcopf_mlp_destroy": (None, [C.c_void_p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+
+
+_bind_mlp()
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class MLP:
+    """Warm-start network on the GPU.  Data arguments of forward/train_step
+    are device addresses (ints, e.g. torch_tensor.data_ptr()) of contiguous
+    FP32 arrays."""
+
+    def __init__(self, n_in, h1, h2, n_out, max_batch=256, beta1=0.9, beta2=0.999, eps=1e-8,
+                 stream=None):
+        self.dims = (n_in, h1, h2, n_out)
+        cfg = MlpConfig_C(n_in, h1, h2, n_out, max_batch, beta1, beta2, eps)
+        h = C.c_void_p()
+        check(lib.dcopf_mlp_create(C.byref(cfg), C.c_void_p(stream or 0), C.byref(h)))
+        self._h = h
+        self.n_params = int(lib.dcopf_mlp_param_count(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.dcopf_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def shapes(self):
+        n_in, h1, h2, n_out = self.dims
+        return [(h1, n_in), (h1,), (h2, h1), (h2,), (n_out, h2), (n_out,)]
+
+    def pack(self, params):
+        return np.ascontiguousarray(np.concatenate([np.asarray(p, np.float32).ravel()
+                                                    for p in params]))
+
+    def unpack(self, flat):
+        out, o = [], 0
+        for s in self.shapes():
+            n = int(np.prod(s))
+            out.append(flat[o:o + n].reshape(s))
+            o += n
+        return out
+
+    def set_params(self, params):
+        flat = self.pack(params)
+        check(lib.dcopf_mlp_set_params(self._h, _fptr(flat), flat.size))
+
+    def get_params(self):
+        flat = np.empty(self.n_params, np.float32)
+        check(lib.dcopf_mlp_get_params(self._h, _fptr(flat), flat.size))
+        return self.unpack(flat)
+
+    def get_grads(self):
+        flat = np.empty(self.n_params, np.float32)
+        check(lib.dcopf_mlp_get_grads(self._h, _fptr(flat), flat.size))
+        return self.unpack(flat)
+
+    def forward(self, x_ptr: int, batch: int, y_ptr: int):
+        check(lib.dcopf_mlp_forward(self._h, C.c_void_p(x_ptr), int(batch), C.c_void_p(y_ptr)))
+
+    def train_step(self, x_ptr: int, t_ptr: int, batch: int, lr: float, want_loss=False):
+        loss = C.c_double()
+        check(lib.dcopf_mlp_train_step(self._h, C.c_void_p(x_ptr), C.c_void_p(t_ptr), int(batch),
+                                       float(lr), C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def time_train(self, x_ptr: int, t_ptr: int, batch: int, n: int) -> float:
+        ms = C.c_double()
+        check(lib.dcopf_mlp_time_train(self._h, C.c_void_p(x_ptr), C.c_void_p(t_ptr),
+                                       int(batch), int(n), C.byref(ms)))
+        return ms.value

@@ -42,7 +42,7 @@ namespace {
 
 struct BNet {
   int n_l, n_c, n_g, B, Bp, ldl, ldc, ncp, nlp, S, kchunk, inst0, ntl;
-  int wm_w, wn_w, wm_f, wn_f;
+  int cfg_w, cfg_f;  // workgroup tile shape codes of the W and F products
   double alpha, rho;
   const __bf16 *PT_hi, *PT_lo, *P_hi, *P_lo;
   const double *P64T;
@@ -54,8 +54,12 @@ struct BNet {
   const double *flim64, *fd64;                  // [n_l], [B][n_l]
   const double *c, *q;                          // [B][n_g]
   const double *pmin, *pmax;                    // [n_g]
-  const int *seg, *gperm;
-  double *lam, *vlam, *slam, *D, *genpart;      // [B]
+  const int *seg;                               // units of column j: seg[j] .. seg[j+1]-1
+                                                // (unit data stored column-sorted)
+  double *lam, *vlam, *slam;                    // [2][B]: state used by the iteration of that parity
+  double *D;                                    // [B]
+  int ncb;                                      // column blocks of 256 in the unit pass
+  double *unitpart;                             // [2][ncb][Bp][2]: sum p*, sum phi by parity
   double *linepart;                             // [ntl][Bp]
   double *V64, *W64;                            // [Bp][ldl], [Bp][ncp]
   double *bound;                                // [B]
@@ -95,129 +99,258 @@ __device__ __forceinline__ int mfma32_row(int j, int lane) {
   return 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
 }
 
-// acc += (A_hi + A_lo)(B_hi + B_lo) over k in [kb, ke) (a multiple of 64):
-// four 16-deep steps per trip, all fragments loaded before the products.
-template <bool LOLO>
-__device__ __forceinline__ void split_mma(const __bf16 *__restrict__ ah,
-                                          const __bf16 *__restrict__ al,
-                                          const __bf16 *__restrict__ bh,
-                                          const __bf16 *__restrict__ bl, int kb, int ke,
-                                          f32x16 &acc) {
-  for (int k = kb; k < ke; k += 64) {
-    bf16x8 a0[4], a1[4], b0[4], b1[4];
+// ---------------------------------------------------------------------------
+// Workgroup tile of a split-BF16 product, staged through LDS.
+//
+// C[BM x BN] += (A_hi + A_lo)[BM x K] (B_hi + B_lo)[BN x K]^T over k in
+// [kb, ke) (a multiple of 64).  256 threads = WM x WN wavefronts, each owning
+// TM x TN tiles of 32 x 32 (v_mfma_f32_32x32x16_bf16).  Per 64-deep K step the
+// four operand tiles are copied to LDS (8 threads per 128-byte row), the next
+// step's global loads are issued into registers before the products, and the
+// fragments are read from LDS with a 144-byte row stride (16-byte reads of 16
+// consecutive rows hit disjoint banks).
+// ---------------------------------------------------------------------------
+constexpr int kBK = 64;
+constexpr int kLdsStride = kBK + 8;  // bf16 elements per LDS row
+
+template <int BM, int BN> struct TileLds {
+  __bf16 a[2][BM][kLdsStride];
+  __bf16 b[2][BN][kLdsStride];
+};
+
+template <int BM, int BN, int WM, int WN, bool LOLO>
+__device__ __forceinline__ void tile_mma(const __bf16 *__restrict__ Ah,
+                                         const __bf16 *__restrict__ Al, int lda,
+                                         const __bf16 *__restrict__ Bh,
+                                         const __bf16 *__restrict__ Bl, int ldb, int kb, int ke,
+                                         TileLds<BM, BN> &sm,
+                                         f32x16 (&acc)[BM / (WM * 32)][BN / (WN * 32)]) {
+  constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
+  constexpr int RA = BM / 32, RB = BN / 32;  // 32-row groups per operand tile
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int lrow = t >> 3, lchunk = (t & 7) * 8;
+  bf16x8 pa[2][RA], pb[2][RB];
+  auto fetch = [&](int k) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a0[u] = *reinterpret_cast<const bf16x8 *>(ah + k + 16 * u);
-      a1[u] = *reinterpret_cast<const bf16x8 *>(al + k + 16 * u);
-      b0[u] = *reinterpret_cast<const bf16x8 *>(bh + k + 16 * u);
-      b1[u] = *reinterpret_cast<const bf16x8 *>(bl + k + 16 * u);
+    for (int r = 0; r < RA; ++r) {
+      const size_t off = (size_t)(r * 32 + lrow) * lda + k + lchunk;
+      pa[0][r] = *reinterpret_cast<const bf16x8 *>(Ah + off);
+      pa[1][r] = *reinterpret_cast<const bf16x8 *>(Al + off);
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[u], b0[u], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[u], b1[u], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[u], b0[u], acc, 0, 0, 0);
-      if (LOLO) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[u], b1[u], acc, 0, 0, 0);
+    for (int r = 0; r < RB; ++r) {
+      const size_t off = (size_t)(r * 32 + lrow) * ldb + k + lchunk;
+      pb[0][r] = *reinterpret_cast<const bf16x8 *>(Bh + off);
+      pb[1][r] = *reinterpret_cast<const bf16x8 *>(Bl + off);
+    }
+  };
+  if (kb < ke) fetch(kb);
+  const int fr = lane & 31, fk = (lane >> 5) * 8;
+  for (int k = kb; k < ke; k += kBK) {
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int r = 0; r < RA; ++r)
+        *reinterpret_cast<bf16x8 *>(&sm.a[h][r * 32 + lrow][lchunk]) = pa[h][r];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+        *reinterpret_cast<bf16x8 *>(&sm.b[h][r * 32 + lrow][lchunk]) = pb[h][r];
+    }
+    __syncthreads();
+    if (k + kBK < ke) fetch(k + kBK);
+#pragma unroll
+    for (int kk = 0; kk < kBK; kk += 16) {
+      bf16x8 fa[2][TM], fb[2][TN];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          fa[h][i] = *reinterpret_cast<const bf16x8 *>(
+              &sm.a[h][(wm * TM + i) * 32 + fr][kk + fk]);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          fb[h][j] = *reinterpret_cast<const bf16x8 *>(
+              &sm.b[h][(wn * TN + j) * 32 + fr][kk + fk]);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0][i], fb[0][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0][i], fb[1][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1][i], fb[0][j], acc[i][j], 0, 0, 0);
+          if (LOLO)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1][i], fb[1][j], acc[i][j], 0, 0, 0);
+        }
     }
   }
 }
 
+// Workgroup tile shapes (code stored per network): BM x BN and wave layout.
+//   0: 128 x 64 (2 x 2 waves, 64 x 32 each)   1: 64 x 128 (2 x 2, 32 x 64)
+//   2: 32 x 128 (1 x 4, 32 x 32)
+#define DCOPF_TILE_SWITCH(code, BODY)                                                      \
+  switch (code) {                                                                         \
+    case 0: { BODY(128, 64, 2, 2); } break;                                               \
+    case 1: { BODY(64, 128, 2, 2); } break;                                               \
+    default: { BODY(32, 128, 1, 4); } break;                                              \
+  }
+
+constexpr int kTileBM[3] = {128, 64, 32};
+constexpr int kTileBN[3] = {64, 128, 128};
+// one LDS buffer serves every shape (the largest is 128 + 64 rows)
+constexpr int kTileLdsBytes = (int)sizeof(TileLds<128, 64>);
+static_assert(sizeof(TileLds<64, 128>) <= (size_t)kTileLdsBytes, "LDS");
+static_assert(sizeof(TileLds<32, 128>) <= (size_t)kTileLdsBytes, "LDS");
+
 // ---------------------------------------------------------------------------
 // W product: Wws[s][i][j] = sum_{l in split s} V[i][l] P[l][j]
 // ---------------------------------------------------------------------------
+template <int BM, int BN, int WM, int WN, bool LOLO>
+__device__ __forceinline__ void wgemm_body(const BNet &N, int4 t, unsigned char *lds) {
+  constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
+  TileLds<BM, BN> &sm = *reinterpret_cast<TileLds<BM, BN> *>(lds);
+  const int m0 = t.y * BM, n0 = t.z * BN;
+  const int kb = t.w * N.kchunk, ke = min(N.ldl, kb + N.kchunk);
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  tile_mma<BM, BN, WM, WN, LOLO>(N.V_hi + (size_t)m0 * N.ldl, N.V_lo + (size_t)m0 * N.ldl,
+                                 N.ldl, N.PT_hi + (size_t)n0 * N.ldl,
+                                 N.PT_lo + (size_t)n0 * N.ldl, N.ldl, kb, ke, sm, acc);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int mb = m0 + (wm * TM + i) * 32, n = n0 + (wn * TN + j) * 32 + (lane & 31);
+      float *out = N.Wws + ((size_t)t.w * N.Bp + mb) * N.ncp + n;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) out[(size_t)mfma32_row(e, lane) * N.ncp] = acc[i][j][e];
+    }
+}
+
 template <bool LOLO>
 __global__ __launch_bounds__(256) void wgemm_kernel(const BNet *__restrict__ nets,
                                                     const int4 *__restrict__ tiles) {
+  __shared__ __align__(16) unsigned char lds[kTileLdsBytes];
   const int4 t = tiles[blockIdx.x];
   const BNet &N = nets[t.x];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int mt = t.y + wave / N.wn_w, nt = t.z + wave % N.wn_w;
-  if (mt * 32 >= N.Bp || nt * 32 >= N.ncp) return;  // whole wavefront
-  const int kb = t.w * N.kchunk, ke = min(N.ldl, kb + N.kchunk);
-  const int r = lane & 31, koff = (lane >> 5) * 8;
-  const size_t arow = (size_t)(mt * 32 + r) * N.ldl + koff;
-  const size_t brow = (size_t)(nt * 32 + r) * N.ldl + koff;
-  const __bf16 *ah = N.V_hi + arow, *al = N.V_lo + arow;
-  const __bf16 *bh = N.PT_hi + brow, *bl = N.PT_lo + brow;
-  f32x16 acc;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) acc[j] = 0.f;
-  split_mma<LOLO>(ah, al, bh, bl, kb, ke, acc);
-  float *out = N.Wws + ((size_t)t.w * N.Bp + mt * 32) * N.ncp + nt * 32 + r;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) out[(size_t)mfma32_row(j, lane) * N.ncp] = acc[j];
+#define DCOPF_WBODY(BM, BN, WM, WN) wgemm_body<BM, BN, WM, WN, LOLO>(N, t, lds)
+  DCOPF_TILE_SWITCH(N.cfg_w, DCOPF_WBODY)
+#undef DCOPF_WBODY
 }
 
-// gamma of the iteration before `it`: gen part minus the line terms.
-__device__ __forceinline__ void finish_gamma(const BNet &N, int i, long long k_prev,
-                                             double *gam_ring, long long gmask, int n_total,
-                                             double *red) {
-  double s = 0.0;
-  for (int t = threadIdx.x; t < N.ntl; t += blockDim.x) s += N.linepart[(size_t)t * N.Bp + i];
-  s = block_sum(s, red);
-  if (threadIdx.x == 0)
-    gam_ring[(size_t)(k_prev & gmask) * n_total + N.inst0 + i] = N.genpart[i] - s;
+// Fold iteration k-1 of instance i (every workgroup of the instance does it
+// identically): sum its unit partials (parity pp) and line terms, form its
+// dual value gamma and take the lambda step from its state slot pp.  Returns
+// the state (lambda, velocity or first moment, second moment) of iteration k.
+struct LamState {
+  double lam, v, s, gamma;
+};
+
+__device__ __forceinline__ LamState fold_inst(const BNet &N, int i, int pp, long long k_prev,
+                                              const BParams &prm, double *red) {
+  double ps = 0.0, phis = 0.0, lines = 0.0;
+  const double *up = N.unitpart + (size_t)pp * N.ncb * N.Bp * 2;
+  for (int t = threadIdx.x; t < N.ncb; t += blockDim.x) {
+    ps += up[((size_t)t * N.Bp + i) * 2];
+    phis += up[((size_t)t * N.Bp + i) * 2 + 1];
+  }
+  for (int t = threadIdx.x; t < N.ntl; t += blockDim.x) lines += N.linepart[(size_t)t * N.Bp + i];
+  ps = block_sum(ps, red);
+  phis = block_sum(phis, red);
+  lines = block_sum(lines, red);
+  const double lam = N.lam[(size_t)pp * N.B + i];
+  const double v0 = N.vlam[(size_t)pp * N.B + i], s0 = N.slam[(size_t)pp * N.B + i];
+  const double D = N.D[i];
+  LamState r;
+  r.gamma = phis + lam * D - lines;
+  const double kk = (double)k_prev;
+  const double a = N.alpha / (1.0 + prm.decay * kk);
+  const double g = D - ps;  // balance residual
+  r.v = v0;
+  r.s = s0;
+  if (prm.rule == DCOPF_RULE_GDM) {
+    r.v = N.rho * v0 + a * g;
+    r.lam = lam + r.v + (prm.literal ? a * g : 0.0);
+  } else if (prm.rule == DCOPF_RULE_ADAM) {
+    const double c1 = 1.0 - pow(prm.beta1, kk + 1.0), c2 = 1.0 - pow(prm.beta2, kk + 1.0);
+    r.v = prm.beta1 * v0 + (1.0 - prm.beta1) * g;
+    r.s = prm.beta2 * s0 + (1.0 - prm.beta2) * g * g;
+    r.lam = lam + a * (r.v / c1) / (sqrt(r.s / c2) + prm.eps);
+  } else {
+    r.s = s0 + g * g;
+    r.lam = lam + a * g / (sqrt(r.s) + prm.eps);
+  }
+  return r;
 }
 
 // ---------------------------------------------------------------------------
-// Unit pass: one workgroup per instance.
+// Unit pass: workgroup (instance i, column block cb) handles columns
+// cb*256 .. cb*256+255, one per thread.  It first folds the previous
+// iteration (every workgroup of the instance identically, so lambda needs no
+// extra launch); workgroup cb = 0 records that instance's lambda state and
+// gamma.  Then w = sum of the K splits, reduced costs, the inner minimiser,
+// the column injections X (BF16 hi/lo), and per-workgroup sums of p* and phi.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ nets,
-                                                    const int2 *__restrict__ inst_tab,
+                                                    const int4 *__restrict__ unit_tab,
                                                     BScal *sc, int par, BParams prm,
                                                     double *__restrict__ gam_ring,
                                                     long long gmask, int n_total) {
   __shared__ double red[4];
-  const int2 e = inst_tab[blockIdx.x];
+  __shared__ double lam_s;
+  const int4 e = unit_tab[blockIdx.x];
   const BNet &N = nets[e.x];
-  const int i = e.y;
+  const int i = e.y, cb = e.z;
   const BIter it = sc->it[par];
-  if (it.pending) finish_gamma(N, i, it.k - 1, gam_ring, gmask, n_total, red);
-  const double lam = N.lam[i];
-  const double *ci = N.c + (size_t)i * N.n_g, *qi = N.q + (size_t)i * N.n_g;
-  double psum = 0.0, phis = 0.0;
-  for (int j = threadIdx.x; j < N.n_c; j += blockDim.x) {
+  if (it.pending) {
+    const LamState r = fold_inst(N, i, par ^ 1, it.k - 1, prm, red);
+    if (threadIdx.x == 0) {
+      lam_s = r.lam;
+      if (cb == 0) {
+        N.lam[(size_t)par * N.B + i] = r.lam;
+        N.vlam[(size_t)par * N.B + i] = r.v;
+        N.slam[(size_t)par * N.B + i] = r.s;
+        gam_ring[(size_t)((it.k - 1) & gmask) * n_total + N.inst0 + i] = r.gamma;
+      }
+    }
+  } else if (threadIdx.x == 0) {
+    lam_s = N.lam[(size_t)par * N.B + i];
+  }
+  __syncthreads();
+  const double lam = lam_s;
+  const int j = cb * 256 + threadIdx.x;
+  double x = 0.0, ph = 0.0;
+  if (j < N.n_c) {
     double w = 0.0;
-    for (int s = 0; s < N.S; ++s) w += (double)N.Wws[((size_t)s * N.Bp + i) * N.ncp + j];
-    double x = 0.0, ph = 0.0;
+    for (int s2 = 0; s2 < N.S; ++s2) w += (double)N.Wws[((size_t)s2 * N.Bp + i) * N.ncp + j];
+    const double *ci = N.c + (size_t)i * N.n_g, *qi = N.q + (size_t)i * N.n_g;
     for (int u = N.seg[j]; u < N.seg[j + 1]; ++u) {
-      const int g = N.gperm[u];
-      const double r = ci[g] - lam + w;
-      const double p = inner_min_b(r, qi[g], N.pmin[g], N.pmax[g]);
-      ph += r * p + qi[g] * p * p;
+      const double r = ci[u] - lam + w;
+      const double p = inner_min_b(r, qi[u], N.pmin[u], N.pmax[u]);
+      ph += r * p + qi[u] * p * p;
       x += p;
     }
     __bf16 hi, lo;
     split_bf16((float)x, &hi, &lo);
     N.X_hi[(size_t)i * N.ldc + j] = hi;
     N.X_lo[(size_t)i * N.ldc + j] = lo;
-    psum += x;
-    phis += ph;
   }
-  psum = block_sum(psum, red);
-  phis = block_sum(phis, red);
+  const double ps = block_sum(x, red);
+  const double phs = block_sum(ph, red);
   if (threadIdx.x == 0) {
-    const double D = N.D[i];
-    N.genpart[i] = phis + lam * D;
-    const double kk = (double)it.k;
-    const double a = N.alpha / (1.0 + prm.decay * kk);
-    const double g = D - psum;  // balance residual
-    if (prm.rule == DCOPF_RULE_GDM) {
-      const double v = N.rho * N.vlam[i] + a * g;
-      N.vlam[i] = v;
-      N.lam[i] = lam + v + (prm.literal ? a * g : 0.0);
-    } else if (prm.rule == DCOPF_RULE_ADAM) {
-      const double c1 = 1.0 - pow(prm.beta1, kk + 1.0), c2 = 1.0 - pow(prm.beta2, kk + 1.0);
-      const double m = prm.beta1 * N.vlam[i] + (1.0 - prm.beta1) * g;
-      const double s = prm.beta2 * N.slam[i] + (1.0 - prm.beta2) * g * g;
-      N.vlam[i] = m;
-      N.slam[i] = s;
-      N.lam[i] = lam + a * (m / c1) / (sqrt(s / c2) + prm.eps);
-    } else {
-      const double s = N.slam[i] + g * g;
-      N.slam[i] = s;
-      N.lam[i] = lam + a * g / (sqrt(s) + prm.eps);
-    }
+    double *up = N.unitpart + (size_t)par * N.ncb * N.Bp * 2 + ((size_t)cb * N.Bp + i) * 2;
+    up[0] = ps;
+    up[1] = phs;
     if (blockIdx.x == 0) {
       BIter nx;
       nx.k = it.k + 1;
@@ -231,24 +364,33 @@ __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ net
 // ---------------------------------------------------------------------------
 // F product with the line update in its epilogue.
 // ---------------------------------------------------------------------------
-template <bool LOLO>
-__global__ __launch_bounds__(256) void fgemm_kernel(const BNet *__restrict__ nets,
-                                                    const int4 *__restrict__ tiles,
-                                                    const BScal *sc, int par, BParams prm) {
-  const int4 t = tiles[blockIdx.x];
-  const BNet &N = nets[t.x];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int mt = t.y + wave / N.wn_f, nt = t.z + wave % N.wn_f;
-  if (mt * 32 >= N.Bp || nt * 32 >= N.nlp) return;  // whole wavefront
-  const int r = lane & 31, koff = (lane >> 5) * 8;
-  const size_t arow = (size_t)(mt * 32 + r) * N.ldc + koff;
-  const size_t brow = (size_t)(nt * 32 + r) * N.ldc + koff;
-  const __bf16 *ah = N.X_hi + arow, *al = N.X_lo + arow;
-  const __bf16 *bh = N.P_hi + brow, *bl = N.P_lo + brow;
-  f32x16 acc;
+// rows of an accumulator whose state is loaded before any of it is stored
+constexpr int kEpiChunk = 8;
+
+// element at a 32-bit byte offset (per-network state arrays are < 4 GiB)
+template <typename T> __device__ __forceinline__ T &at(T *p, unsigned byte_off) {
+  return *reinterpret_cast<T *>(reinterpret_cast<char *>(p) + byte_off);
+}
+template <typename T> __device__ __forceinline__ const T &at(const T *p, unsigned byte_off) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + byte_off);
+}
+
+template <int BM, int BN, int WM, int WN, bool LOLO>
+__device__ __forceinline__ void fgemm_body(const BNet &N, int4 t, const BScal *sc, int par,
+                                           const BParams &prm, unsigned char *lds) {
+  constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
+  TileLds<BM, BN> &sm = *reinterpret_cast<TileLds<BM, BN> *>(lds);
+  const int m0 = t.y * BM, n0 = t.z * BN;
+  f32x16 acc[TM][TN];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) acc[j] = 0.f;
-  split_mma<LOLO>(ah, al, bh, bl, 0, N.ldc, acc);
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  tile_mma<BM, BN, WM, WN, LOLO>(N.X_hi + (size_t)m0 * N.ldc, N.X_lo + (size_t)m0 * N.ldc,
+                                 N.ldc, N.P_hi + (size_t)n0 * N.ldc,
+                                 N.P_lo + (size_t)n0 * N.ldc, N.ldc, 0, N.ldc, sm, acc);
   const long long k = sc->it[par].k;
   const double kk = (double)k;
   const float a = (float)(N.alpha / (1.0 + prm.decay * kk));
@@ -256,75 +398,145 @@ __global__ __launch_bounds__(256) void fgemm_kernel(const BNet *__restrict__ net
   const float c1 = (float)(1.0 - pow(prm.beta1, kk + 1.0));
   const float c2 = (float)(1.0 - pow(prm.beta2, kk + 1.0));
   const float b1 = (float)prm.beta1, b2 = (float)prm.beta2, eps = (float)prm.eps;
-  const int line = nt * 32 + r;
-  const bool lvalid = line < N.n_l;
-  const float fl = lvalid ? N.flim32[line] : 0.f;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  // restrict-qualified views: the loads of a 16-row chunk are issued before
+  // any of its stores
+  const float *__restrict__ fdp = N.fd32;
+  float *__restrict__ mup = N.mu_p;
+  float *__restrict__ mum = N.mu_m;
+  float *__restrict__ vpp = N.v_p;
+  float *__restrict__ vmp = N.v_m;
+  float *__restrict__ spp = N.s_p;
+  float *__restrict__ smp = N.s_m;
+  __bf16 *__restrict__ vhi = N.V_hi;
+  __bf16 *__restrict__ vlo = N.V_lo;
+  const bool need_v = prm.rule != DCOPF_RULE_ADAGRAD, need_s = prm.rule != DCOPF_RULE_GDM;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int i = mt * 32 + mfma32_row(j, lane);
-    double term = 0.0;
-    if (lvalid && i < N.B) {
-      const size_t idx = (size_t)i * N.ldl + line;
-      const float fd = N.fd32[idx];
-      const float F = acc[j] - fd;
-      const float gp = F - fl, gm = -F - fl;
-      const float mp = N.mu_p[idx], mm = N.mu_m[idx];
-      term = (double)(mp - mm) * (double)fd + (double)(mp + mm) * (double)fl;
-      float np_, nm_;
-      if (prm.rule == DCOPF_RULE_GDM) {
-        const float vp = rho * N.v_p[idx] + a * gp, vm = rho * N.v_m[idx] + a * gm;
-        N.v_p[idx] = vp;
-        N.v_m[idx] = vm;
-        np_ = mp + vp;
-        nm_ = mm + vm;
-        if (prm.literal) {
-          np_ += a * gp;
-          nm_ += a * gm;
-        }
-      } else if (prm.rule == DCOPF_RULE_ADAM) {
-        const float m1 = b1 * N.v_p[idx] + (1.f - b1) * gp;
-        const float m2 = b1 * N.v_m[idx] + (1.f - b1) * gm;
-        const float s1 = b2 * N.s_p[idx] + (1.f - b2) * gp * gp;
-        const float s2 = b2 * N.s_m[idx] + (1.f - b2) * gm * gm;
-        N.v_p[idx] = m1;
-        N.v_m[idx] = m2;
-        N.s_p[idx] = s1;
-        N.s_m[idx] = s2;
-        np_ = mp + a * (m1 / c1) / (sqrtf(s1 / c2) + eps);
-        nm_ = mm + a * (m2 / c1) / (sqrtf(s2 / c2) + eps);
-      } else {
-        const float s1 = N.s_p[idx] + gp * gp, s2 = N.s_m[idx] + gm * gm;
-        N.s_p[idx] = s1;
-        N.s_m[idx] = s2;
-        np_ = mp + a * gp / (sqrtf(s1) + eps);
-        nm_ = mm + a * gm / (sqrtf(s2) + eps);
+  for (int j = 0; j < TN; ++j) {
+    const int nsub = n0 + (wn * TN + j) * 32;  // first line of this 32-line tile
+    const int line = nsub + (lane & 31);
+    const bool lvalid = line < N.n_l;
+    const float fl = lvalid ? N.flim32[line] : 0.f;
+#pragma unroll
+    for (int ii = 0; ii < TM; ++ii) {
+      const int mb = m0 + (wm * TM + ii) * 32;
+#pragma unroll
+      for (int h = 0; h < 16; h += kEpiChunk) {
+      float fd[kEpiChunk], mp[kEpiChunk], mm[kEpiChunk], v1[kEpiChunk], v2[kEpiChunk],
+          s1[kEpiChunk], s2[kEpiChunk];
+#pragma unroll
+      for (int c = 0; c < kEpiChunk; ++c) {
+        const int e = h + c;
+        const int i = mb + mfma32_row(e, lane);
+        const bool ok = lvalid && i < N.B;
+        const unsigned bo = ((unsigned)i * (unsigned)N.ldl + (unsigned)line) * 4u;
+        fd[c] = ok ? at(fdp, bo) : 0.f;
+        mp[c] = ok ? at(mup, bo) : 0.f;
+        mm[c] = ok ? at(mum, bo) : 0.f;
+        v1[c] = ok && need_v ? at(vpp, bo) : 0.f;
+        v2[c] = ok && need_v ? at(vmp, bo) : 0.f;
+        s1[c] = ok && need_s ? at(spp, bo) : 0.f;
+        s2[c] = ok && need_s ? at(smp, bo) : 0.f;
       }
-      np_ = fmaxf(np_, 0.f);
-      nm_ = fmaxf(nm_, 0.f);
-      N.mu_p[idx] = np_;
-      N.mu_m[idx] = nm_;
-      __bf16 hi, lo;
-      split_bf16(np_ - nm_, &hi, &lo);
-      N.V_hi[idx] = hi;
-      N.V_lo[idx] = lo;
-    }
-    // line terms of instance i summed over the 32 lines of this tile
 #pragma unroll
-    for (int off = 16; off > 0; off >>= 1) term += __shfl_xor(term, off, kWave);
-    if (r == 0 && i < N.B) N.linepart[(size_t)nt * N.Bp + i] = term;
+      for (int c = 0; c < kEpiChunk; ++c) {
+        const int e = h + c;
+        const int i = mb + mfma32_row(e, lane);
+        const bool ok = lvalid && i < N.B;
+        const unsigned bo = ((unsigned)i * (unsigned)N.ldl + (unsigned)line) * 4u;
+        const float F = acc[ii][j][e] - fd[c];
+        const float gp = F - fl, gm = -F - fl;
+        double term = (double)(mp[c] - mm[c]) * (double)fd[c] + (double)(mp[c] + mm[c]) * (double)fl;
+        float np_, nm_;
+        if (prm.rule == DCOPF_RULE_GDM) {
+          const float vp = rho * v1[c] + a * gp, vm = rho * v2[c] + a * gm;
+          if (ok) {
+            at(vpp, bo) = vp;
+            at(vmp, bo) = vm;
+          }
+          np_ = mp[c] + vp;
+          nm_ = mm[c] + vm;
+          if (prm.literal) {
+            np_ += a * gp;
+            nm_ += a * gm;
+          }
+        } else if (prm.rule == DCOPF_RULE_ADAM) {
+          const float m1 = b1 * v1[c] + (1.f - b1) * gp;
+          const float m2 = b1 * v2[c] + (1.f - b1) * gm;
+          const float q1 = b2 * s1[c] + (1.f - b2) * gp * gp;
+          const float q2 = b2 * s2[c] + (1.f - b2) * gm * gm;
+          if (ok) {
+            at(vpp, bo) = m1;
+            at(vmp, bo) = m2;
+            at(spp, bo) = q1;
+            at(smp, bo) = q2;
+          }
+          np_ = mp[c] + a * (m1 / c1) / (sqrtf(q1 / c2) + eps);
+          nm_ = mm[c] + a * (m2 / c1) / (sqrtf(q2 / c2) + eps);
+        } else {
+          const float q1 = s1[c] + gp * gp, q2 = s2[c] + gm * gm;
+          if (ok) {
+            at(spp, bo) = q1;
+            at(smp, bo) = q2;
+          }
+          np_ = mp[c] + a * gp / (sqrtf(q1) + eps);
+          nm_ = mm[c] + a * gm / (sqrtf(q2) + eps);
+        }
+        np_ = fmaxf(np_, 0.f);
+        nm_ = fmaxf(nm_, 0.f);
+        if (ok) {
+          at(mup, bo) = np_;
+          at(mum, bo) = nm_;
+          __bf16 hi, lo;
+          split_bf16(np_ - nm_, &hi, &lo);
+          at(vhi, bo >> 1) = hi;
+          at(vlo, bo >> 1) = lo;
+        }
+        // line terms of instance i summed over the 32 lines of this tile
+        if (!ok) term = 0.0;
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) term += __shfl_xor(term, off, kWave);
+        if ((lane & 31) == 0 && i < N.B) N.linepart[(size_t)(nsub / 32) * N.Bp + i] = term;
+      }
+      }
+    }
   }
 }
 
-// Finish gamma of iteration k_prev for every instance (end of a step call).
+template <bool LOLO>
+__global__ __launch_bounds__(256) void fgemm_kernel(const BNet *__restrict__ nets,
+                                                    const int4 *__restrict__ tiles,
+                                                    const BScal *sc, int par, BParams prm) {
+  __shared__ __align__(16) unsigned char lds[kTileLdsBytes];
+  const int4 t = tiles[blockIdx.x];
+  const BNet &N = nets[t.x];
+#define DCOPF_FBODY(BM, BN, WM, WN) fgemm_body<BM, BN, WM, WN, LOLO>(N, t, sc, par, prm, lds)
+  DCOPF_TILE_SWITCH(N.cfg_f, DCOPF_FBODY)
+#undef DCOPF_FBODY
+}
+
+// End of a step call: fold the last iteration (k_prev, parity pp) of every
+// instance into the lambda slot of the next iteration (parity pp ^ 1), which
+// is then no longer pending.
 __global__ __launch_bounds__(256) void bfinal_kernel(const BNet *__restrict__ nets,
                                                      const int2 *__restrict__ inst_tab,
-                                                     BScal *sc, int par, long long k_prev,
-                                                     double *__restrict__ gam_ring,
+                                                     BScal *sc, int pp, long long k_prev,
+                                                     BParams prm, double *__restrict__ gam_ring,
                                                      long long gmask, int n_total) {
   __shared__ double red[4];
   const int2 e = inst_tab[blockIdx.x];
-  finish_gamma(nets[e.x], e.y, k_prev, gam_ring, gmask, n_total, red);
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc->it[par].pending = 0;
+  const BNet &N = nets[e.x];
+  const int i = e.y;
+  const LamState r = fold_inst(N, i, pp, k_prev, prm, red);
+  if (threadIdx.x == 0) {
+    const int np = pp ^ 1;
+    N.lam[(size_t)np * N.B + i] = r.lam;
+    N.vlam[(size_t)np * N.B + i] = r.v;
+    N.slam[(size_t)np * N.B + i] = r.s;
+    gam_ring[(size_t)(k_prev & gmask) * n_total + N.inst0 + i] = r.gamma;
+    if (blockIdx.x == 0) sc->it[np].pending = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -361,19 +573,18 @@ __global__ void make_v64_kernel(const float *mu_p, const float *mu_m, int B, int
 
 // Exact bound of instance i (one workgroup): sum over units of phi with the
 // FP64 w, plus lambda D, minus the FP64 line terms.
-__global__ __launch_bounds__(256) void bound_inst_kernel(BNet N) {
+__global__ __launch_bounds__(256) void bound_inst_kernel(BNet N, int par) {
   __shared__ double red[4];
   const int i = blockIdx.x;
-  const double lam = N.lam[i];
+  const double lam = N.lam[(size_t)par * N.B + i];
   const double *ci = N.c + (size_t)i * N.n_g, *qi = N.q + (size_t)i * N.n_g;
   double phis = 0.0, lines = 0.0;
   for (int j = threadIdx.x; j < N.n_c; j += blockDim.x) {
     const double w = N.W64[(size_t)i * N.ncp + j];
     for (int u = N.seg[j]; u < N.seg[j + 1]; ++u) {
-      const int g = N.gperm[u];
-      const double r = ci[g] - lam + w;
-      const double p = inner_min_b(r, qi[g], N.pmin[g], N.pmax[g]);
-      phis += r * p + qi[g] * p * p;
+      const double r = ci[u] - lam + w;
+      const double p = inner_min_b(r, qi[u], N.pmin[u], N.pmax[u]);
+      phis += r * p + qi[u] * p * p;
     }
   }
   for (int l = threadIdx.x; l < N.n_l; l += blockDim.x) {
@@ -486,8 +697,9 @@ struct dcopf_batch_s {
   hipStream_t stream = nullptr;
   BNet *d_nets = nullptr;
   int4 *d_wtiles = nullptr, *d_ftiles = nullptr;
-  int2 *d_inst = nullptr;
-  int n_wtiles = 0, n_ftiles = 0, n_total = 0;
+  int2 *d_inst = nullptr;   // (network, instance) per instance
+  int4 *d_units = nullptr;  // (network, instance, column block) per unit-pass workgroup
+  int n_wtiles = 0, n_ftiles = 0, n_total = 0, n_units = 0;
   BScal *sc = nullptr;
   double *gam = nullptr;
   long long gcap = 0;
@@ -507,7 +719,7 @@ void free_batch(dcopf_batch_s *b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (auto &n : b->nets)
     for (void *p : n.owned) (void)hipFree(p);
-  void *ptrs[] = {b->d_nets, b->d_wtiles, b->d_ftiles, b->d_inst, b->sc, b->gam};
+  void *ptrs[] = {b->d_nets, b->d_wtiles, b->d_ftiles, b->d_inst, b->d_units, b->sc, b->gam};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete b;
@@ -522,18 +734,22 @@ void build_tables(const std::vector<HostNet> &nets, const std::vector<int> &whic
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     return nets[a].d.kchunk > nets[b].d.kchunk;
   });
+  // tile (m, n) covers rows m BM .. m BM + BM - 1 and columns n BN .. + BN - 1;
+  // the padded extents (multiples of 128) contain every such tile
   for (int k : order) {
     const BNet &N = nets[k].d;
-    const int Mt = N.Bp / 32, Nt = N.ncp / 32;
-    for (int m = 0; m < Mt; m += N.wm_w)
-      for (int n = 0; n < Nt; n += N.wn_w)
+    const int BM = kTileBM[N.cfg_w], BN = kTileBN[N.cfg_w];
+    const int Mt = (N.B + BM - 1) / BM, Nt = (N.n_c + BN - 1) / BN;
+    for (int m = 0; m < Mt; ++m)
+      for (int n = 0; n < Nt; ++n)
         for (int s = 0; s < N.S; ++s) wt->push_back(make_int4(k, m, n, s));
   }
   for (int k : which) {
     const BNet &N = nets[k].d;
-    const int Mt = N.Bp / 32, Nt = N.nlp / 32;
-    for (int m = 0; m < Mt; m += N.wm_f)
-      for (int n = 0; n < Nt; n += N.wn_f) ft->push_back(make_int4(k, m, n, 0));
+    const int BM = kTileBM[N.cfg_f], BN = kTileBN[N.cfg_f];
+    const int Mt = (N.B + BM - 1) / BM, Nt = (N.n_l + BN - 1) / BN;
+    for (int m = 0; m < Mt; ++m)
+      for (int n = 0; n < Nt; ++n) ft->push_back(make_int4(k, m, n, 0));
   }
 }
 
@@ -544,25 +760,26 @@ void set_split(BNet &N, int S) {
   N.S = (N.ldl + N.kchunk - 1) / N.kchunk;
 }
 
-void launch_w(dcopf_batch_s *b, hipStream_t s, const int4 *tiles, int n) {
+// the three passes of one iteration; with events e0/e1 the launch records
+// the dispatch's own start and end
+void launch_w(dcopf_batch_s *b, hipStream_t s, const int4 *tiles, int n,
+              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   if (n == 0) return;
-  if (b->opts.lolo)
-    wgemm_kernel<true><<<n, 256, 0, s>>>(b->d_nets, tiles);
-  else
-    wgemm_kernel<false><<<n, 256, 0, s>>>(b->d_nets, tiles);
+  (void)launch_k(b->opts.lolo ? wgemm_kernel<true> : wgemm_kernel<false>, dim3(n), dim3(256), 0,
+                 s, e0, e1, b->d_nets, tiles);
 }
 
-void launch_u(dcopf_batch_s *b, hipStream_t s, int par) {
-  units_kernel<<<b->n_total, 256, 0, s>>>(b->d_nets, b->d_inst, b->sc, par, b->prm, b->gam,
-                                          b->gcap - 1, b->n_total);
+void launch_u(dcopf_batch_s *b, hipStream_t s, int par, hipEvent_t e0 = nullptr,
+              hipEvent_t e1 = nullptr) {
+  (void)launch_k(units_kernel, dim3(b->n_units), dim3(256), 0, s, e0, e1, b->d_nets, b->d_units,
+                 b->sc, par, b->prm, b->gam, b->gcap - 1, b->n_total);
 }
 
-void launch_f(dcopf_batch_s *b, hipStream_t s, const int4 *tiles, int n, int par) {
+void launch_f(dcopf_batch_s *b, hipStream_t s, const int4 *tiles, int n, int par,
+              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   if (n == 0) return;
-  if (b->opts.lolo)
-    fgemm_kernel<true><<<n, 256, 0, s>>>(b->d_nets, tiles, b->sc, par, b->prm);
-  else
-    fgemm_kernel<false><<<n, 256, 0, s>>>(b->d_nets, tiles, b->sc, par, b->prm);
+  (void)launch_k(b->opts.lolo ? fgemm_kernel<true> : fgemm_kernel<false>, dim3(n), dim3(256), 0,
+                 s, e0, e1, b->d_nets, tiles, b->sc, par, b->prm);
 }
 
 void launch_iters_b(dcopf_batch_s *b, hipStream_t s, long long first, int64_t n) {
@@ -576,8 +793,8 @@ void launch_iters_b(dcopf_batch_s *b, hipStream_t s, long long first, int64_t n)
 
 void launch_final_b(dcopf_batch_s *b, hipStream_t s) {
   if (b->iters <= 0) return;
-  const int par = (int)(b->iters & 1);
-  bfinal_kernel<<<b->n_total, 256, 0, s>>>(b->d_nets, b->d_inst, b->sc, par, b->iters - 1,
+  const int pp = (int)((b->iters - 1) & 1);  // parity of the last iteration
+  bfinal_kernel<<<b->n_total, 256, 0, s>>>(b->d_nets, b->d_inst, b->sc, pp, b->iters - 1, b->prm,
                                            b->gam, b->gcap - 1, b->n_total);
 }
 
@@ -594,9 +811,25 @@ hipError_t reset_state(dcopf_batch_s *b, long long k0, int only = -1) {
       if (e == hipSuccess) e = hipMemsetAsync(a, 0, st, b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(N.V_hi, 0, (size_t)N.Bp * N.ldl * 2, b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(N.V_lo, 0, (size_t)N.Bp * N.ldl * 2, b->stream);
-    double *d8[] = {N.lam, N.vlam, N.slam, N.genpart};
+    double *d8[] = {N.lam, N.vlam, N.slam};
     for (double *a : d8)
-      if (e == hipSuccess) e = hipMemsetAsync(a, 0, (size_t)N.B * 8, b->stream);
+      if (e == hipSuccess) e = hipMemsetAsync(a, 0, (size_t)2 * N.B * 8, b->stream);
+    if (e == hipSuccess)
+      e = hipMemsetAsync(N.unitpart, 0, (size_t)2 * N.ncb * N.Bp * 2 * 8, b->stream);
+  }
+  // the other networks keep their state; it moves to the slot that
+  // iteration k0 reads
+  if (only >= 0 && ((b->iters ^ k0) & 1)) {
+    const int from = (int)(b->iters & 1), to = (int)(k0 & 1);
+    for (size_t k = 0; k < b->nets.size(); ++k) {
+      if ((int)k == only) continue;
+      const BNet &N = b->nets[k].d;
+      double *d8[] = {N.lam, N.vlam, N.slam};
+      for (double *a : d8)
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(a + (size_t)to * N.B, a + (size_t)from * N.B, (size_t)N.B * 8,
+                             hipMemcpyDeviceToDevice, b->stream);
+    }
   }
   BScal s{};
   s.it[k0 & 1].k = k0;
@@ -663,41 +896,36 @@ float time_net(dcopf_batch_s *b, int k, bool wphase, int reps) {
   return ms / reps;
 }
 
-// Autotuner: per network, the W arrangement x K split and the F arrangement
+// Autotuner: per network, the W tile shape x K split and the F tile shape
 // with the least measured time (each network timed alone).
 hipError_t autotune(dcopf_batch_s *b) {
-  const int arr[3][2] = {{4, 1}, {2, 2}, {1, 4}};
   const int splits[] = {1, 2, 4, 8, 16, 32};
   for (size_t k = 0; k < b->nets.size(); ++k) {
     BNet &N = b->nets[k].d;
     float bestw = 1e30f;
     int bw = 0, bs = 1;
-    for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c)
       for (int S : splits) {
         if (S > 1 && N.ldl / S < 256) continue;
-        N.wm_w = arr[a][0];
-        N.wn_w = arr[a][1];
+        N.cfg_w = c;
         set_split(N, S);
         hipError_t e = upload_nets(b);
         if (e != hipSuccess) return e;
         const float t = time_net(b, (int)k, true, 5);
-        if (t < bestw) bestw = t, bw = a, bs = S;
+        if (t < bestw) bestw = t, bw = c, bs = S;
       }
-    N.wm_w = arr[bw][0];
-    N.wn_w = arr[bw][1];
+    N.cfg_w = bw;
     set_split(N, bs);
     float bestf = 1e30f;
     int bf = 0;
-    for (int a = 0; a < 3; ++a) {
-      N.wm_f = arr[a][0];
-      N.wn_f = arr[a][1];
+    for (int c = 0; c < 3; ++c) {
+      N.cfg_f = c;
       hipError_t e = upload_nets(b);
       if (e != hipSuccess) return e;
       const float t = time_net(b, (int)k, false, 5);
-      if (t < bestf) bestf = t, bf = a;
+      if (t < bestf) bestf = t, bf = c;
     }
-    N.wm_f = arr[bf][0];
-    N.wn_f = arr[bf][1];
+    N.cfg_f = bf;
   }
   return upload_nets(b);
 }
@@ -713,6 +941,9 @@ dcopf_status validate_net(const dcopf_batch_network &n, int idx, size_t inst0) {
     return set_error(tag + "null data pointer"), DCOPF_E_INVALID;
   const size_t nl = n.n_line, nb = n.n_bus, ng = n.n_gen, B = n.n_inst;
   if ((double)nl * (double)nb > 4.0e9) return set_error(tag + "H too large"), DCOPF_E_INVALID;
+  // line-state arrays are addressed with 32-bit byte offsets
+  if ((B + 127) / 128 * 128 * ((nl + 127) / 128 * 128) >= ((size_t)1 << 30))
+    return set_error(tag + "n_inst * n_line too large (split the instances)"), DCOPF_E_INVALID;
   for (size_t g = 0; g < ng; ++g)
     if (n.gen_bus[g] < 0 || n.gen_bus[g] >= n.n_bus)
       return set_error(tag + "gen_bus out of range"), DCOPF_E_INVALID;
@@ -771,20 +1002,19 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
   N.n_c = nc;
   N.n_g = ng;
   N.B = B;
-  N.Bp = (int)round_up(B, 64);  // multiple of 64 for the FP64 bound product
+  N.Bp = (int)round_up(B, 128);  // every tile shape divides the padded extents
   N.ldl = (int)round_up(nl, 64);
   N.ldc = (int)round_up(nc, 64);
-  N.ncp = (int)round_up(nc, 32);
-  N.nlp = (int)round_up(nl, 32);
-  N.ntl = N.nlp / 32;
+  N.ncp = (int)round_up(nc, 128);
+  N.nlp = (int)round_up(nl, 128);
+  N.ntl = (nl + 31) / 32;  // 32-line tiles carrying line terms
   N.inst0 = inst0;
   N.alpha = n.alpha;
   N.rho = n.rho;
   // default shapes: instances along the workgroup when there are many
-  N.wm_w = N.Bp >= 128 ? 4 : 1;
-  N.wn_w = 4 / N.wm_w;
-  N.wm_f = N.wm_w;
-  N.wn_f = N.wn_w;
+  // default shapes: tall tiles when there are many instances, wide otherwise
+  N.cfg_w = B >= 128 ? 0 : (B > 32 ? 1 : 2);
+  N.cfg_f = N.cfg_w;
   set_split(N, N.Bp >= 256 ? 1 : std::max(1, N.ldl / 2048));
   const size_t Bp = N.Bp, ldl = N.ldl, ldc = N.ldc, ncp = N.ncp, nlp = N.nlp;
   __bf16 *PT_hi = balloc<__bf16>(own, ncp * ldl, &ok), *PT_lo = balloc<__bf16>(own, ncp * ldl, &ok);
@@ -803,13 +1033,14 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
   double *fd64 = balloc<double>(own, (size_t)B * nl, &ok);
   double *c = balloc<double>(own, (size_t)B * ng, &ok), *q = balloc<double>(own, (size_t)B * ng, &ok);
   double *pmin = balloc<double>(own, ng, &ok), *pmax = balloc<double>(own, ng, &ok);
-  int *dseg = balloc<int>(own, nc + 1, &ok), *dgperm = balloc<int>(own, ng, &ok);
-  N.lam = balloc<double>(own, B, &ok);
-  N.vlam = balloc<double>(own, B, &ok);
-  N.slam = balloc<double>(own, B, &ok);
-  N.genpart = balloc<double>(own, B, &ok);
+  int *dseg = balloc<int>(own, nc + 1, &ok);
+  N.lam = balloc<double>(own, (size_t)2 * B, &ok);
+  N.vlam = balloc<double>(own, (size_t)2 * B, &ok);
+  N.slam = balloc<double>(own, (size_t)2 * B, &ok);
+  N.ncb = (nc + 255) / 256;
+  N.unitpart = balloc<double>(own, (size_t)2 * N.ncb * Bp * 2, &ok);
   double *D = balloc<double>(own, B, &ok);
-  N.linepart = balloc<double>(own, (size_t)N.ntl * Bp, &ok);
+  N.linepart = balloc<double>(own, (size_t)(nlp / 32) * Bp, &ok);  // every 32-line tile an F tile can write
   N.V64 = balloc<double>(own, Bp * ldl, &ok);
   N.W64 = balloc<double>(own, Bp * ncp, &ok);
   N.bound = balloc<double>(own, B, &ok);
@@ -828,7 +1059,6 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
   N.pmin = pmin;
   N.pmax = pmax;
   N.seg = dseg;
-  N.gperm = dgperm;
   N.D = D;
   hipStream_t s = b->stream;
   hipError_t e = hipSuccess;
@@ -868,23 +1098,31 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
     chk(hipGetLastError());
     // data
     std::vector<float> f32(n.f_max, n.f_max + nl);
-    std::vector<double> qh((size_t)B * ng, 0.0), Dh(B, 0.0);
-    if (n.q) std::copy(n.q, n.q + (size_t)B * ng, qh.begin());
+    // unit data in column-sorted order: unit t of the panel is generator gperm[t]
+    std::vector<double> cs((size_t)B * ng), qs((size_t)B * ng, 0.0), lo(ng), hi(ng), Dh(B, 0.0);
+    for (int t = 0; t < ng; ++t) {
+      const int g = gperm[t];
+      lo[t] = n.p_min[g];
+      hi[t] = n.p_max[g];
+      for (int i = 0; i < B; ++i) {
+        cs[(size_t)i * ng + t] = n.c[(size_t)i * ng + g];
+        if (n.q) qs[(size_t)i * ng + t] = n.q[(size_t)i * ng + g];
+      }
+    }
     for (int i = 0; i < B; ++i)
       for (int bb = 0; bb < nb; ++bb) Dh[i] += n.d[(size_t)i * nb + bb];
     chk(hipMemcpyAsync(fl32, f32.data(), nl * 4, hipMemcpyHostToDevice, s));
     chk(hipMemcpyAsync(fl64, n.f_max, nl * 8, hipMemcpyHostToDevice, s));
-    chk(hipMemcpyAsync(c, n.c, (size_t)B * ng * 8, hipMemcpyHostToDevice, s));
-    chk(hipMemcpyAsync(q, qh.data(), (size_t)B * ng * 8, hipMemcpyHostToDevice, s));
-    chk(hipMemcpyAsync(pmin, n.p_min, ng * 8, hipMemcpyHostToDevice, s));
-    chk(hipMemcpyAsync(pmax, n.p_max, ng * 8, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(c, cs.data(), (size_t)B * ng * 8, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(q, qs.data(), (size_t)B * ng * 8, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(pmin, lo.data(), ng * 8, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(pmax, hi.data(), ng * 8, hipMemcpyHostToDevice, s));
     chk(hipMemcpyAsync(dseg, seg.data(), (nc + 1) * 4, hipMemcpyHostToDevice, s));
-    chk(hipMemcpyAsync(dgperm, gperm.data(), ng * 4, hipMemcpyHostToDevice, s));
     chk(hipMemcpyAsync(D, Dh.data(), B * 8, hipMemcpyHostToDevice, s));
     chk(hipMemsetAsync(N.X_hi, 0, Bp * ldc * 2, s));
     chk(hipMemsetAsync(N.X_lo, 0, Bp * ldc * 2, s));
     chk(hipMemsetAsync(N.V64, 0, Bp * ldl * 8, s));
-    chk(hipMemsetAsync(N.linepart, 0, (size_t)N.ntl * Bp * 8, s));
+    chk(hipMemsetAsync(N.linepart, 0, (size_t)(nlp / 32) * Bp * 8, s));
     chk(hipStreamSynchronize(s));
   }
   if (Hd) (void)hipFree(Hd);
@@ -906,7 +1144,7 @@ dcopf_status eval_bounds(dcopf_batch_s *b) {
     make_v64_kernel<<<vg, 256, 0, s>>>(N.mu_p, N.mu_m, N.B, N.n_l, N.ldl, N.V64);
     dim3 dg((unsigned)(N.ncp / 16), (unsigned)(N.Bp / 64));
     dgemm_nt_kernel<<<dg, 256, 0, s>>>(N.V64, N.P64T, N.W64, N.ldl, N.ncp, N.Bp);
-    bound_inst_kernel<<<N.B, 256, 0, s>>>(N);
+    bound_inst_kernel<<<N.B, 256, 0, s>>>(N, (int)(b->iters & 1));
   }
   DCOPF_HIP_TRY(hipGetLastError());
   DCOPF_HIP_TRY(hipStreamSynchronize(s));
@@ -959,11 +1197,19 @@ dcopf_status dcopf_batch_create(const dcopf_batch_network *nets, int32_t n_nets,
     inst0 += nets[k].n_inst;
   }
   std::vector<int2> inst;
+  std::vector<int4> units;
   for (int k = 0; k < n_nets; ++k)
-    for (int i = 0; i < nets[k].n_inst; ++i) inst.push_back(make_int2(k, i));
+    for (int i = 0; i < nets[k].n_inst; ++i) {
+      inst.push_back(make_int2(k, i));
+      for (int cb = 0; cb < b->nets[k].d.ncb; ++cb) units.push_back(make_int4(k, i, cb, 0));
+    }
+  b->n_units = (int)units.size();
   b->gcap = o.gamma_cap;
   hipError_t e = hipMalloc(&b->d_nets, n_nets * sizeof(BNet));
   if (e == hipSuccess) e = hipMalloc(&b->d_inst, inst.size() * sizeof(int2));
+  if (e == hipSuccess) e = hipMalloc(&b->d_units, units.size() * sizeof(int4));
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_units, units.data(), units.size() * sizeof(int4), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&b->sc, sizeof(BScal));
   if (e == hipSuccess) e = hipMalloc(&b->gam, (size_t)b->gcap * total * 8);
   if (e == hipSuccess)
@@ -1099,7 +1345,10 @@ dcopf_status dcopf_batch_get_multipliers(dcopf_batch_t b, int32_t net, double *l
   if (!b || net < 0 || net >= (int)b->nets.size()) return set_error("bad network"), DCOPF_E_INVALID;
   DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
   const BNet &N = b->nets[net].d;
-  if (lambda) DCOPF_HIP_TRY(hipMemcpy(lambda, N.lam, (size_t)N.B * 8, hipMemcpyDeviceToHost));
+  // after a step call the state of iteration `iters` sits in slot iters & 1
+  if (lambda)
+    DCOPF_HIP_TRY(hipMemcpy(lambda, N.lam + (size_t)(b->iters & 1) * N.B, (size_t)N.B * 8,
+                            hipMemcpyDeviceToHost));
   std::vector<float> tmp((size_t)N.B * N.ldl);
   float *src[2] = {N.mu_p, N.mu_m};
   double *dst[2] = {mu_plus, mu_minus};
@@ -1134,7 +1383,7 @@ dcopf_status dcopf_batch_set_multipliers(dcopf_batch_t b, int32_t net, const dou
       for (int l = 0; l < N.n_l; ++l) tmp[(size_t)i * N.ldl + l] = (float)srcs[s][(size_t)i * N.n_l + l];
     DCOPF_HIP_TRY(hipMemcpy(dsts[s], tmp.data(), tmp.size() * 4, hipMemcpyHostToDevice));
   }
-  DCOPF_HIP_TRY(hipMemcpy(N.lam, lambda, (size_t)N.B * 8, hipMemcpyHostToDevice));
+  DCOPF_HIP_TRY(hipMemcpy(N.lam, lambda, (size_t)N.B * 8, hipMemcpyHostToDevice));  // slot 0
   dim3 vg((unsigned)std::min(64, (N.n_l + 255) / 256), (unsigned)N.B);
   bmake_v_kernel<<<vg, 256, 0, b->stream>>>(N.mu_p, N.mu_m, N.B, N.n_l, N.ldl, N.V_hi, N.V_lo);
   DCOPF_HIP_TRY(hipGetLastError());
@@ -1148,10 +1397,10 @@ dcopf_status dcopf_batch_info(dcopf_batch_t b, int32_t net, int32_t *cfg, int64_
   if (!b || net < 0 || net >= (int)b->nets.size()) return set_error("bad network"), DCOPF_E_INVALID;
   const BNet &N = b->nets[net].d;
   if (cfg) {
-    cfg[0] = N.wm_w;
-    cfg[1] = N.wn_w;
+    cfg[0] = kTileBM[N.cfg_w];
+    cfg[1] = kTileBN[N.cfg_w];
     cfg[2] = N.S;
-    cfg[3] = N.wm_f * 10 + N.wn_f;
+    cfg[3] = kTileBM[N.cfg_f] * 1000 + kTileBN[N.cfg_f];
   }
   if (iters) *iters = b->iters;
   return DCOPF_OK;
@@ -1159,20 +1408,15 @@ dcopf_status dcopf_batch_info(dcopf_batch_t b, int32_t net, int32_t *cfg, int64_
 
 dcopf_status dcopf_batch_time_phases(dcopf_batch_t b, int64_t n, double *ms_out) {
   if (!b || !ms_out || n < 1) return set_error("bad arguments"), DCOPF_E_INVALID;
+  // real iterations, each dispatch timed by events attached to it
   std::vector<hipEvent_t> ev(6 * (size_t)n, nullptr);
   for (auto &e : ev) DCOPF_HIP_TRY(hipEventCreate(&e));
   for (int64_t t = 0; t < n; ++t) {
     const int par = (int)((b->iters + t) & 1);
     hipEvent_t *E = &ev[6 * t];
-    DCOPF_HIP_TRY(hipEventRecord(E[0], b->stream));
-    launch_w(b, b->stream, b->d_wtiles, b->n_wtiles);
-    DCOPF_HIP_TRY(hipEventRecord(E[1], b->stream));
-    DCOPF_HIP_TRY(hipEventRecord(E[2], b->stream));
-    launch_u(b, b->stream, par);
-    DCOPF_HIP_TRY(hipEventRecord(E[3], b->stream));
-    DCOPF_HIP_TRY(hipEventRecord(E[4], b->stream));
-    launch_f(b, b->stream, b->d_ftiles, b->n_ftiles, par);
-    DCOPF_HIP_TRY(hipEventRecord(E[5], b->stream));
+    launch_w(b, b->stream, b->d_wtiles, b->n_wtiles, E[0], E[1]);
+    launch_u(b, b->stream, par, E[2], E[3]);
+    launch_f(b, b->stream, b->d_ftiles, b->n_ftiles, par, E[4], E[5]);
   }
   b->iters += n;
   launch_final_b(b, b->stream);

@@ -1,9 +1,12 @@
 // Shared device/host helpers of the HIP path (not used by the oracle).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <tuple>
+#include <utility>
 #include <cstdio>
 #include <string>
 
@@ -103,6 +106,24 @@ __device__ __forceinline__ bool last_block_done(unsigned *counter, bool *flag_sm
   bool last = *flag_smem;
   if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return last;
+}
+
+// Launch `kernel` with the arguments converted to its parameter types.  With
+// events e0 != nullptr the start and stop events are attached to the dispatch
+// itself (the kernel's own start/end timestamps, as a profiler records them);
+// otherwise an ordinary launch (capturable into a HIP graph).
+template <typename... KA, typename... A>
+inline hipError_t launch_k(void (*kernel)(KA...), dim3 grid, dim3 block, unsigned lds,
+                           hipStream_t stream, hipEvent_t e0, hipEvent_t e1, A... args) {
+  std::tuple<KA...> t{static_cast<KA>(args)...};
+  void *ptrs[sizeof...(KA) > 0 ? sizeof...(KA) : 1];
+  std::apply([&](auto &...x) {
+    int i = 0;
+    ((ptrs[i++] = (void *)&x), ...);
+  }, t);
+  if (e0)
+    return hipExtLaunchKernel((const void *)kernel, grid, block, ptrs, lds, stream, e0, e1, 0);
+  return hipLaunchKernel((const void *)kernel, grid, block, ptrs, lds, stream);
 }
 
 }  // namespace dcopf

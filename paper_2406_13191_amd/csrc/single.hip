@@ -616,42 +616,45 @@ namespace {
 constexpr int kLineRows = 4;  // lines per wavefront in the line pass
 
 template <typename T, int CB>
-void launch_colpass_cb(dcopf_dual_s *h, hipStream_t s, int par) {
+void launch_colpass_cb(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hipEvent_t e1) {
   T *PT = std::is_same<T, float>::value ? (T *)h->P32T : (T *)h->P64T;
-  colpass_kernel<T, CB><<<h->grid_col, 256, 0, s>>>(
-      PT, h->n_cols, h->ldl, (T *)h->vbuf, h->seg, h->c, h->q, h->pmin, h->pmax, h->sc, par,
-      (T *)h->xbuf, h->part_a, h->grid_col, h->part_b, h->grid_line, h->prm, h->gam,
-      kGamCap - 1);
+  (void)launch_k(colpass_kernel<T, CB>, dim3(h->grid_col), dim3(256), 0, s, e0, e1, PT,
+                 h->n_cols, h->ldl, (T *)h->vbuf, h->seg, h->c, h->q, h->pmin, h->pmax, h->sc,
+                 par, (T *)h->xbuf, h->part_a, h->grid_col, h->part_b, h->grid_line, h->prm,
+                 h->gam, kGamCap - 1);
 }
 
 template <typename T>
-void launch_colpass(dcopf_dual_s *h, hipStream_t s, int par) {
-  if (h->col_cb == 1) launch_colpass_cb<T, 1>(h, s, par);
-  else if (h->col_cb == 2) launch_colpass_cb<T, 2>(h, s, par);
-  else launch_colpass_cb<T, 4>(h, s, par);
+void launch_colpass(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hipEvent_t e1) {
+  if (h->col_cb == 1) launch_colpass_cb<T, 1>(h, s, par, e0, e1);
+  else if (h->col_cb == 2) launch_colpass_cb<T, 2>(h, s, par, e0, e1);
+  else launch_colpass_cb<T, 4>(h, s, par, e0, e1);
 }
 
 template <typename T>
-void launch_linepass(dcopf_dual_s *h, hipStream_t s, int par) {
+void launch_linepass(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hipEvent_t e1) {
   T *P = std::is_same<T, float>::value ? (T *)h->P32 : (T *)h->P64;
   T *v = (T *)h->vbuf, *x = (T *)h->xbuf;
-#define DCOPF_LINEPASS(STAGE, XR, LDS)                                                      \
-  linepass_kernel<T, STAGE, kLineRows, XR><<<h->grid_line, 256, LDS, s>>>(                  \
-      P, h->n_lines, h->ldc, x, h->fd, h->fmax, h->mu_p, h->mu_m, h->v_p, h->v_m, h->s_p,     \
-      h->s_m, v, h->sc, par, h->part_b, h->grid_line, h->prm)
+#define DCOPF_LINEPASS(STAGE, XR, LDS)                                                       \
+  (void)launch_k(linepass_kernel<T, STAGE, kLineRows, XR>, dim3(h->grid_line), dim3(256), LDS, \
+                 s, e0, e1, P, h->n_lines, h->ldc, x, h->fd, h->fmax, h->mu_p, h->mu_m,       \
+                 h->v_p, h->v_m, h->s_p, h->s_m, v, h->sc, par, h->part_b, h->grid_line, h->prm)
   if (h->line_xr == 2) DCOPF_LINEPASS(false, 2, 0);
   else if (h->line_xr == 4) DCOPF_LINEPASS(false, 4, 0);
-  else if (h->stage_line) DCOPF_LINEPASS(true, 0, h->lds_line);
+  else if (h->stage_line) DCOPF_LINEPASS(true, 0, (unsigned)h->lds_line);
   else DCOPF_LINEPASS(false, 0, 0);
 #undef DCOPF_LINEPASS
 }
 
-void launch_phase(dcopf_dual_s *h, hipStream_t s, int phase, int par) {
+void launch_phase(dcopf_dual_s *h, hipStream_t s, int phase, int par, hipEvent_t e0 = nullptr,
+                  hipEvent_t e1 = nullptr) {
   const bool fp32 = h->opts.precision == DCOPF_PREC_FP32;
   if (phase == 0) {
-    if (fp32) launch_colpass<float>(h, s, par); else launch_colpass<double>(h, s, par);
+    if (fp32) launch_colpass<float>(h, s, par, e0, e1);
+    else launch_colpass<double>(h, s, par, e0, e1);
   } else {
-    if (fp32) launch_linepass<float>(h, s, par); else launch_linepass<double>(h, s, par);
+    if (fp32) launch_linepass<float>(h, s, par, e0, e1);
+    else launch_linepass<double>(h, s, par, e0, e1);
   }
 }
 
@@ -1182,10 +1185,9 @@ dcopf_status dcopf_dual_set_state(dcopf_dual_t h, const double *buf, size_t len)
 
 dcopf_status dcopf_dual_time_phases(dcopf_dual_t h, int64_t n, double *ms_out) {
   if (!h || !ms_out || n < 1) return set_error("bad arguments"), DCOPF_E_INVALID;
-  // Each pass is launched n times back to back between one event pair.  The
-  // column pass is idempotent when repeated on one parity (it re-folds the
-  // same previous iteration); the line pass advances mu, so the mutable
-  // state is saved first and restored afterwards: the iterate is unchanged.
+  // n real iterations (column pass, line pass alternating as in step), each
+  // launch carrying dispatch-attached start/stop events; the mutable state is
+  // saved first and restored afterwards, so the iterate is unchanged.
   const size_t nl = h->n_lines;
   const size_t esz = h->opts.precision == DCOPF_PREC_FP32 ? 4 : 8;
   double *save = nullptr;
@@ -1200,14 +1202,12 @@ dcopf_status dcopf_dual_time_phases(dcopf_dual_t h, int64_t n, double *ms_out) {
     DCOPF_HIP_TRY(hipMemcpyAsync(save + i * nl, arrs[i], nl * 8, hipMemcpyDeviceToDevice, s));
   DCOPF_HIP_TRY(hipMemcpyAsync(vsave, h->vbuf, (size_t)h->ldl * esz, hipMemcpyDeviceToDevice, s));
   DCOPF_HIP_TRY(hipMemcpyAsync(ssave, h->sc, sizeof(DevScalars), hipMemcpyDeviceToDevice, s));
-  const int par = (int)(h->iters & 1);
-  hipEvent_t ev[4];
+  std::vector<hipEvent_t> ev(4 * (size_t)n, nullptr);
   for (auto &e : ev) DCOPF_HIP_TRY(hipEventCreate(&e));
-  for (int phase = 0; phase < 2; ++phase) {
-    launch_phase(h, s, phase, par);  // warm
-    DCOPF_HIP_TRY(hipEventRecord(ev[2 * phase], s));
-    for (int64_t i = 0; i < n; ++i) launch_phase(h, s, phase, par);
-    DCOPF_HIP_TRY(hipEventRecord(ev[2 * phase + 1], s));
+  for (int64_t i = 0; i < n; ++i) {
+    const int par = (int)((h->iters + i) & 1);
+    for (int phase = 0; phase < 2; ++phase)
+      launch_phase(h, s, phase, par, ev[4 * i + 2 * phase], ev[4 * i + 2 * phase + 1]);
   }
   for (int i = 0; i < 6; ++i)
     DCOPF_HIP_TRY(hipMemcpyAsync(arrs[i], save + i * nl, nl * 8, hipMemcpyDeviceToDevice, s));
@@ -1215,11 +1215,14 @@ dcopf_status dcopf_dual_time_phases(dcopf_dual_t h, int64_t n, double *ms_out) {
   DCOPF_HIP_TRY(hipMemcpyAsync(h->sc, ssave, sizeof(DevScalars), hipMemcpyDeviceToDevice, s));
   DCOPF_HIP_TRY(hipGetLastError());
   DCOPF_HIP_TRY(hipStreamSynchronize(s));
-  for (int phase = 0; phase < 2; ++phase) {
-    float ms = 0.f;
-    DCOPF_HIP_TRY(hipEventElapsedTime(&ms, ev[2 * phase], ev[2 * phase + 1]));
-    ms_out[phase] = ms / n;
-  }
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = 0; i < n; ++i)
+    for (int phase = 0; phase < 2; ++phase) {
+      float ms = 0.f;
+      DCOPF_HIP_TRY(hipEventElapsedTime(&ms, ev[4 * i + 2 * phase], ev[4 * i + 2 * phase + 1]));
+      acc[phase] += ms;
+    }
+  for (int phase = 0; phase < 2; ++phase) ms_out[phase] = acc[phase] / n;
   for (auto &e : ev) (void)hipEventDestroy(e);
   (void)hipFree(save);
   (void)hipFree(vsave);

@@ -255,7 +255,7 @@ def _line_prices(net, gen_bus, c, p_min, p_max, d, f_max):
 
 
 def _cap_prices(net, gen_bus, c, p_min, p_max, d, f_max, cap, rounds=6):
-    """Relax (to 1.1 x the optimal flow) every line whose limit price exceeds
+    """Relax (to REPAIR_MARGIN x the optimal flow) every line whose limit price exceeds
     ``cap`` and re-solve, so that no congestion price is extreme.  A line the
     generators can barely influence needs an enormous multiplier to bind;
     such lines make the dual badly scaled and are not what the workload is
@@ -266,7 +266,7 @@ def _cap_prices(net, gen_bus, c, p_min, p_max, d, f_max, cap, rounds=6):
         bad = price > cap
         if not np.any(bad):
             break
-        f[bad] = np.abs(flows[bad]) * 1.1
+        f[bad] = np.abs(flows[bad]) * REPAIR_MARGIN
     return f
 
 
@@ -335,13 +335,36 @@ def _relievable(net, gen_bus, p_min, p_max, d, F0, lines):
     return (lo <= lim) & (hi >= -lim)
 
 
+def _widen_for_scenarios(net, gen_bus, p_min, p_max, d, f_max, rng, sigma=0.15,
+                         samples=16, rounds=4):
+    """Widen limits so that load scenarios around the base case (per-bus
+    multipliers exp(N(0, sigma^2))) are feasible: for each sampled scenario
+    the least-violation dispatch is computed and every limit it violates is
+    raised to 1.1 x that flow."""
+    f = f_max.copy()
+    for _ in range(rounds):
+        changed = False
+        for _ in range(samples):
+            dd = d * np.exp(rng.normal(0.0, sigma, d.size))
+            if dd.sum() > p_max.sum() or dd.sum() < p_min.sum():
+                continue
+            flows, viol = _min_violation_dispatch(net, gen_bus, p_min, p_max, dd, f)
+            bad = viol > 1e-9 * np.maximum(f, 1.0)
+            if np.any(bad):
+                f[bad] = np.abs(flows[bad]) * 1.1
+                changed = True
+        if not changed:
+            break
+    return f
+
+
 def _place_targets(net, gen_bus, p_min, p_max, d, f_max, F0, order, n_target):
     """Tighten the first ``n_target`` candidate lines of ``order`` to 0.8 |F0|
     and make the instance feasible with one LP.
 
     Bridge lines and lines that no dispatch can relieve on their own are not
     candidates.  The dispatch of least total violation is then computed; every
-    limit it still violates is raised to that dispatch's flow (x (1 + 1e-6)),
+    limit it still violates is raised to REPAIR_MARGIN x that dispatch's flow,
     so that dispatch is feasible and the instance is feasible by construction.
     """
     order = order[~_bridges(net.n_bus, net.fbus, net.tbus)[order]]
@@ -351,7 +374,7 @@ def _place_targets(net, gen_bus, p_min, p_max, d, f_max, F0, order, n_target):
     f[target] = 0.8 * F0[target]
     flows, viol = _min_violation_dispatch(net, gen_bus, p_min, p_max, d, f)
     raise_ = viol > 0
-    f[raise_] = np.abs(flows[raise_]) * (1.0 + 1e-6)
+    f[raise_] = np.abs(flows[raise_]) * REPAIR_MARGIN
     return f
 
 
@@ -359,6 +382,8 @@ def _place_targets(net, gen_bus, p_min, p_max, d, f_max, F0, order, n_target):
 # Recipes
 # --------------------------------------------------------------------------
 PRICE_CAP = 1000.0   # $/MWh, largest line-limit price allowed in a recipe
+REPAIR_MARGIN = 1.25  # headroom of a repaired or relaxed limit over its flow, so
+                      # that load scenarios around the base case stay feasible
 
 NET_SPECS = {
     # name: (recipe, n_bus, n_line, n_gen, qp, c range, load fraction, bind fraction)
@@ -426,6 +451,7 @@ def make_network(name: str, seed: int):
                                n_target)
         f_max = _cap_prices(net, gen_bus, c, p_min, p_max, d, f_max,
                             cap=PRICE_CAP)
+        f_max = _widen_for_scenarios(net, gen_bus, p_min, p_max, d, f_max, rng)
     net._H = None
     prob = Problem(H=H, gen_bus=gen_bus, c=c, q=q, p_min=p_min, p_max=p_max,
                    d=d, f_max=f_max, slack=0, net=net)

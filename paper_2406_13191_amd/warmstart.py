@@ -1,0 +1,158 @@
+"""Learned warm start for the batched dual ascent (GPU pipeline).
+
+The ascent of Section 3.3 starts from lambda = mu = 0.  Here a network
+(dcopf_mlp.h) maps an instance's load vector to initial multipliers:
+
+1. scenarios: per-bus load multipliers exp(N(0, sigma^2)) on one network
+   (``synth.make_scenarios``);
+2. targets: the multipliers the method itself reaches from a cold start
+   (batched GPU solves, ``dcopf_batch``);
+3. training: standardised inputs and targets, mean squared error, Adam, on
+   the GPU with the library's own forward/backward kernels;
+4. use: predicted multipliers, mu projected onto mu >= 0, set as the start of
+   a batched solve.  Fallback: a cold start runs beside it, and after
+   ``fallback_at`` iterations each instance keeps whichever trajectory has
+   the larger exact bound.  Every bound reported is an exact dual value.
+
+Every numerical step runs in the HIP library; this module moves arrays.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+
+from . import _abi, synth
+
+
+@dataclasses.dataclass
+class Standardizer:
+    mean: np.ndarray
+    std: np.ndarray
+
+    @staticmethod
+    def fit(a: np.ndarray) -> "Standardizer":
+        mean = a.mean(0)
+        std = a.std(0)
+        return Standardizer(mean, np.where(std > 1e-12 * (np.abs(mean) + 1), std, 1.0))
+
+    def apply(self, a):
+        return (a - self.mean) / self.std
+
+    def invert(self, a):
+        return a * self.std + self.mean
+
+
+def cold_solve(base, D, iters, alpha, rho, stream=None, chunk=8192):
+    """Multipliers after ``iters`` cold-start GDM iterations for every load
+    scenario D [B, n_bus] (batched GPU solves, chunks of ``chunk``).
+    Returns (targets [B, 2 n_line + 1] = [mu+, mu-, lambda], exact bounds)."""
+    out, bounds = [], []
+    C = np.tile(base.c, (D.shape[0], 1))
+    for s in range(0, D.shape[0], chunk):
+        Dc = D[s:s + chunk]
+        net = _abi.BatchNetwork(base, Dc, C[s:s + chunk], None, alpha=alpha, rho=rho)
+        with _abi.BatchSolver([net], stream=stream, graph_iters=50, gamma_cap=1) as b:
+            b.step(iters)
+            bounds.append(b.bound())
+            lam, mp, mm = b.get_multipliers(0)
+        out.append(np.concatenate([mp, mm, lam[:, None]], axis=1))
+    return np.concatenate(out), np.concatenate(bounds)
+
+
+def train(model: "_abi.MLP", X, T, epochs, batch, lr, seed=0, lr_decay=0.9, log=None):
+    """Mini-batch training on device tensors X [N, n_in], T [N, n_out] (FP32,
+    already standardised).  Returns the per-epoch mean batch loss."""
+    import torch
+    N = X.shape[0]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    losses = []
+    for ep in range(epochs):
+        perm = torch.randperm(N, generator=g).to(X.device)
+        tot, nb = 0.0, 0
+        for s in range(0, N - batch + 1, batch):
+            idx = perm[s:s + batch]
+            xb = X.index_select(0, idx).contiguous()
+            tb = T.index_select(0, idx).contiguous()
+            want = (s // batch) % 20 == 0
+            l = model.train_step(xb.data_ptr(), tb.data_ptr(), batch, lr, want_loss=want)
+            if want:
+                tot += l
+                nb += 1
+        losses.append(tot / max(nb, 1))
+        if log:
+            log(f"epoch {ep}: loss {losses[-1]:.4e} lr {lr:.2e}")
+        lr *= lr_decay
+    return losses
+
+
+def predict(model: "_abi.MLP", X, sx: Standardizer, st: Standardizer, n_line, batch=256):
+    """Warm-start multipliers for load vectors X [N, n_bus] (host): returns
+    (lambda [N], mu+ [N, n_line], mu- [N, n_line]) with mu >= 0."""
+    import torch
+    N = X.shape[0]
+    Xn = torch.tensor(sx.apply(X), dtype=torch.float32, device="cuda")
+    Y = torch.empty((N, 2 * n_line + 1), dtype=torch.float32, device="cuda")
+    for s in range(0, N, batch):
+        n = min(batch, N - s)
+        model.forward(Xn[s:s + n].data_ptr(), n, Y[s:s + n].data_ptr())
+    torch.cuda.synchronize()
+    Yh = st.invert(Y.cpu().numpy().astype(np.float64))
+    mp = np.maximum(Yh[:, :n_line], 0.0)
+    mm = np.maximum(Yh[:, n_line:2 * n_line], 0.0)
+    return Yh[:, -1], mp, mm
+
+
+def run_to_gap(base, D, opt, alpha, rho, start=None, max_iters=5000, check_every=10,
+               probe_at=100, stream=None):
+    """Batched solve of the scenarios D (cold, or from start = (lam, mu+, mu-)).
+    Returns (iteration of the first exact bound within 0.1 % of opt per
+    instance, -1 if none; exact bound at iteration probe_at)."""
+    C = np.tile(base.c, (D.shape[0], 1))
+    net = _abi.BatchNetwork(base, D, C, None, alpha=alpha, rho=rho)
+    with _abi.BatchSolver([net], stream=stream, graph_iters=10, gamma_cap=1) as b:
+        if start is not None:
+            b.set_multipliers(0, *start)
+        hit = np.full(D.shape[0], -1, np.int64)
+        probe = None
+        it = 0
+        vals = b.bound()
+        hit[(opt - vals) <= 1e-3 * np.abs(opt)] = 0
+        while it < max_iters and np.any(hit < 0):
+            b.step(check_every)
+            it += check_every
+            vals = b.bound()
+            newly = (hit < 0) & ((opt - vals) <= 1e-3 * np.abs(opt))
+            hit[newly] = it
+            if it == probe_at:
+                probe = vals.copy()
+        if probe is None:
+            probe = vals.copy()
+    return hit, probe
+
+
+def combine_with_fallback(hit_cold, probe_cold, hit_warm, probe_warm, probe_at):
+    """Warm start with a cold shadow: both trajectories run until probe_at;
+    an instance certified by either of them by then stops at the first
+    certification; otherwise the trajectory with the larger exact bound at
+    probe_at continues alone.  Returns (iterations to the gap, -1 if never;
+    which instances kept the warm trajectory)."""
+    use_warm = probe_warm >= probe_cold
+    big = np.iinfo(np.int64).max
+    ew = np.where((hit_warm >= 0) & (hit_warm <= probe_at), hit_warm, big)
+    ec = np.where((hit_cold >= 0) & (hit_cold <= probe_at), hit_cold, big)
+    early = np.minimum(ew, ec)
+    later = np.where(use_warm, hit_warm, hit_cold)
+    return np.where(early < big, early, later), use_warm
+
+
+def median_iters(hit, cap):
+    """Median with unreached instances counted at the cap."""
+    return float(np.median(np.where(hit >= 0, hit, cap)))
+
+
+def timed(fn, *a, **k):
+    t = time.perf_counter()
+    r = fn(*a, **k)
+    return r, time.perf_counter() - t

@@ -128,7 +128,13 @@ def one_step_parity(specs, rule="gdm", tol_rel=1e-5):
                     nc = len(np.unique(K.C[:nl].nonzero()[1]))
                     Pabs = np.abs(K.C[:nl])
                     dF = split_bound(K, ev.x, nc, False) + Pabs @ dp
-                    bound = alpha * dF + 4 * U32 * np.abs(st1.mu[:nl]) + 1e-9
+                    # plus FP32 rounding of f_d and of the state update
+                    fd = np.abs(K.d[:nl] - K.d[nl:]) / 2  # = |H d|
+                    fl = (K.d[:nl] + K.d[nl:]) / 2         # = f_max
+                    g = np.abs(ev.grad_mu[:nl])
+                    bound = (alpha * (dF + 4 * U32 * (fd + fl))
+                             + 4 * U32 * (np.abs(st.mu[:nl]) + np.abs(st1.mu[:nl]) + alpha * g)
+                             + 1e-12)
                     assert np.all(np.abs(mp_g[i] - st1.mu[:nl]) <= bound)
         print(f"worst mu error / scale: {worst:.3e}", flush=True)
 
@@ -192,6 +198,55 @@ def test_deterministic_and_graph():
         for x, y in zip(a.get_multipliers(0), b.get_multipliers(0)):
             np.testing.assert_array_equal(x, y)
         np.testing.assert_array_equal(a.gammas(0, 33), b.gammas(0, 33))
+
+
+def test_split_calls_and_timed_iterations_match_one_call():
+    # step calls fold the last iteration at their end; time_phases runs real
+    # iterations: every way of cutting 13 iterations gives the same state
+    A = _abi()
+    n1, _ = batch_net("geo300q", 7, 24, 5100)
+    with A.BatchSolver([n1]) as a, A.BatchSolver([n1], graph_iters=4) as b, \
+            A.BatchSolver([n1]) as c:
+        a.step(13)
+        for n in (3, 1, 4, 5):
+            b.step(n)
+        c.step(2)
+        c.time_phases(5)
+        c.step(6)
+        ref_m = a.get_multipliers(0)
+        for other in (b, c):
+            for x, y in zip(ref_m, other.get_multipliers(0)):
+                np.testing.assert_array_equal(x, y)
+        np.testing.assert_array_equal(a.gammas(0, 13), b.gammas(0, 13))
+        np.testing.assert_array_equal(a.gammas(0, 13), c.gammas(0, 13))
+
+
+def test_set_multipliers_keeps_other_networks():
+    # after an odd number of iterations, a warm start of network 1 leaves
+    # network 0's iterate and optimiser state as they were
+    A = _abi()
+    n1, _ = batch_net("geo300", 7, 16, 5200)
+    n2, (base2, Dm2, _, _) = batch_net("geo300q", 7, 8, 5300)
+    nl2 = base2.n_line
+    rng = np.random.default_rng(3)
+    lam2 = rng.uniform(20, 40, 8)
+    mp2 = rng.exponential(1.0, (8, nl2)).astype(np.float32).astype(np.float64)
+    mm2 = rng.exponential(1.0, (8, nl2)).astype(np.float32).astype(np.float64)
+    with A.BatchSolver([n1, n2]) as b, A.BatchSolver([n1]) as s:
+        b.step(5)
+        before = b.get_multipliers(0)
+        b.set_multipliers(1, lam2, mp2, mm2)
+        for x, y in zip(before, b.get_multipliers(0)):
+            np.testing.assert_array_equal(x, y)
+        got = b.get_multipliers(1)
+        np.testing.assert_array_equal(got[0], lam2)
+        np.testing.assert_array_equal(got[1], mp2)
+        np.testing.assert_array_equal(got[2], mm2)
+        # GDM without decay: network 0 continues exactly as if alone
+        b.step(4)
+        s.step(9)
+        for x, y in zip(s.get_multipliers(0), b.get_multipliers(0)):
+            np.testing.assert_array_equal(x, y)
 
 
 def test_batched_qp_tracks_oracle_trajectory():

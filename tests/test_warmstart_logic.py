@@ -1,0 +1,36 @@
+"""Host logic of the warm-start pipeline (no GPU): the fallback combination,
+the standardiser and the capped median."""
+import numpy as np
+
+from paper_2406_13191_amd import warmstart as W
+
+
+def test_fallback_rule():
+    # columns: cold hit, cold bound at the probe, warm hit, warm bound at the probe
+    hc = np.array([500, 40, 500, -1, 300, 90])
+    pc = np.array([10., 10., 10., 10., 10., 10.])
+    hw = np.array([200, 500, 60, 150, -1, 80])
+    pw = np.array([11., 12., 9., 12., 9., 9.])
+    got, used = W.combine_with_fallback(hc, pc, hw, pw, 100)
+    # 0: warm better at probe -> warm's 200; 1: cold certified at 40 (< probe)
+    # 2: warm certified at 60 before the probe; 3: warm kept -> 150
+    # 4: cold kept -> 300; 5: both certified before the probe -> 80
+    np.testing.assert_array_equal(got, [200, 40, 60, 150, 300, 80])
+    np.testing.assert_array_equal(used, [True, True, False, True, False, False])
+
+
+def test_standardizer_roundtrip_and_constant_columns():
+    rng = np.random.default_rng(0)
+    a = rng.normal(3, 2, (100, 5))
+    a[:, 2] = 7.0
+    s = W.Standardizer.fit(a)
+    z = s.apply(a)
+    np.testing.assert_allclose(z[:, [0, 1, 3, 4]].mean(0), 0, atol=1e-12)
+    np.testing.assert_allclose(z[:, [0, 1, 3, 4]].std(0), 1, atol=1e-12)
+    np.testing.assert_allclose(z[:, 2], 0, atol=1e-12)
+    np.testing.assert_allclose(s.invert(z), a, atol=1e-12)
+
+
+def test_median_counts_unreached_at_cap():
+    assert W.median_iters(np.array([10, -1, -1]), 5000) == 5000
+    assert W.median_iters(np.array([10, 20, -1]), 5000) == 20
