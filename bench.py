@@ -8,9 +8,11 @@ minimiser, residuals, step + projection).  Inputs are resident in HBM before
 the timed region; the iteration loop is replayed as captured HIP graphs.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -19,6 +21,49 @@ sys.path.insert(0, ROOT)
 
 METRIC = "instance-iterations/s of dual ascent; time to bound within 0.1% of FP64 optimum"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+SINGLE_SRC = ("paper_2406_13191_amd/csrc/common.h", "paper_2406_13191_amd/csrc/single.hip")
+BATCH_SRC = ("paper_2406_13191_amd/csrc/common.h", "paper_2406_13191_amd/csrc/batch.hip")
+
+
+def source_sha(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key, files):
+    """HBM bytes per launch of kernel `key` from the rocprofv3 counter runs
+    recorded in profiles/hbm_traffic.md: FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch), each scaled by what the counter reads for a plain 1 GiB copy.
+    None when not recorded or when the kernel's sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            m = re.search(r"```json\n(.*?)\n```", f.read(), re.S)
+        table = json.loads(m.group(1))
+        e = table["kernels"][key]
+        cal = table["copy_calibration"]
+    except (OSError, AttributeError, KeyError, ValueError):
+        return None
+    if e.get("source_sha256") != source_sha(files):
+        return None
+    return int(round(e["fetch_kib"] * 1024 * cal["fetch_scale"]
+                     + e["write_kib"] * 1024 * cal["write_scale"]))
+
+
+def copy_calibration():
+    """A plain 1 GiB device copy, three times: the kernel whose counter
+    readings calibrate FETCH_SIZE and WRITE_SIZE."""
+    import torch
+    a = torch.empty(2 ** 28, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read": 2 ** 30,
+                      "bytes_written": 2 ** 30, "repeats": 3}), flush=True)
 
 
 def panel_bytes(n_line, n_cols, n_gen):
@@ -66,12 +111,15 @@ def bench_mixed(args, stream):
     from paper_2406_13191_amd import _abi, synth
     nets, shapes = [], []
     for name, seed, B, seed0 in MIXED:
+        t = time.perf_counter()
         _, base = synth.make_network(name, seed)
+        print(f"[bench] network {name}: {time.perf_counter() - t:.1f} s", file=sys.stderr,
+              flush=True)
         Dm, Cc, Q = synth.make_scenarios(base, seed0, B, 0.1, 0.1)
         r = synth.STEP_RULES[name]
         nets.append(_abi.BatchNetwork(base, Dm, Cc, Q if base.is_qp else None,
                                       alpha=r["alpha"], rho=r["rho"]))
-        shapes.append((name, base.n_line, len(np.unique(base.gen_bus)), B))
+        shapes.append((name, base.n_line, len(np.unique(base.gen_bus)), base.n_gen, B))
     b = _abi.BatchSolver(nets, stream=stream.cuda_stream, autotune=True, graph_iters=20,
                          gamma_cap=64)
     n_total = b.n_total
@@ -87,27 +135,48 @@ def bench_mixed(args, stream):
     ms_w, ms_u, ms_f = b.time_phases(20)
     tiles = [b.info(k) for k in range(len(nets))]
     b.close()
-    useful = sum(2.0 * nl * nc * B for _, nl, nc, B in shapes)  # one product, FP32-equivalent
-    issued = 3 * useful
-    # HBM bytes of one iteration: both panels (BF16 hi+lo), the FP32 state
-    # (mu, velocity read+write, f_d read) and V hi/lo writes per (line, instance)
-    state = sum(B * nl * (4 * 4 + 4 * 4 + 4 + 4) for _, nl, nc, B in shapes)
-    panels = sum(2 * 4 * nl * nc for _, nl, nc, B in shapes)
-    dom = ("W product (W^T = V^T P, split-BF16 MFMA)", ms_w) if ms_w >= ms_f else \
-          ("F product (F^T = X^T P^T, split-BF16 MFMA, mu step)", ms_f)
-    achieved = issued / (dom[1] * 1e-3) / 1e12
+    splits = [t["w_split"] for t in tiles]
+    bw, bu, bf = batch_phase_bytes(shapes, splits)
+    phases = {"w": ("W product (W^T = V^T P, split-BF16 MFMA)", ms_w, bw),
+              "units": ("unit pass (reduced costs, inner minimiser, lambda step)", ms_u, bu),
+              "f": ("F product (F^T = X^T P^T, split-BF16 MFMA, mu step)", ms_f, bf)}
+    key = max(phases, key=lambda k: phases[k][1])
+    kname, kms, kbytes = phases[key]
+    achieved = kbytes / (kms * 1e-3) / 1e9
+    useful = sum(2.0 * nl * nc * B for _, nl, nc, ng, B in shapes)  # one product
+    issued = 3 * useful  # three split-BF16 terms
+    mfma_tflops = 2 * issued / ((ms_w + ms_f) * 1e-3) / 1e12
     return dict(
         value=n_total * args.steps / (ms / 1e3), ms=ms, n_total=n_total,
-        roofline=dict(bound="mfma", achieved=round(achieved, 2), peak=BF16_PEAK_TFLOPS,
-                      unit="TFLOP/s", frac=round(achieved / BF16_PEAK_TFLOPS, 4),
-                      traffic=None, kernel=dom[0], kernel_ms=round(dom[1], 5),
-                      flops_per_launch=issued, useful_fp32_equiv_flops=useful,
-                      phase_ms=dict(w=round(ms_w, 5), units=round(ms_u, 5),
-                                    f=round(ms_f, 5)),
-                      hbm_bytes_per_iteration=int(state + panels),
-                      hbm_gbs_per_iteration=round((state + panels) / (ms / args.steps * 1e-3)
-                                                  / 1e9, 1)),
+        roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                      unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                      traffic=measured_traffic("mixed:" + key, BATCH_SRC), kernel=kname,
+                      kernel_ms=round(kms, 5), bytes_per_launch=int(kbytes),
+                      phase_ms={k: round(v[1], 5) for k, v in phases.items()},
+                      phase_bytes={k: int(v[2]) for k, v in phases.items()},
+                      phase_gbs={k: round(v[2] / (v[1] * 1e-3) / 1e9, 1)
+                                 for k, v in phases.items()},
+                      mfma=dict(issued_flops_per_product=issued,
+                                achieved_tflops=round(mfma_tflops, 2),
+                                peak_tflops=BF16_PEAK_TFLOPS,
+                                frac=round(mfma_tflops / BF16_PEAK_TFLOPS, 4))),
         shapes=shapes, tiles=tiles)
+
+
+def batch_phase_bytes(shapes, splits):
+    """Algorithmic HBM bytes of one launch of each batched phase, summed over
+    the networks (GDM state; split-BF16 operands are 4 bytes per element)."""
+    w = u = f = 0
+    for (_, nl, nc, ng, B), S in zip(shapes, splits):
+        ntl = (nl + 31) // 32
+        # W: P^T hi/lo, V hi/lo read; FP32 split-K partials written
+        w += 4 * nl * nc + 4 * B * nl + 4 * S * B * nc
+        # units: partials, costs, generator bounds read; X hi/lo written
+        u += 4 * S * B * nc + 16 * B * ng + 16 * ng + 4 * B * nc + 8 * B * ntl
+        # F: P hi/lo, X hi/lo, f_max read; f_d, mu+-, velocity+- read,
+        # mu+-, velocity+-, V hi/lo written (40 bytes per line and instance)
+        f += 4 * nl * nc + 4 * B * nc + 4 * nl + 40 * B * nl + 8 * B * ntl
+    return w, u, f
 
 
 def _highs_opt(args):
@@ -201,6 +270,9 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.workload == "copy":
+        copy_calibration()
+        return
     if args.workload == "warmstart":
         r = bench_warmstart(args, stream)
         out = {
@@ -225,15 +297,18 @@ def main():
             "ms_per_step": r["ms"] / args.steps, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
             "config": {"workload": "mixed batch: " + ", ".join(
-                f"{B} x {n} ({nl} lines, {nc} generator buses)" for n, nl, nc, B in r["shapes"])
+                f"{B} x {n} ({nl} lines, {nc} generator buses)" for n, nl, nc, ng, B in r["shapes"])
                 + "; split-BF16 MFMA products, FP32 line state, FP64 lambda and bound; GDM",
                 "instances": r["n_total"], "tiles": r["tiles"]},
             "roofline": r["roofline"], "cpu_baseline": None,
         }
         print(json.dumps(out), flush=True)
         return
+    t = time.perf_counter()
     net, p = synth.make_network(args.workload, {"bus2000": 2000, "bus4600": 4600,
                                                 "bus10000": 10000}[args.workload])
+    print(f"[bench] network {args.workload}: {time.perf_counter() - t:.1f} s", file=sys.stderr,
+          flush=True)
     r = synth.STEP_RULES[args.workload]
     n_cols = len(np.unique(p.gen_bus))
     kw = dict(rule="gdm", alpha=r["alpha"], rho=r["rho"], precision="fp32", panel=args.panel,
@@ -255,17 +330,19 @@ def main():
     value = args.steps / (ms / 1e3)
     print(f"[bench] {args.steps} iterations in {ms:.2f} ms (wall {wall*1e3:.2f} ms)",
           file=sys.stderr, flush=True)
-    # per-kernel durations (back-to-back launches between HIP events) for the roofline
+    # per-kernel durations for the roofline: events attached to each dispatch of
+    # 200 real iterations (the iterate is restored afterwards)
     ms_col, ms_line = s.time_phases(200)
     s.close()
     b_col, b_line = panel_bytes(p.n_line, n_cols, p.n_gen)
     if ms_line >= ms_col:
-        kname, kms, kbytes = "linepass (F = P x - f_d, mu step)", ms_line, b_line
+        kkey, kname, kms, kbytes = "linepass", "linepass (F = P x - f_d, mu step)", ms_line, b_line
     else:
-        kname, kms, kbytes = "colpass (w = P^T v, inner minimiser)", ms_col, b_col
+        kkey, kname, kms, kbytes = "colpass", "colpass (w = P^T v, inner minimiser)", ms_col, b_col
     achieved = kbytes / (kms * 1e-3) / 1e9
+    traffic = measured_traffic(f"{args.workload}/{args.panel}:{kkey}", SINGLE_SRC)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=kname,
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=kname,
                     kernel_ms=round(kms, 5), bytes_per_launch=int(kbytes),
                     other_kernel_ms=round(min(ms_col, ms_line), 5))
 

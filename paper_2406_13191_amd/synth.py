@@ -24,7 +24,9 @@ order, so a (recipe, seed) pair always yields the same arrays.
 from __future__ import annotations
 
 import dataclasses
+import hashlib
 import math
+import os
 from typing import Optional
 
 import numpy as np
@@ -402,8 +404,44 @@ NET_SPECS = {
 }
 
 
+def _cache_path(name: str, seed: int):
+    """Directory for a generated network when DCOPF_SYNTH_CACHE names a
+    cache directory (keyed by this module's source, so a changed recipe
+    never reuses an old network); None otherwise."""
+    root = os.environ.get("DCOPF_SYNTH_CACHE")
+    if not root:
+        return None
+    with open(__file__, "rb") as f:
+        tag = hashlib.sha256(f.read()).hexdigest()[:16]
+    return os.path.join(root, f"{name}_{seed}_{tag}")
+
+
+_CACHED = ("fbus", "tbus", "b", "H", "gen_bus", "c", "q", "p_min", "p_max", "d", "f_max")
+
+
 def make_network(name: str, seed: int):
     """Return (Network, Problem) for the named recipe and seed."""
+    path = _cache_path(name, seed)
+    if path and os.path.exists(os.path.join(path, "done")):
+        a = {k: np.load(os.path.join(path, k + ".npy"), allow_pickle=False) for k in _CACHED}
+        net = Network(int(a["H"].shape[1]), a["fbus"], a["tbus"], a["b"], 0)
+        net._H = None
+        return net, Problem(H=a["H"], gen_bus=a["gen_bus"], c=a["c"], q=a["q"],
+                            p_min=a["p_min"], p_max=a["p_max"], d=a["d"], f_max=a["f_max"],
+                            slack=0, net=net)
+    net, prob = _make_network(name, seed)
+    if path:
+        os.makedirs(path, exist_ok=True)
+        vals = dict(fbus=net.fbus, tbus=net.tbus, b=net.b, H=prob.H, gen_bus=prob.gen_bus,
+                    c=prob.c, q=prob.q, p_min=prob.p_min, p_max=prob.p_max, d=prob.d,
+                    f_max=prob.f_max)
+        for k in _CACHED:
+            np.save(os.path.join(path, k + ".npy"), vals[k], allow_pickle=False)
+        open(os.path.join(path, "done"), "w").close()
+    return net, prob
+
+
+def _make_network(name: str, seed: int):
     spec = NET_SPECS[name]
     rng = np.random.Generator(np.random.PCG64(seed))
     nb, ng = spec["n_bus"], spec["n_gen"]
