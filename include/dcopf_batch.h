@@ -108,9 +108,17 @@ dcopf_status dcopf_batch_set_multipliers(dcopf_batch_t b, int32_t net, const dou
                                          const double *mu_plus, const double *mu_minus);
 
 /* Tile shapes in use for network `net`: cfg[0], cfg[1] = instances x
- * columns of one W-product workgroup tile, cfg[2] = its K split,
- * cfg[3] = instances * 1000 + lines of one F-product tile.                 */
+ * columns of one W-product workgroup tile, cfg[2] = its K split (over
+ * lines), cfg[3] = instances * 1000 + lines of one F-product tile.         */
 dcopf_status dcopf_batch_info(dcopf_batch_t b, int32_t net, int32_t *cfg, int64_t *iters);
+
+/* Pin the tile shapes of network `net` (cfg[0..3] encoded as in
+ * dcopf_batch_info: tiles 128x64, 64x128 or 32x128; K split 1..32, clamped
+ * to the K extent), e.g. to reuse an earlier autotuning result.  Results do
+ * not depend on the tile shapes; the K split changes only the FP32
+ * summation order.  Rebuilds the tile tables and the captured graph.
+ * Synchronises.                                                            */
+dcopf_status dcopf_batch_set_tiles(dcopf_batch_t b, int32_t net, const int32_t *cfg);
 
 /* Measurement: run n_iters >= 1 real iterations (they advance the batch)
  * with events attached to each dispatch (start and end of that kernel

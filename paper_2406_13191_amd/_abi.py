@@ -266,6 +266,7 @@ def _bind_batch():
         "dcopf_batch_set_multipliers": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double),
                                                   P(C.c_double), P(C.c_double)]),
         "dcopf_batch_info": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int32), P(C.c_int64)]),
+        "dcopf_batch_set_tiles": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int32)]),
         "dcopf_batch_time_phases": (C.c_int, [C.c_void_p, C.c_int64, P(C.c_double)]),
         "dcopf_batch_destroy": (None, [C.c_void_p]),
     }
@@ -383,6 +384,12 @@ class BatchSolver:
                                    C.byref(it)))
         return dict(w_tile=(int(cfg[0]), int(cfg[1])), w_split=int(cfg[2]),
                     f_tile=(int(cfg[3]) // 1000, int(cfg[3]) % 1000), iters=it.value)
+
+    def set_tiles(self, net: int, w_tile, w_split: int, f_tile):
+        """Pin network `net`'s tile shapes, e.g. an earlier ``info(net)``."""
+        cfg = np.array([w_tile[0], w_tile[1], w_split, f_tile[0] * 1000 + f_tile[1]], np.int32)
+        check(lib.dcopf_batch_set_tiles(self._h, int(net),
+                                        cfg.ctypes.data_as(C.POINTER(C.c_int32))))
 
     def time_phases(self, n: int):
         ms = np.zeros(3)

@@ -99,6 +99,24 @@ __device__ __forceinline__ int mfma32_row(int j, int lane) {
   return 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
 }
 
+// load through a global-address-space pointer (global_load rather than
+// flat_load: only the vector memory counter is involved in its waits)
+template <typename T> __device__ __forceinline__ T ldg(const T *p) {
+  return *(const __attribute__((address_space(1))) T *)(p);
+}
+
+// element at a 32-bit byte offset (per-network state arrays are < 4 GiB)
+template <typename T> __device__ __forceinline__ T &at(T *p, unsigned byte_off) {
+  return *reinterpret_cast<T *>(reinterpret_cast<char *>(p) + byte_off);
+}
+template <typename T> __device__ __forceinline__ const T &at(const T *p, unsigned byte_off) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + byte_off);
+}
+
+// largest K split of the W product (the unit pass holds every split's
+// partial of its column in registers)
+constexpr int kMaxSplit = 32;
+
 // ---------------------------------------------------------------------------
 // Workgroup tile of a split-BF16 product, staged through LDS.
 //
@@ -248,34 +266,60 @@ __global__ __launch_bounds__(256) void wgemm_kernel(const BNet *__restrict__ net
 #undef DCOPF_WBODY
 }
 
-// Fold iteration k-1 of instance i (every workgroup of the instance does it
-// identically): sum its unit partials (parity pp) and line terms, form its
-// dual value gamma and take the lambda step from its state slot pp.  Returns
-// the state (lambda, velocity or first moment, second moment) of iteration k.
+// Block-wide deterministic sums of NV values per thread in one pass (three
+// barriers for all of them); every thread gets the sums.  `scratch` holds
+// NV * (blockDim.x / 64) doubles.
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&v)[NV], double *scratch) {
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) v[c] = wave_sum(v[c]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) scratch[c * nw + wave] = v[c];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += scratch[c * nw + w];
+    v[c] = t;
+  }
+  __syncthreads();
+}
+
+// Folding iteration k-1 of instance i: this thread's share of the partial
+// sums it left (sum of p*, sum of phi over unit-pass workgroups of parity pp;
+// line terms of the F product), to be summed over the workgroup.
+__device__ __forceinline__ void fold_partials(const BNet &N, int i, int pp, double (&f)[3]) {
+  const double *up = N.unitpart + (size_t)pp * N.ncb * N.Bp * 2;
+  for (int t = threadIdx.x; t < N.ncb; t += blockDim.x) {
+    f[0] += ldg(up + ((size_t)t * N.Bp + i) * 2);
+    f[1] += ldg(up + ((size_t)t * N.Bp + i) * 2 + 1);
+  }
+  for (int t = threadIdx.x; t < N.ntl; t += blockDim.x)
+    f[2] += ldg(N.linepart + (size_t)t * N.Bp + i);
+}
+
+// The state (lambda, velocity or first moment, second moment) of iteration
+// k from that of iteration k-1 (slot pp) and its sums f = (sum p*, sum phi,
+// line terms), and the dual value gamma of iteration k-1.  Every workgroup
+// of the instance computes it identically.
 struct LamState {
   double lam, v, s, gamma;
 };
 
-__device__ __forceinline__ LamState fold_inst(const BNet &N, int i, int pp, long long k_prev,
-                                              const BParams &prm, double *red) {
-  double ps = 0.0, phis = 0.0, lines = 0.0;
-  const double *up = N.unitpart + (size_t)pp * N.ncb * N.Bp * 2;
-  for (int t = threadIdx.x; t < N.ncb; t += blockDim.x) {
-    ps += up[((size_t)t * N.Bp + i) * 2];
-    phis += up[((size_t)t * N.Bp + i) * 2 + 1];
-  }
-  for (int t = threadIdx.x; t < N.ntl; t += blockDim.x) lines += N.linepart[(size_t)t * N.Bp + i];
-  ps = block_sum(ps, red);
-  phis = block_sum(phis, red);
-  lines = block_sum(lines, red);
+__device__ __forceinline__ LamState fold_finish(const BNet &N, int i, int pp, long long k_prev,
+                                                const BParams &prm, const double (&f)[3]) {
   const double lam = N.lam[(size_t)pp * N.B + i];
   const double v0 = N.vlam[(size_t)pp * N.B + i], s0 = N.slam[(size_t)pp * N.B + i];
   const double D = N.D[i];
   LamState r;
-  r.gamma = phis + lam * D - lines;
+  r.gamma = f[1] + lam * D - f[2];
   const double kk = (double)k_prev;
   const double a = N.alpha / (1.0 + prm.decay * kk);
-  const double g = D - ps;  // balance residual
+  const double g = D - f[0];  // balance residual
   r.v = v0;
   r.s = s0;
   if (prm.rule == DCOPF_RULE_GDM) {
@@ -295,49 +339,78 @@ __device__ __forceinline__ LamState fold_inst(const BNet &N, int i, int pp, long
 
 // ---------------------------------------------------------------------------
 // Unit pass: workgroup (instance i, column block cb) handles columns
-// cb*256 .. cb*256+255, one per thread.  It first folds the previous
-// iteration (every workgroup of the instance identically, so lambda needs no
-// extra launch); workgroup cb = 0 records that instance's lambda state and
-// gamma.  Then w = sum of the K splits, reduced costs, the inner minimiser,
-// the column injections X (BF16 hi/lo), and per-workgroup sums of p* and phi.
+// cb*256 .. cb*256+255, one per thread.  Every load that does not depend on
+// lambda (the K-split partials of w, the column's first unit, the previous
+// iteration's partial sums) is issued before the first wait.  The previous
+// iteration is then folded (every workgroup of the instance identically, so
+// lambda needs no extra launch; workgroup cb = 0 records lambda's state and
+// gamma), and the columns' reduced costs, inner minimiser, injections X
+// (BF16 hi/lo) and per-workgroup sums of p* and phi follow.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ nets,
                                                     const int4 *__restrict__ unit_tab,
                                                     BScal *sc, int par, BParams prm,
                                                     double *__restrict__ gam_ring,
                                                     long long gmask, int n_total) {
-  __shared__ double red[4];
-  __shared__ double lam_s;
+  __shared__ double red[3 * 4];
   const int4 e = unit_tab[blockIdx.x];
   const BNet &N = nets[e.x];
   const int i = e.y, cb = e.z;
   const BIter it = sc->it[par];
-  if (it.pending) {
-    const LamState r = fold_inst(N, i, par ^ 1, it.k - 1, prm, red);
-    if (threadIdx.x == 0) {
-      lam_s = r.lam;
-      if (cb == 0) {
-        N.lam[(size_t)par * N.B + i] = r.lam;
-        N.vlam[(size_t)par * N.B + i] = r.v;
-        N.slam[(size_t)par * N.B + i] = r.s;
-        gam_ring[(size_t)((it.k - 1) & gmask) * n_total + N.inst0 + i] = r.gamma;
-      }
-    }
-  } else if (threadIdx.x == 0) {
-    lam_s = N.lam[(size_t)par * N.B + i];
-  }
-  __syncthreads();
-  const double lam = lam_s;
   const int j = cb * 256 + threadIdx.x;
+  const bool valid = j < N.n_c;
+  // loads are issued unconditionally from clamped (in-range) indices and
+  // masked afterwards, so that none of them waits for another
+  const int jc = valid ? j : 0;
+  int u0 = ldg(N.seg + jc), u1 = ldg(N.seg + jc + 1);
+  if (!valid) u1 = u0;
+  const int uc = u0 < u1 ? u0 : 0;
+  const double *ci = N.c + (size_t)i * N.n_g, *qi = N.q + (size_t)i * N.n_g;
+  const double c0 = ldg(ci + uc), q0 = ldg(qi + uc), lo0 = ldg(N.pmin + uc),
+               hi0 = ldg(N.pmax + uc);
+  // all K-split partials of w at once (S <= kMaxSplit), summed in split order
+  float wpart[kMaxSplit];
+  {
+    const float *wp = N.Wws + (size_t)i * N.ncp + jc;
+    const size_t ss = (size_t)N.Bp * N.ncp;
+#pragma unroll
+    for (int t = 0; t < kMaxSplit; ++t) {
+      const float v = ldg(wp + (t < N.S ? t : 0) * ss);
+      wpart[t] = t < N.S ? v : 0.f;
+    }
+  }
+  double f[3] = {0.0, 0.0, 0.0};
+  if (it.pending) fold_partials(N, i, par ^ 1, f);
+  block_sums<3>(f, red);
+  double w = 0.0;
+#pragma unroll
+  for (int t = 0; t < kMaxSplit; ++t) w += (double)wpart[t];
+  double lam;
+  if (it.pending) {
+    const LamState r = fold_finish(N, i, par ^ 1, it.k - 1, prm, f);
+    lam = r.lam;
+    if (cb == 0 && threadIdx.x == 0) {
+      N.lam[(size_t)par * N.B + i] = r.lam;
+      N.vlam[(size_t)par * N.B + i] = r.v;
+      N.slam[(size_t)par * N.B + i] = r.s;
+      gam_ring[(size_t)((it.k - 1) & gmask) * n_total + N.inst0 + i] = r.gamma;
+    }
+  } else {
+    lam = N.lam[(size_t)par * N.B + i];
+  }
   double x = 0.0, ph = 0.0;
-  if (j < N.n_c) {
-    double w = 0.0;
-    for (int s2 = 0; s2 < N.S; ++s2) w += (double)N.Wws[((size_t)s2 * N.Bp + i) * N.ncp + j];
-    const double *ci = N.c + (size_t)i * N.n_g, *qi = N.q + (size_t)i * N.n_g;
-    for (int u = N.seg[j]; u < N.seg[j + 1]; ++u) {
-      const double r = ci[u] - lam + w;
-      const double p = inner_min_b(r, qi[u], N.pmin[u], N.pmax[u]);
-      ph += r * p + qi[u] * p * p;
+  if (valid) {
+    for (int u = u0; u < u1; ++u) {
+      double cu = c0, qu = q0, lo = lo0, hi = hi0;
+      if (u != u0) {
+        cu = ci[u];
+        qu = qi[u];
+        lo = N.pmin[u];
+        hi = N.pmax[u];
+      }
+      const double r = cu - lam + w;
+      const double p = inner_min_b(r, qu, lo, hi);
+      ph += r * p + qu * p * p;
       x += p;
     }
     __bf16 hi, lo;
@@ -345,12 +418,12 @@ __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ net
     N.X_hi[(size_t)i * N.ldc + j] = hi;
     N.X_lo[(size_t)i * N.ldc + j] = lo;
   }
-  const double ps = block_sum(x, red);
-  const double phs = block_sum(ph, red);
+  double sums[2] = {x, ph};
+  block_sums<2>(sums, red);
   if (threadIdx.x == 0) {
     double *up = N.unitpart + (size_t)par * N.ncb * N.Bp * 2 + ((size_t)cb * N.Bp + i) * 2;
-    up[0] = ps;
-    up[1] = phs;
+    up[0] = sums[0];
+    up[1] = sums[1];
     if (blockIdx.x == 0) {
       BIter nx;
       nx.k = it.k + 1;
@@ -367,13 +440,6 @@ __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ net
 // rows of an accumulator whose state is loaded before any of it is stored
 constexpr int kEpiChunk = 8;
 
-// element at a 32-bit byte offset (per-network state arrays are < 4 GiB)
-template <typename T> __device__ __forceinline__ T &at(T *p, unsigned byte_off) {
-  return *reinterpret_cast<T *>(reinterpret_cast<char *>(p) + byte_off);
-}
-template <typename T> __device__ __forceinline__ const T &at(const T *p, unsigned byte_off) {
-  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + byte_off);
-}
 
 template <int BM, int BN, int WM, int WN, bool LOLO>
 __device__ __forceinline__ void fgemm_body(const BNet &N, int4 t, const BScal *sc, int par,
@@ -524,11 +590,14 @@ __global__ __launch_bounds__(256) void bfinal_kernel(const BNet *__restrict__ ne
                                                      BScal *sc, int pp, long long k_prev,
                                                      BParams prm, double *__restrict__ gam_ring,
                                                      long long gmask, int n_total) {
-  __shared__ double red[4];
+  __shared__ double red[3 * 4];
   const int2 e = inst_tab[blockIdx.x];
   const BNet &N = nets[e.x];
   const int i = e.y;
-  const LamState r = fold_inst(N, i, pp, k_prev, prm, red);
+  double f[3] = {0.0, 0.0, 0.0};
+  fold_partials(N, i, pp, f);
+  block_sums<3>(f, red);
+  const LamState r = fold_finish(N, i, pp, k_prev, prm, f);
   if (threadIdx.x == 0) {
     const int np = pp ^ 1;
     N.lam[(size_t)np * N.B + i] = r.lam;
@@ -779,7 +848,7 @@ void build_tables(const std::vector<HostNet> &nets, const std::vector<int> &whic
 
 void set_split(BNet &N, int S) {
   const int kblocks = N.ldl / 64;
-  S = std::max(1, std::min(S, kblocks));
+  S = std::max(1, std::min(std::min(S, kblocks), kMaxSplit));
   N.kchunk = (kblocks + S - 1) / S * 64;
   N.S = (N.ldl + N.kchunk - 1) / N.kchunk;
 }
@@ -891,6 +960,26 @@ hipError_t upload_tables(dcopf_batch_s *b) {
 }
 
 // time `reps` launches of one phase for network k alone (ms per launch)
+// (Re)capture graph_iters iterations (an even count, so the parity slots
+// line up on every replay) as one HIP graph; the tile tables are baked in.
+hipError_t capture_graph(dcopf_batch_s *b) {
+  if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->graph_exec = nullptr;
+  b->graph = nullptr;
+  if (b->graph_iters <= 0) return hipSuccess;
+  hipStream_t cs = nullptr;
+  hipError_t ce = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (ce == hipSuccess) ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (ce == hipSuccess) {
+    launch_iters_b(b, cs, 0, b->graph_iters);
+    ce = hipStreamEndCapture(cs, &b->graph);
+  }
+  if (ce == hipSuccess) ce = hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0);
+  if (cs) (void)hipStreamDestroy(cs);
+  return ce;
+}
+
 // average ms of one whole iteration (every network, the three launches);
 // the best of three runs of `reps` iterations
 float time_iters(dcopf_batch_s *b, int reps) {
@@ -1262,21 +1351,11 @@ dcopf_status dcopf_batch_create(const dcopf_batch_network *nets, int32_t n_nets,
   b->best.assign(total, -INFINITY);
   b->best_iter.assign(total, -1);
   b->graph_iters = (o.graph_iters + 1) / 2 * 2;
-  if (b->graph_iters > 0) {
-    hipStream_t cs = nullptr;
-    hipError_t ce = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (ce == hipSuccess) ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (ce == hipSuccess) {
-      launch_iters_b(b, cs, 0, b->graph_iters);
-      ce = hipStreamEndCapture(cs, &b->graph);
-    }
-    if (ce == hipSuccess) ce = hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0);
-    if (cs) (void)hipStreamDestroy(cs);
-    if (ce != hipSuccess) {
-      set_error(std::string("graph capture failed: ") + hipGetErrorString(ce));
-      free_batch(b);
-      return DCOPF_E_HIP;
-    }
+  hipError_t ce = capture_graph(b);
+  if (ce != hipSuccess) {
+    set_error(std::string("graph capture failed: ") + hipGetErrorString(ce));
+    free_batch(b);
+    return DCOPF_E_HIP;
   }
   *out = b;
   return DCOPF_OK;
@@ -1437,6 +1516,29 @@ dcopf_status dcopf_batch_info(dcopf_batch_t b, int32_t net, int32_t *cfg, int64_
     cfg[3] = kTileBM[N.cfg_f] * 1000 + kTileBN[N.cfg_f];
   }
   if (iters) *iters = b->iters;
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_set_tiles(dcopf_batch_t b, int32_t net, const int32_t *cfg) {
+  if (!b || !cfg || net < 0 || net >= (int)b->nets.size())
+    return set_error("bad arguments"), DCOPF_E_INVALID;
+  auto code = [](int bm, int bn) {
+    for (int c = 0; c < 3; ++c)
+      if (kTileBM[c] == bm && kTileBN[c] == bn) return c;
+    return -1;
+  };
+  const int cw = code(cfg[0], cfg[1]), cf = code(cfg[3] / 1000, cfg[3] % 1000);
+  if (cw < 0 || cf < 0) return set_error("unsupported tile shape"), DCOPF_E_INVALID;
+  if (cfg[2] < 1 || cfg[2] > kMaxSplit)
+    return set_error("K split must be in [1, 32]"), DCOPF_E_INVALID;
+  DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
+  BNet &N = b->nets[net].d;
+  N.cfg_w = cw;
+  N.cfg_f = cf;
+  set_split(N, cfg[2]);
+  DCOPF_HIP_TRY(upload_nets(b));
+  DCOPF_HIP_TRY(upload_tables(b));
+  DCOPF_HIP_TRY(capture_graph(b));
   return DCOPF_OK;
 }
 

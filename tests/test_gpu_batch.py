@@ -249,6 +249,35 @@ def test_set_multipliers_keeps_other_networks():
             np.testing.assert_array_equal(x, y)
 
 
+def test_tile_shapes_are_bitwise_equal_and_splits_agree():
+    # per output element the K order is the same in every tile shape, so
+    # pinned shapes give identical results; a different K split only changes
+    # the FP32 summation order
+    A = _abi()
+    n1, _ = batch_net("geo300q", 7, 40, 5400)
+    shapes = [(128, 64), (64, 128), (32, 128)]
+    with A.BatchSolver([n1]) as ref_b:
+        ref_b.step(9)
+        ref_m = ref_b.get_multipliers(0)
+        split = ref_b.info(0)["w_split"]
+    for w in shapes:
+        for f in shapes:
+            with A.BatchSolver([n1]) as b:
+                b.set_tiles(0, w, split, f)
+                info = b.info(0)
+                assert info["w_tile"] == w and info["f_tile"] == f
+                b.step(9)
+                for x, y in zip(ref_m, b.get_multipliers(0)):
+                    np.testing.assert_array_equal(x, y)
+    scale = max(np.abs(ref_m[1]).max(), np.abs(ref_m[2]).max(), 1.0)
+    with A.BatchSolver([n1]) as b:
+        b.set_tiles(0, (32, 128), 4, (32, 128), 1)
+        b.step(9)
+        lam, mp, mm = b.get_multipliers(0)
+    assert np.abs(mp - ref_m[1]).max() <= 1e-4 * scale
+    assert np.abs(lam - ref_m[0]).max() <= 1e-5 * np.abs(ref_m[0]).max()
+
+
 def test_batched_qp_tracks_oracle_trajectory():
     """Continuous (QP) map: 200 batched iterations stay close to the FP64
     oracle trajectory of each instance."""
