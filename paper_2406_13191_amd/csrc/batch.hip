@@ -99,12 +99,6 @@ __device__ __forceinline__ int mfma32_row(int j, int lane) {
   return 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
 }
 
-// load through a global-address-space pointer (global_load rather than
-// flat_load: only the vector memory counter is involved in its waits)
-template <typename T> __device__ __forceinline__ T ldg(const T *p) {
-  return *(const __attribute__((address_space(1))) T *)(p);
-}
-
 // element at a 32-bit byte offset (per-network state arrays are < 4 GiB)
 template <typename T> __device__ __forceinline__ T &at(T *p, unsigned byte_off) {
   return *reinterpret_cast<T *>(reinterpret_cast<char *>(p) + byte_off);
@@ -266,29 +260,6 @@ __global__ __launch_bounds__(256) void wgemm_kernel(const BNet *__restrict__ net
 #undef DCOPF_WBODY
 }
 
-// Block-wide deterministic sums of NV values per thread in one pass (three
-// barriers for all of them); every thread gets the sums.  `scratch` holds
-// NV * (blockDim.x / 64) doubles.
-template <int NV>
-__device__ __forceinline__ void block_sums(double (&v)[NV], double *scratch) {
-  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  const int nw = blockDim.x / kWave;
-#pragma unroll
-  for (int c = 0; c < NV; ++c) v[c] = wave_sum(v[c]);
-  __syncthreads();
-  if (lane == 0)
-#pragma unroll
-    for (int c = 0; c < NV; ++c) scratch[c * nw + wave] = v[c];
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    double t = 0.0;
-    for (int w = 0; w < nw; ++w) t += scratch[c * nw + w];
-    v[c] = t;
-  }
-  __syncthreads();
-}
-
 // Folding iteration k-1 of instance i: this thread's share of the partial
 // sums it left (sum of p*, sum of phi over unit-pass workgroups of parity pp;
 // line terms of the F product), to be summed over the workgroup.
@@ -318,7 +289,7 @@ __device__ __forceinline__ LamState fold_finish(const BNet &N, int i, int pp, lo
   LamState r;
   r.gamma = f[1] + lam * D - f[2];
   const double kk = (double)k_prev;
-  const double a = N.alpha / (1.0 + prm.decay * kk);
+  const double a = (prm.decay == 0.0 ? N.alpha : N.alpha / (1.0 + prm.decay * kk));
   const double g = D - f[0];  // balance residual
   r.v = v0;
   r.s = s0;
@@ -459,10 +430,14 @@ __device__ __forceinline__ void fgemm_body(const BNet &N, int4 t, const BScal *s
                                  N.P_lo + (size_t)n0 * N.ldc, N.ldc, 0, N.ldc, sm, acc);
   const long long k = sc->it[par].k;
   const double kk = (double)k;
-  const float a = (float)(N.alpha / (1.0 + prm.decay * kk));
+  const float a = (float)((prm.decay == 0.0 ? N.alpha : N.alpha / (1.0 + prm.decay * kk)));
   const float rho = (float)N.rho;
-  const float c1 = (float)(1.0 - pow(prm.beta1, kk + 1.0));
-  const float c2 = (float)(1.0 - pow(prm.beta2, kk + 1.0));
+  // Adam's bias corrections (pow is costly; the other rules skip it)
+  float c1 = 1.f, c2 = 1.f;
+  if (prm.rule == DCOPF_RULE_ADAM) {
+    c1 = (float)(1.0 - pow(prm.beta1, kk + 1.0));
+    c2 = (float)(1.0 - pow(prm.beta2, kk + 1.0));
+  }
   const float b1 = (float)prm.beta1, b2 = (float)prm.beta2, eps = (float)prm.eps;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / WN, wn = wave % WN;

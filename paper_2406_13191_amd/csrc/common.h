@@ -80,6 +80,35 @@ template <typename T> __device__ __forceinline__ T block_sum(T v, T *scratch) {
   return s;
 }
 
+// Block-wide deterministic sums of NV values per thread in one pass (three
+// barriers for all of them); every thread gets the sums.  `scratch` holds
+// NV * (blockDim.x / 64) doubles.
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&v)[NV], double *scratch) {
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) v[c] = wave_sum(v[c]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) scratch[c * nw + wave] = v[c];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += scratch[c * nw + w];
+    v[c] = t;
+  }
+  __syncthreads();
+}
+
+// load through a global-address-space pointer (global_load rather than
+// flat_load: only the vector memory counter is involved in its waits)
+template <typename T> __device__ __forceinline__ T ldg(const T *p) {
+  return *(const __attribute__((address_space(1))) T *)(p);
+}
+
 // Agent-scope loads/stores for values exchanged between workgroups of one
 // launch (cross-XCD visibility).
 template <typename T> __device__ __forceinline__ void store_agent(T *p, T v) {

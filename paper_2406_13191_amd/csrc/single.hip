@@ -101,9 +101,13 @@ __device__ __forceinline__ IterSlot fold(const IterSlot &prev, double psum, doub
 __device__ __forceinline__ void set_step(IterSlot &s, long long k, const StepParams &prm) {
   const double kk = (double)k;
   s.k = k;
-  s.alpha = prm.alpha / (1.0 + prm.decay * kk);
-  s.c1 = 1.0 - pow(prm.beta1, kk + 1.0);
-  s.c2 = 1.0 - pow(prm.beta2, kk + 1.0);
+  s.alpha = prm.decay == 0.0 ? prm.alpha : prm.alpha / (1.0 + prm.decay * kk);
+  // Adam's bias corrections; pow is costly, the other rules skip it
+  s.c1 = s.c2 = 1.0;
+  if (prm.rule == DCOPF_RULE_ADAM) {
+    s.c1 = 1.0 - pow(prm.beta1, kk + 1.0);
+    s.c2 = 1.0 - pow(prm.beta2, kk + 1.0);
+  }
 }
 
 // Sum (in index order, deterministic) the partials the previous iteration
@@ -154,6 +158,30 @@ __device__ __forceinline__ void stage_vec(T *dst, const T *src, int ld) {
 // wave sums of p* (the column injection) and phi.  Every lane gets the sums.
 // Unit data is stored column-sorted: the units of column j are
 // seg[j] .. seg[j+1] - 1.
+// Units of column j handled lane-parallel by one wavefront: lane l takes
+// units g0 + l, g0 + l + 64, ...  The data of the lane's first unit (cf, qf,
+// lof, hif; valid when g0 + lane < g1) were loaded earlier.
+__device__ __forceinline__ void column_units(double w, double lam, int g0, int g1, double cf,
+                                             double qf, double lof, double hif,
+                                             const double *__restrict__ c,
+                                             const double *__restrict__ q,
+                                             const double *__restrict__ pmin,
+                                             const double *__restrict__ pmax, int lane,
+                                             double *xj, double *phij) {
+  double xs = 0.0, ph = 0.0;
+  for (int t = g0 + lane; t < g1; t += kWave) {
+    const bool first = t == g0 + lane;
+    const double ct = first ? cf : c[t], qt = first ? qf : q[t];
+    const double r = ct - lam + w;
+    const double p = inner_min(r, qt, first ? lof : pmin[t], first ? hif : pmax[t]);
+    ph += r * p + qt * p * p;
+    xs += p;
+  }
+  *xj = wave_sum(xs);
+  *phij = wave_sum(ph);
+}
+
+// The same for column j, loading everything here.
 __device__ __forceinline__ void column_units(int j, double w, double lam,
                                              const int *__restrict__ seg,
                                              const double *__restrict__ c,
@@ -162,16 +190,36 @@ __device__ __forceinline__ void column_units(int j, double w, double lam,
                                              const double *__restrict__ pmax, int lane,
                                              double *xj, double *phij) {
   const int g0 = seg[j], g1 = seg[j + 1];
-  double xs = 0.0, ph = 0.0;
-  for (int t = g0 + lane; t < g1; t += kWave) {
-    const double r = c[t] - lam + w;
-    const double p = inner_min(r, q[t], pmin[t], pmax[t]);
-    ph += r * p + q[t] * p * p;
-    xs += p;
-  }
-  *xj = wave_sum(xs);
-  *phij = wave_sum(ph);
+  const int tf = g0 + lane < g1 ? g0 + lane : 0;
+  column_units(w, lam, g0, g1, c[tf], q[tf], pmin[tf], pmax[tf], c, q, pmin, pmax, lane, xj,
+               phij);
 }
+
+// Partials of a previous launch, n of them (index idx, element a[idx *
+// stride + off]), summed over the workgroup's threads (idx = threadIdx.x +
+// m blockDim.x).  load() issues the first kPre loads from clamped indices
+// without waiting; sum() adds them and any further terms.
+constexpr int kPre = 4;
+struct StridedSum {
+  double v[kPre];
+  __device__ __forceinline__ void load(const double *__restrict__ a, int n, int stride, int off) {
+#pragma unroll
+    for (int m = 0; m < kPre; ++m) {
+      const int idx = threadIdx.x + m * blockDim.x;
+      v[m] = ldg(a + (size_t)(idx < n ? idx : 0) * stride + off);
+    }
+  }
+  __device__ __forceinline__ double sum(const double *__restrict__ a, int n, int stride,
+                                        int off) const {
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < kPre; ++m)
+      if (threadIdx.x + m * blockDim.x < n) s += v[m];
+    for (int idx = threadIdx.x + kPre * blockDim.x; idx < n; idx += blockDim.x)
+      s += a[(size_t)idx * stride + off];
+    return s;
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Column pass of iteration k (parity par = k & 1).  A workgroup owns CB
@@ -181,8 +229,14 @@ __device__ __forceinline__ void column_units(int j, double w, double lam,
 // iteration k-1 (identically, from its partials) to obtain the lambda of
 // iteration k; workgroup 0 records it.  Wavefront c then handles the units
 // of column c lane-parallel and writes the injection x_j.
+//
+// Memory round trips are the cost for panels of a few MB, so the loads are
+// ordered by dependence: the unit boundaries first, then the partials of
+// iteration k-1 and (UNR > 0: every chunk, at most UNR per lane) the panel
+// and v chunks, then the data of each lane's first unit, which waits only
+// for the boundaries.  UNR = 0 streams larger panels in a loop.
 // ---------------------------------------------------------------------------
-template <typename T, int CB>
+template <typename T, int CB, int UNR>
 __global__ __launch_bounds__(256) void colpass_kernel(
     const T *__restrict__ PT, int n_cols, int ldl, const T *__restrict__ vvec,
     const int *__restrict__ seg, const double *__restrict__ c, const double *__restrict__ q,
@@ -190,63 +244,98 @@ __global__ __launch_bounds__(256) void colpass_kernel(
     T *__restrict__ x_out, double *__restrict__ part_a, int ga, const double *__restrict__ part_b,
     int gb, StepParams prm, double *__restrict__ gam_buf, long long gam_mask) {
   using V = typename Vec16<T>::type;
-  __shared__ double red[4];
+  __shared__ double red[3 * 4];
   __shared__ double lam_s;
   __shared__ T dots[4][CB];
   __shared__ double colsum[2][4];
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int j0 = blockIdx.x * CB;
+  // (1) units of this wavefront's column (wavefronts c < CB own column j0 + c)
+  const bool unit_wave = wave < CB && j0 + wave < n_cols;
+  const int jw = unit_wave ? j0 + wave : 0;
+  const int g0 = ldg(seg + jw), g1 = ldg(seg + jw + 1);
+  // (2) the previous iteration's partials (loaded whether or not they are
+  // pending: the buffers always exist; unused values are dropped)
   const IterSlot prev = sc->slot[par ^ 1];
-  // the previous iteration's partials: loads issued now, summed after the products
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  if (prev.pending) {
-    const double *pa = part_a + (size_t)(par ^ 1) * 2 * ga;
-    const double *pb = part_b + (size_t)(par ^ 1) * gb;
-    for (int b = threadIdx.x; b < ga; b += blockDim.x) {
-      s0 += pa[2 * b];
-      s1 += pa[2 * b + 1];
-    }
-    for (int b = threadIdx.x; b < gb; b += blockDim.x) s2 += pb[b];
-  }
-  // quarter of every owned row: chunks [cb, ce) of nv 16-byte chunks
+  const double *pa = part_a + (size_t)(par ^ 1) * 2 * ga;
+  const double *pb = part_b + (size_t)(par ^ 1) * gb;
+  StridedSum f0, f1, f2;
+  f0.load(pa, ga, 2, 0);
+  f1.load(pa, ga, 2, 1);
+  f2.load(pb, gb, 1, 0);
+  // (3) quarter of every owned row: chunks [cb, ce) of nv 16-byte chunks
   const int nv = ldl / Vec16<T>::n;
   const int quarter = (nv + 3) / 4;
   const int cb = wave * quarter, ce = min(nv, cb + quarter);
-  const int j0 = blockIdx.x * CB;
   const V *vv = reinterpret_cast<const V *>(vvec);
-  T acc[CB], acc2[CB];
+  T acc[CB];
 #pragma unroll
-  for (int u = 0; u < CB; ++u) acc[u] = acc2[u] = (T)0;
-  int i = cb + lane;
-  for (; i + kWave < ce; i += 2 * kWave) {
-    const V x0 = vv[i], x1 = vv[i + kWave];
+  for (int u = 0; u < CB; ++u) acc[u] = (T)0;
+  const V *rows[CB];
 #pragma unroll
-    for (int u = 0; u < CB; ++u)
-      if (j0 + u < n_cols) {
-        const V *row = reinterpret_cast<const V *>(PT + (size_t)(j0 + u) * ldl);
-        acc[u] = fma_vec(__builtin_nontemporal_load(row + i), x0, acc[u]);
-        acc2[u] = fma_vec(__builtin_nontemporal_load(row + i + kWave), x1, acc2[u]);
+  for (int u = 0; u < CB; ++u)
+    rows[u] = reinterpret_cast<const V *>(PT + (size_t)min(j0 + u, n_cols - 1) * ldl);
+  double cf = 0.0, qf = 0.0, lof = 0.0, hif = 0.0;
+  const int tf = g0 + lane < g1 ? g0 + lane : 0;
+  if (UNR > 0) {
+    V pv[UNR > 0 ? UNR : 1][CB], xv[UNR > 0 ? UNR : 1];
+#pragma unroll
+    for (int m = 0; m < UNR; ++m) {
+      const int i = cb + lane + m * kWave;
+      const int ic = i < ce ? i : 0;
+      xv[m] = vv[ic];
+#pragma unroll
+      for (int u = 0; u < CB; ++u) pv[m][u] = __builtin_nontemporal_load(rows[u] + ic);
+    }
+    // (4) the lane's first unit: waits for the boundaries only
+    cf = ldg(c + tf);
+    qf = ldg(q + tf);
+    lof = ldg(pmin + tf);
+    hif = ldg(pmax + tf);
+#pragma unroll
+    for (int m = 0; m < UNR; ++m)
+      if (cb + lane + m * kWave < ce)
+#pragma unroll
+        for (int u = 0; u < CB; ++u) acc[u] = fma_vec(pv[m][u], xv[m], acc[u]);
+  } else {
+    T acc2[CB];
+#pragma unroll
+    for (int u = 0; u < CB; ++u) acc2[u] = (T)0;
+    int i = cb + lane;
+    for (; i + kWave < ce; i += 2 * kWave) {
+      const V x0 = vv[i], x1 = vv[i + kWave];
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        acc[u] = fma_vec(__builtin_nontemporal_load(rows[u] + i), x0, acc[u]);
+        acc2[u] = fma_vec(__builtin_nontemporal_load(rows[u] + i + kWave), x1, acc2[u]);
       }
-  }
-  if (i < ce) {
-    const V x0 = vv[i];
+    }
+    if (i < ce) {
+      const V x0 = vv[i];
 #pragma unroll
-    for (int u = 0; u < CB; ++u)
-      if (j0 + u < n_cols) {
-        const V *row = reinterpret_cast<const V *>(PT + (size_t)(j0 + u) * ldl);
-        acc[u] = fma_vec(__builtin_nontemporal_load(row + i), x0, acc[u]);
-      }
+      for (int u = 0; u < CB; ++u)
+        acc[u] = fma_vec(__builtin_nontemporal_load(rows[u] + i), x0, acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < CB; ++u) acc[u] += acc2[u];
+    cf = ldg(c + tf);
+    qf = ldg(q + tf);
+    lof = ldg(pmin + tf);
+    hif = ldg(pmax + tf);
   }
 #pragma unroll
   for (int u = 0; u < CB; ++u) {
-    const T d = wave_sum(acc[u] + acc2[u]);
+    const T d = wave_sum(acc[u]);
     if (lane == 0) dots[wave][u] = d;
   }
-  double ps = 0.0, phis = 0.0, lines = 0.0;
+  double fsum[3] = {0.0, 0.0, 0.0};
   if (prev.pending) {
-    ps = block_sum(s0, red);
-    phis = block_sum(s1, red);
-    lines = block_sum(s2, red);
+    fsum[0] = f0.sum(pa, ga, 2, 0);
+    fsum[1] = f1.sum(pa, ga, 2, 1);
+    fsum[2] = f2.sum(pb, gb, 1, 0);
+    block_sums<3>(fsum, red);
   }
+  const double ps = fsum[0], phis = fsum[1], lines = fsum[2];
   if (threadIdx.x == 0) {
     IterSlot cur = prev;
     double gam = 0.0;
@@ -264,12 +353,11 @@ __global__ __launch_bounds__(256) void colpass_kernel(
   }
   __syncthreads();
   double xsum = 0.0, phsum = 0.0;
-  if (wave < CB && j0 + wave < n_cols) {
-    const int j = j0 + wave;
+  if (unit_wave) {
     const double w = (double)(((dots[0][wave] + dots[1][wave]) + dots[2][wave]) + dots[3][wave]);
     double xj, phij;
-    column_units(j, w, lam_s, seg, c, q, pmin, pmax, lane, &xj, &phij);
-    if (lane == 0) x_out[j] = (T)xj;
+    column_units(w, lam_s, g0, g1, cf, qf, lof, hif, c, q, pmin, pmax, lane, &xj, &phij);
+    if (lane == 0) x_out[jw] = (T)xj;
     xsum = xj;
     phsum = phij;
   }
@@ -308,18 +396,12 @@ __global__ __launch_bounds__(256) void linepass_kernel(
   // prefetch the state of line base + lane
   const int l = base + lane;
   const bool mine = lane < RW && l < n_lines;
-  double fdl = 0, fl = 0, mp = 0, mm = 0, vp = 0, vm = 0, sp = 0, sm = 0;
-  if (mine) {
-    fdl = fd[l];
-    fl = flim[l];
-    mp = mu_p[l];
-    mm = mu_m[l];
-    vp = v_p[l];
-    vm = v_m[l];
-    if (prm.rule != DCOPF_RULE_GDM) {
-      sp = s_p[l];
-      sm = s_m[l];
-    }
+  const int lc = mine ? l : 0;  // loads from a valid line; results kept only when mine
+  double fdl = ldg(fd + lc), fl = ldg(flim + lc), mp = ldg(mu_p + lc), mm = ldg(mu_m + lc),
+         vp = ldg(v_p + lc), vm = ldg(v_m + lc), sp = 0, sm = 0;
+  if (prm.rule != DCOPF_RULE_GDM) {
+    sp = ldg(s_p + lc);
+    sm = ldg(s_m + lc);
   }
   const IterSlot cur = sc->slot[par];
   const int nv = ldc / Vec16<T>::n;
@@ -327,26 +409,32 @@ __global__ __launch_bounds__(256) void linepass_kernel(
   if (XR > 0) {
     // narrow panel: the x chunks this lane needs (the same for every row)
     // are held in registers, no LDS staging and no barrier
+    // Every load is issued from a clamped (in-range) index before the first
+    // wait; out-of-range terms are masked afterwards.
     using V = typename Vec16<T>::type;
     const V *xv = reinterpret_cast<const V *>(x_in);
-    V xr[XR > 0 ? XR : 1];
+    V xr[XR > 0 ? XR : 1], pr[RW][XR > 0 ? XR : 1];
 #pragma unroll
     for (int u = 0; u < XR; ++u) {
       const int idx = lane + u * kWave;
-      if (idx < nv) xr[u] = xv[idx];
+      xr[u] = xv[idx < nv ? idx : 0];
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const V *row = reinterpret_cast<const V *>(P + (size_t)min(base + r, n_lines - 1) * ldc);
+#pragma unroll
+      for (int u = 0; u < XR; ++u) {
+        const int idx = lane + u * kWave;
+        pr[r][u] = __builtin_nontemporal_load(row + (idx < nv ? idx : 0));
+      }
     }
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
       T a = (T)0;
-      if (base + r < n_lines) {
-        const V *row = reinterpret_cast<const V *>(P + (size_t)(base + r) * ldc);
 #pragma unroll
-        for (int u = 0; u < XR; ++u) {
-          const int idx = lane + u * kWave;
-          if (idx < nv) a = fma_vec(__builtin_nontemporal_load(row + idx), xr[u], a);
-        }
-      }
-      acc[r] = a;
+      for (int u = 0; u < XR; ++u)
+        if (lane + u * kWave < nv) a = fma_vec(pr[r][u], xr[u], a);
+      acc[r] = base + r < n_lines ? a : (T)0;
     }
   } else {
     const T *xs = x_in;
@@ -615,20 +703,29 @@ namespace {
 
 constexpr int kLineRows = 4;  // lines per wavefront in the line pass
 
-template <typename T, int CB>
+template <typename T, int CB, int UNR>
 void launch_colpass_cb(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hipEvent_t e1) {
   T *PT = std::is_same<T, float>::value ? (T *)h->P32T : (T *)h->P64T;
-  (void)launch_k(colpass_kernel<T, CB>, dim3(h->grid_col), dim3(256), 0, s, e0, e1, PT,
+  (void)launch_k(colpass_kernel<T, CB, UNR>, dim3(h->grid_col), dim3(256), 0, s, e0, e1, PT,
                  h->n_cols, h->ldl, (T *)h->vbuf, h->seg, h->c, h->q, h->pmin, h->pmax, h->sc,
                  par, (T *)h->xbuf, h->part_a, h->grid_col, h->part_b, h->grid_line, h->prm,
                  h->gam, kGamCap - 1);
 }
 
+// one column per workgroup and a quarter of at most 8 chunks per lane: every
+// panel load is issued before the first wait
 template <typename T>
 void launch_colpass(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hipEvent_t e1) {
-  if (h->col_cb == 1) launch_colpass_cb<T, 1>(h, s, par, e0, e1);
-  else if (h->col_cb == 2) launch_colpass_cb<T, 2>(h, s, par, e0, e1);
-  else launch_colpass_cb<T, 4>(h, s, par, e0, e1);
+  const int quarter = (h->ldl / Vec16<T>::n + 3) / 4;
+  if (h->col_cb == 1) {
+    if (quarter <= 4 * kWave) launch_colpass_cb<T, 1, 4>(h, s, par, e0, e1);
+    else if (quarter <= 8 * kWave) launch_colpass_cb<T, 1, 8>(h, s, par, e0, e1);
+    else launch_colpass_cb<T, 1, 0>(h, s, par, e0, e1);
+  } else if (h->col_cb == 2) {
+    launch_colpass_cb<T, 2, 0>(h, s, par, e0, e1);
+  } else {
+    launch_colpass_cb<T, 4, 0>(h, s, par, e0, e1);
+  }
 }
 
 template <typename T>

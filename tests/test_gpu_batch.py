@@ -271,7 +271,7 @@ def test_tile_shapes_are_bitwise_equal_and_splits_agree():
                     np.testing.assert_array_equal(x, y)
     scale = max(np.abs(ref_m[1]).max(), np.abs(ref_m[2]).max(), 1.0)
     with A.BatchSolver([n1]) as b:
-        b.set_tiles(0, (32, 128), 4, (32, 128), 1)
+        b.set_tiles(0, (32, 128), 4, (32, 128))
         b.step(9)
         lam, mp, mm = b.get_multipliers(0)
     assert np.abs(mp - ref_m[1]).max() <= 1e-4 * scale
