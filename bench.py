@@ -120,8 +120,12 @@ def bench_mixed(args, stream):
         nets.append(_abi.BatchNetwork(base, Dm, Cc, Q if base.is_qp else None,
                                       alpha=r["alpha"], rho=r["rho"]))
         shapes.append((name, base.n_line, len(np.unique(base.gen_bus)), base.n_gen, B))
-    b = _abi.BatchSolver(nets, stream=stream.cuda_stream, autotune=True, graph_iters=20,
-                         gamma_cap=64)
+    pinned = json.loads(args.tiles) if args.tiles else None
+    b = _abi.BatchSolver(nets, stream=stream.cuda_stream, autotune=pinned is None,
+                         graph_iters=20, gamma_cap=64)
+    if pinned:
+        for k, t in enumerate(pinned):
+            b.set_tiles(k, t["w_tile"], t["w_split"], t["f_tile"])
     n_total = b.n_total
     b.step(args.warmup)
     torch.cuda.synchronize()
@@ -204,10 +208,11 @@ def bench_warmstart(args, stream):
     r = synth.STEP_RULES["bus2000"]
     Dtr, _, _ = synth.make_scenarios(base, 5_000_000, args.train, 0.15, 0.0)
     Dev, _, _ = synth.make_scenarios(base, 6_000_000, args.eval, 0.15, 0.0)
-    (T, tb), t_data = W.timed(W.cold_solve, base, Dtr, args.target_iters, r["alpha"], r["rho"],
-                              stream.cuda_stream)
+    log(f"targets: {args.train} cold solves of {args.target_iters} iterations")
+    (T, tb, te), t_data = W.timed(W.cold_solve, base, Dtr, args.target_iters, r["alpha"],
+                                  r["rho"], stream.cuda_stream)
     cost_ub = float(np.sum(np.maximum(base.c * base.p_min, base.c * base.p_max)))
-    ok = np.isfinite(tb) & (tb <= cost_ub) & np.all(np.isfinite(T), axis=1)
+    ok = W.settled(tb, te, cost_ub) & np.all(np.isfinite(T), axis=1)
     log(f"targets: {ok.sum()} of {ok.size} scenarios kept, {t_data:.1f} s")
     Dtr, T = Dtr[ok], T[ok]
     sx, st = W.Standardizer.fit(Dtr), W.Standardizer.fit(T)
@@ -221,16 +226,24 @@ def bench_warmstart(args, stream):
     losses, t_train = W.timed(W.train, model, X, Y, args.epochs, 256, 1e-3, 0, 0.9, log)
     start = W.predict(model, Dev, sx, st, base.n_line)
     model.close()
+    opt = []
     with mp.get_context("spawn").Pool(16) as pool:
-        opt = np.array(pool.map(_highs_opt, [(net, base.replace(d=Dev[i]))
-                                             for i in range(Dev.shape[0])]))
+        for o in pool.imap(_highs_opt, [(net, base.replace(d=Dev[i]))
+                                        for i in range(Dev.shape[0])], chunksize=16):
+            opt.append(o)
+            if len(opt) % 512 == 0:
+                log(f"HiGHS optima: {len(opt)} of {Dev.shape[0]}")
+    opt = np.array(opt)
     keep = np.isfinite(opt)
     Dev, opt = Dev[keep], opt[keep]
     start = tuple(a[keep] for a in start)
+    log(f"{int(keep.sum())} held-out scenarios with an optimum; cold solves")
     (hc, pc), t_cold = W.timed(W.run_to_gap, base, Dev, opt, r["alpha"], r["rho"], None,
                                args.max_iters, 10, 100, stream.cuda_stream)
+    log(f"cold: {t_cold:.1f} s; warm solves")
     (hw, pw), t_warm = W.timed(W.run_to_gap, base, Dev, opt, r["alpha"], r["rho"], start,
                                args.max_iters, 10, 100, stream.cuda_stream)
+    log(f"warm: {t_warm:.1f} s")
     hf, used = W.combine_with_fallback(hc, pc, hw, pw, 100)
     flops = 6.0 * 256 * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
     return dict(
@@ -257,6 +270,9 @@ def main():
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--target-iters", type=int, default=5000)
     ap.add_argument("--max-iters", type=int, default=5000)
+    ap.add_argument("--tiles", default=None,
+                    help="mixed batch: JSON list of per-network tiles (the 'tiles' of an "
+                         "earlier run's config) to pin instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the single-instance path does not shard "

@@ -44,21 +44,36 @@ class Standardizer:
         return a * self.std + self.mean
 
 
-def cold_solve(base, D, iters, alpha, rho, stream=None, chunk=8192):
+def cold_solve(base, D, iters, alpha, rho, stream=None, chunk=8192, trend_window=1000):
     """Multipliers after ``iters`` cold-start GDM iterations for every load
     scenario D [B, n_bus] (batched GPU solves, chunks of ``chunk``).
-    Returns (targets [B, 2 n_line + 1] = [mu+, mu-, lambda], exact bounds)."""
-    out, bounds = [], []
+    Returns (targets [B, 2 n_line + 1] = [mu+, mu-, lambda], exact bounds at
+    ``iters``, exact bounds ``trend_window`` iterations earlier)."""
+    out, bounds, earlier = [], [], []
     C = np.tile(base.c, (D.shape[0], 1))
+    w = min(trend_window, iters)
     for s in range(0, D.shape[0], chunk):
         Dc = D[s:s + chunk]
         net = _abi.BatchNetwork(base, Dc, C[s:s + chunk], None, alpha=alpha, rho=rho)
         with _abi.BatchSolver([net], stream=stream, graph_iters=50, gamma_cap=1) as b:
-            b.step(iters)
+            b.step(iters - w)
+            earlier.append(b.bound())
+            b.step(w)
             bounds.append(b.bound())
             lam, mp, mm = b.get_multipliers(0)
         out.append(np.concatenate([mp, mm, lam[:, None]], axis=1))
-    return np.concatenate(out), np.concatenate(bounds)
+    return np.concatenate(out), np.concatenate(bounds), np.concatenate(earlier)
+
+
+def settled(bound, earlier, cost_ub, rel=1e-3):
+    """Scenarios whose cold-start ascent has settled: finite targets, a bound
+    below the largest possible cost, and a bound that rose by at most ``rel``
+    (relative) over the trend window.  An infeasible scenario has an
+    unbounded dual, so its bound keeps rising; it fails this test."""
+    ok = np.isfinite(bound) & np.isfinite(earlier) & (bound <= cost_ub)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        rise = (bound - earlier) / np.abs(bound)
+    return ok & (rise <= rel)
 
 
 def train(model: "_abi.MLP", X, T, epochs, batch, lr, seed=0, lr_decay=0.9, log=None):

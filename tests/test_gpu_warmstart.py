@@ -35,11 +35,11 @@ def test_warm_start_gains_over_cold_start():
     Dtr, _, _ = synth.make_scenarios(base, 5_000_000, n_train, 0.15, 0.0)
     Dev, _, _ = synth.make_scenarios(base, 6_000_000, n_eval, 0.15, 0.0)
     print("[warm] targets", flush=True)
-    T, tb = W.cold_solve(base, Dtr, 3000, r["alpha"], r["rho"])
-    # an infeasible scenario has an unbounded dual: its bound passes the
-    # largest possible cost; such scenarios are dropped from the data
+    T, tb, te = W.cold_solve(base, Dtr, 3000, r["alpha"], r["rho"])
+    # an infeasible scenario has an unbounded dual: its bound keeps rising
+    # (or passes the largest possible cost); such scenarios are dropped
     cost_ub = float(np.sum(np.maximum(base.c * base.p_min, base.c * base.p_max)))
-    ok = np.isfinite(tb) & (tb <= cost_ub) & np.all(np.isfinite(T), axis=1)
+    ok = W.settled(tb, te, cost_ub) & np.all(np.isfinite(T), axis=1)
     print(f"[warm] kept {ok.sum()} of {ok.size} training scenarios", flush=True)
     Dtr, T = Dtr[ok], T[ok]
     sx, st = W.Standardizer.fit(Dtr), W.Standardizer.fit(T)

@@ -34,3 +34,12 @@ def test_standardizer_roundtrip_and_constant_columns():
 def test_median_counts_unreached_at_cap():
     assert W.median_iters(np.array([10, -1, -1]), 5000) == 5000
     assert W.median_iters(np.array([10, 20, -1]), 5000) == 20
+
+
+def test_settled_drops_rising_and_oversized_bounds():
+    from paper_2406_13191_amd import warmstart as W
+    bound = np.array([100.0, 100.0, 100.0, 5000.0, np.nan, 100.0])
+    earlier = np.array([99.99, 90.0, 100.0, 4999.0, 100.0, np.inf])
+    ok = W.settled(bound, earlier, cost_ub=1000.0, rel=1e-3)
+    # settled; rose 10 %; flat; above the largest cost; NaN; infinite history
+    assert ok.tolist() == [True, False, True, False, False, False]
