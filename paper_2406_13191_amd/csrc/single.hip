@@ -374,6 +374,133 @@ __global__ __launch_bounds__(256) void colpass_kernel(
   }
 }
 
+// Sums of the previous iteration's partials taken by one wavefront: lane l
+// adds the entries l, l + 64, ... (the first kPreW of them loaded before any
+// wait by load()), then the lanes' sums meet in a butterfly.  The finalize
+// kernel uses the same order when the column pass does (bitwise equal
+// results however the iterations are split into calls).
+constexpr int kPreW = 16;
+struct WaveSums {
+  double a0[kPreW], a1[kPreW], b0[kPreW];
+  __device__ __forceinline__ void load(const double *__restrict__ pa, int ga,
+                                       const double *__restrict__ pb, int gb, int lane) {
+#pragma unroll
+    for (int m = 0; m < kPreW; ++m) {
+      const int ia = lane + m * kWave, ib = lane + m * kWave;
+      a0[m] = ldg(pa + 2 * (size_t)(ia < ga ? ia : 0));
+      a1[m] = ldg(pa + 2 * (size_t)(ia < ga ? ia : 0) + 1);
+      b0[m] = ldg(pb + (ib < gb ? ib : 0));
+    }
+  }
+  __device__ __forceinline__ void sum(const double *__restrict__ pa, int ga,
+                                      const double *__restrict__ pb, int gb, int lane,
+                                      double *ps, double *phis, double *lines) const {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int m = 0; m < kPreW; ++m) {
+      if (lane + m * kWave < ga) {
+        s0 += a0[m];
+        s1 += a1[m];
+      }
+      if (lane + m * kWave < gb) s2 += b0[m];
+    }
+    for (int i = lane + kPreW * kWave; i < ga; i += kWave) {
+      s0 += pa[2 * (size_t)i];
+      s1 += pa[2 * (size_t)i + 1];
+    }
+    for (int i = lane + kPreW * kWave; i < gb; i += kWave) s2 += pb[i];
+    *ps = wave_sum(s0);
+    *phis = wave_sum(s1);
+    *lines = wave_sum(s2);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Column pass with one column per workgroup (panels of at most 8 chunks per
+// lane and quarter): one barrier in all.  The four wavefronts each load and
+// multiply a quarter of the column against v; wavefront 0 meanwhile loads the
+// column's units and every partial of iteration k-1.  After the quarter sums
+// meet in LDS, wavefront 0 alone folds iteration k-1 (lane-parallel, no
+// further barrier), runs the units and writes x_j and the workgroup's
+// partials; workgroup 0 records the new slot.
+// ---------------------------------------------------------------------------
+template <typename T, int UNR>
+__global__ __launch_bounds__(256) void colpass1_kernel(
+    const T *__restrict__ PT, int n_cols, int ldl, const T *__restrict__ vvec,
+    const int *__restrict__ seg, const double *__restrict__ c, const double *__restrict__ q,
+    const double *__restrict__ pmin, const double *__restrict__ pmax, DevScalars *sc, int par,
+    T *__restrict__ x_out, double *__restrict__ part_a, int ga, const double *__restrict__ part_b,
+    int gb, StepParams prm, double *__restrict__ gam_buf, long long gam_mask) {
+  using V = typename Vec16<T>::type;
+  __shared__ T dots[4];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int j = blockIdx.x;
+  const IterSlot prev = sc->slot[par ^ 1];
+  const double *pa = part_a + (size_t)(par ^ 1) * 2 * ga;
+  const double *pb = part_b + (size_t)(par ^ 1) * gb;
+  // wavefront 0: the column's unit boundaries and the previous partials
+  int g0 = 0, g1 = 0;
+  WaveSums ws;
+  if (wave == 0) {
+    g0 = ldg(seg + j);
+    g1 = ldg(seg + j + 1);
+    ws.load(pa, ga, pb, gb, lane);
+  }
+  // every wavefront: a quarter of the column (all chunks in flight at once)
+  const int nv = ldl / Vec16<T>::n;
+  const int quarter = (nv + 3) / 4;
+  const int cb = wave * quarter, ce = min(nv, cb + quarter);
+  const V *vv = reinterpret_cast<const V *>(vvec);
+  const V *row = reinterpret_cast<const V *>(PT + (size_t)j * ldl);
+  V pv[UNR], xv[UNR];
+#pragma unroll
+  for (int m = 0; m < UNR; ++m) {
+    const int i = cb + lane + m * kWave;
+    const int ic = i < ce ? i : 0;
+    xv[m] = vv[ic];
+    pv[m] = __builtin_nontemporal_load(row + ic);
+  }
+  // wavefront 0: the lane's first unit (waits for the boundaries only)
+  double cf = 0.0, qf = 0.0, lof = 0.0, hif = 0.0;
+  if (wave == 0) {
+    const int tf = g0 + lane < g1 ? g0 + lane : 0;
+    cf = ldg(c + tf);
+    qf = ldg(q + tf);
+    lof = ldg(pmin + tf);
+    hif = ldg(pmax + tf);
+  }
+  T acc = (T)0;
+#pragma unroll
+  for (int m = 0; m < UNR; ++m)
+    if (cb + lane + m * kWave < ce) acc = fma_vec(pv[m], xv[m], acc);
+  const T d = wave_sum(acc);
+  if (lane == 0) dots[wave] = d;
+  __syncthreads();
+  if (wave != 0) return;
+  // wavefront 0: fold iteration k-1, then the units of column j
+  IterSlot cur = prev;
+  if (prev.pending) {
+    double ps, phis, lines, gam;
+    ws.sum(pa, ga, pb, gb, lane, &ps, &phis, &lines);
+    cur = fold(prev, ps, phis, lines, sc->D, prm, &gam);
+    if (blockIdx.x == 0 && lane == 0) {
+      gam_buf[prev.k & gam_mask] = gam;
+      sc->gamma_last = gam;
+    }
+  }
+  set_step(cur, prev.k + 1, prm);
+  cur.pending = 1;
+  if (blockIdx.x == 0 && lane == 0) sc->slot[par] = cur;
+  const double w = (double)(((dots[0] + dots[1]) + dots[2]) + dots[3]);
+  double xj, phij;
+  column_units(w, cur.lam, g0, g1, cf, qf, lof, hif, c, q, pmin, pmax, lane, &xj, &phij);
+  if (lane == 0) {
+    x_out[j] = (T)xj;
+    part_a[(size_t)par * 2 * ga + 2 * j] = xj;
+    part_a[(size_t)par * 2 * ga + 2 * j + 1] = phij;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Line pass of iteration k: F = P x - f_d for RW lines per wavefront (their
 // loads interleaved), then lane t < RW applies the step and projection to
@@ -389,7 +516,6 @@ __global__ __launch_bounds__(256) void linepass_kernel(
     T *__restrict__ v_out, const DevScalars *sc, int par, double *__restrict__ part_b, int gb,
     StepParams prm) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[4];
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
   const int base = (blockIdx.x * nw + wave) * RW;
@@ -497,8 +623,9 @@ __global__ __launch_bounds__(256) void linepass_kernel(
     mu_m[l] = nm_;
     v_out[l] = (T)(np_ - nm_);
   }
-  const double bl = block_sum(term, red);
-  if (threadIdx.x == 0) part_b[(size_t)par * gb + blockIdx.x] = bl;
+  // one partial per wavefront (no workgroup barrier)
+  const double wl = wave_sum(term);
+  if (lane == 0) part_b[(size_t)par * gb + blockIdx.x * nw + wave] = wl;
 }
 
 // Fold the last iteration of a step() call (one workgroup).
@@ -507,13 +634,22 @@ __global__ __launch_bounds__(256) void finalize_kernel(DevScalars *sc, int par,
                                                        const double *__restrict__ part_b, int gb,
                                                        StepParams prm,
                                                        double *__restrict__ gam_buf,
-                                                       long long gam_mask) {
+                                                       long long gam_mask, int wave_order) {
   __shared__ double red[4];
   const IterSlot s = sc->slot[par];
   if (!s.pending) return;
   double ps, phis, lines;
-  sum_partials(part_a + (size_t)par * 2 * ga, ga, part_b + (size_t)par * gb, gb, red, &ps,
-               &phis, &lines);
+  if (wave_order) {
+    // the summation order of the one-column column pass
+    if (threadIdx.x >= kWave) return;
+    WaveSums ws;
+    const double *pa = part_a + (size_t)par * 2 * ga, *pb = part_b + (size_t)par * gb;
+    ws.load(pa, ga, pb, gb, threadIdx.x);
+    ws.sum(pa, ga, pb, gb, threadIdx.x, &ps, &phis, &lines);
+  } else {
+    sum_partials(part_a + (size_t)par * 2 * ga, ga, part_b + (size_t)par * gb, gb, red, &ps,
+                 &phis, &lines);
+  }
   if (threadIdx.x == 0) {
     double gam = 0.0;
     IterSlot n = fold(s, ps, phis, lines, sc->D, prm, &gam);
@@ -684,9 +820,11 @@ struct dcopf_dual_s {
   double *gam = nullptr;
   // launch shapes
   int grid_col = 0, grid_line = 0, grid_bnd_col = 0, grid_bnd_line = 0;
+  int n_line_part = 0;  // line-pass partials: one per wavefront
   size_t lds_col = 0, lds_line = 0, lds_bnd = 0;
   bool stage_col = false, stage_line = false, stage_bnd = false;
   int col_cb = 1;   // panel columns per workgroup in the column pass
+  bool col_one = false;  // one-column, one-barrier column pass (small panels)
   int line_xr = 0;  // x chunks per lane held in registers (0: LDS / global)
   // graph of graph_iters iterations (even), starting at an even iteration
   hipGraph_t graph = nullptr;
@@ -708,19 +846,29 @@ void launch_colpass_cb(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, h
   T *PT = std::is_same<T, float>::value ? (T *)h->P32T : (T *)h->P64T;
   (void)launch_k(colpass_kernel<T, CB, UNR>, dim3(h->grid_col), dim3(256), 0, s, e0, e1, PT,
                  h->n_cols, h->ldl, (T *)h->vbuf, h->seg, h->c, h->q, h->pmin, h->pmax, h->sc,
-                 par, (T *)h->xbuf, h->part_a, h->grid_col, h->part_b, h->grid_line, h->prm,
+                 par, (T *)h->xbuf, h->part_a, h->grid_col, h->part_b, h->n_line_part, h->prm,
                  h->gam, kGamCap - 1);
 }
 
-// one column per workgroup and a quarter of at most 8 chunks per lane: every
-// panel load is issued before the first wait
+template <typename T, int UNR>
+void launch_colpass1(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hipEvent_t e1) {
+  T *PT = std::is_same<T, float>::value ? (T *)h->P32T : (T *)h->P64T;
+  (void)launch_k(colpass1_kernel<T, UNR>, dim3(h->grid_col), dim3(256), 0, s, e0, e1, PT,
+                 h->n_cols, h->ldl, (T *)h->vbuf, h->seg, h->c, h->q, h->pmin, h->pmax, h->sc,
+                 par, (T *)h->xbuf, h->part_a, h->grid_col, h->part_b, h->n_line_part, h->prm,
+                 h->gam, kGamCap - 1);
+}
+
+// one column per workgroup and a quarter of at most 8 chunks per lane: the
+// one-barrier column pass; otherwise the general one
 template <typename T>
 void launch_colpass(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hipEvent_t e1) {
   const int quarter = (h->ldl / Vec16<T>::n + 3) / 4;
-  if (h->col_cb == 1) {
-    if (quarter <= 4 * kWave) launch_colpass_cb<T, 1, 4>(h, s, par, e0, e1);
-    else if (quarter <= 8 * kWave) launch_colpass_cb<T, 1, 8>(h, s, par, e0, e1);
-    else launch_colpass_cb<T, 1, 0>(h, s, par, e0, e1);
+  if (h->col_one) {
+    if (quarter <= 4 * kWave) launch_colpass1<T, 4>(h, s, par, e0, e1);
+    else launch_colpass1<T, 8>(h, s, par, e0, e1);
+  } else if (h->col_cb == 1) {
+    launch_colpass_cb<T, 1, 0>(h, s, par, e0, e1);
   } else if (h->col_cb == 2) {
     launch_colpass_cb<T, 2, 0>(h, s, par, e0, e1);
   } else {
@@ -735,7 +883,7 @@ void launch_linepass(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hip
 #define DCOPF_LINEPASS(STAGE, XR, LDS)                                                       \
   (void)launch_k(linepass_kernel<T, STAGE, kLineRows, XR>, dim3(h->grid_line), dim3(256), LDS, \
                  s, e0, e1, P, h->n_lines, h->ldc, x, h->fd, h->fmax, h->mu_p, h->mu_m,       \
-                 h->v_p, h->v_m, h->s_p, h->s_m, v, h->sc, par, h->part_b, h->grid_line, h->prm)
+                 h->v_p, h->v_m, h->s_p, h->s_m, v, h->sc, par, h->part_b, h->n_line_part, h->prm)
   if (h->line_xr == 2) DCOPF_LINEPASS(false, 2, 0);
   else if (h->line_xr == 4) DCOPF_LINEPASS(false, 4, 0);
   else if (h->stage_line) DCOPF_LINEPASS(true, 0, (unsigned)h->lds_line);
@@ -768,7 +916,8 @@ void launch_iters(dcopf_dual_s *h, hipStream_t s, long long first, int64_t n) {
 void launch_finalize(dcopf_dual_s *h, hipStream_t s) {
   const int par = (int)((h->iters - 1) & 1);
   finalize_kernel<<<1, 256, 0, s>>>(h->sc, par, h->part_a, h->grid_col, h->part_b,
-                                    h->grid_line, h->prm, h->gam, kGamCap - 1);
+                                    h->n_line_part, h->prm, h->gam, kGamCap - 1,
+                                    h->col_one ? 1 : 0);
 }
 
 void refresh_v(dcopf_dual_s *h) {
@@ -919,10 +1068,16 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   h->col_cb = nc >= 2048 ? 4 : (nc >= 1024 ? 2 : 1);
   h->grid_col = (nc + h->col_cb - 1) / h->col_cb;
   {
+    const int per_chunk = o->precision == DCOPF_PREC_FP32 ? 4 : 2;
+    const int quarter = (h->ldl / per_chunk + 3) / 4;
+    h->col_one = h->col_cb == 1 && quarter <= 8 * kWave;
+  }
+  {
     const int nvc = h->ldc / (fp32 ? 4 : 2);
     h->line_xr = nvc <= 128 ? 2 : (nvc <= 256 ? 4 : 0);
   }
   h->grid_line = grid_for(nl, 4 * kLineRows, 65536);
+  h->n_line_part = 4 * h->grid_line;
   h->grid_bnd_col = grid_for(nc, 4, 4096);
   h->grid_bnd_line = grid_for(nl, 256, 1024);
   h->lds_col = (size_t)h->ldl * esz;
@@ -955,7 +1110,7 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   h->xbuf = dalloc<unsigned char>((size_t)h->ldc * esz, &st);
   h->v64b = dalloc<double>(h->ldl, &st);
   h->part_a = dalloc<double>(4 * (size_t)h->grid_col, &st);
-  h->part_b = dalloc<double>(2 * (size_t)h->grid_line, &st);
+  h->part_b = dalloc<double>(2 * (size_t)h->n_line_part, &st);
   h->part_c = dalloc<double>((size_t)h->grid_bnd_line, &st);
   h->part_d = dalloc<double>((size_t)h->grid_bnd_col, &st);
   h->counters = dalloc<unsigned>(8, &st);
