@@ -100,11 +100,12 @@ __device__ __forceinline__ int mfma32_row(int j, int lane) {
 }
 
 // element at a 32-bit byte offset (per-network state arrays are < 4 GiB)
-template <typename T> __device__ __forceinline__ T &at(T *p, unsigned byte_off) {
-  return *reinterpret_cast<T *>(reinterpret_cast<char *>(p) + byte_off);
+// (loads and stores through global-address-space pointers)
+template <typename T> __device__ __forceinline__ T ld_at(const T *p, unsigned byte_off) {
+  return ldg(reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + byte_off));
 }
-template <typename T> __device__ __forceinline__ const T &at(const T *p, unsigned byte_off) {
-  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + byte_off);
+template <typename T> __device__ __forceinline__ void st_at(T *p, unsigned byte_off, T v) {
+  *(__attribute__((address_space(1))) T *)(reinterpret_cast<char *>(p) + byte_off) = v;
 }
 
 // largest K split of the W product (the unit pass holds every split's
@@ -117,10 +118,11 @@ constexpr int kMaxSplit = 32;
 // C[BM x BN] += (A_hi + A_lo)[BM x K] (B_hi + B_lo)[BN x K]^T over k in
 // [kb, ke) (a multiple of 64).  256 threads = WM x WN wavefronts, each owning
 // TM x TN tiles of 32 x 32 (v_mfma_f32_32x32x16_bf16).  Per 64-deep K step the
-// four operand tiles are copied to LDS (8 threads per 128-byte row), the next
-// step's global loads are issued into registers before the products, and the
-// fragments are read from LDS with a 144-byte row stride (16-byte reads of 16
-// consecutive rows hit disjoint banks).
+// four operand tiles are copied to LDS (8 threads per 128-byte row) from one
+// of two register stages, that stage is refilled with the loads of the step
+// after next before the products, and the fragments are read from LDS with a
+// 144-byte row stride (16-byte reads of 16 consecutive rows hit disjoint
+// banks).
 // ---------------------------------------------------------------------------
 constexpr int kBK = 64;
 constexpr int kLdsStride = kBK + 8;  // bf16 elements per LDS row
@@ -142,24 +144,25 @@ __device__ __forceinline__ void tile_mma(const __bf16 *__restrict__ Ah,
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int lrow = t >> 3, lchunk = (t & 7) * 8;
-  bf16x8 pa[2][RA], pb[2][RB];
-  auto fetch = [&](int k) {
+  // two register stages: while step k is copied to LDS and multiplied, the
+  // loads of steps k + 1 and k + 2 are in flight
+  bf16x8 pa0[2][RA], pb0[2][RB], pa1[2][RA], pb1[2][RB];
+  auto fetch = [&](bf16x8 (&pa)[2][RA], bf16x8 (&pb)[2][RB], int k) {
 #pragma unroll
     for (int r = 0; r < RA; ++r) {
       const size_t off = (size_t)(r * 32 + lrow) * lda + k + lchunk;
-      pa[0][r] = *reinterpret_cast<const bf16x8 *>(Ah + off);
-      pa[1][r] = *reinterpret_cast<const bf16x8 *>(Al + off);
+      pa[0][r] = ldg(reinterpret_cast<const bf16x8 *>(Ah + off));
+      pa[1][r] = ldg(reinterpret_cast<const bf16x8 *>(Al + off));
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       const size_t off = (size_t)(r * 32 + lrow) * ldb + k + lchunk;
-      pb[0][r] = *reinterpret_cast<const bf16x8 *>(Bh + off);
-      pb[1][r] = *reinterpret_cast<const bf16x8 *>(Bl + off);
+      pb[0][r] = ldg(reinterpret_cast<const bf16x8 *>(Bh + off));
+      pb[1][r] = ldg(reinterpret_cast<const bf16x8 *>(Bl + off));
     }
   };
-  if (kb < ke) fetch(kb);
   const int fr = lane & 31, fk = (lane >> 5) * 8;
-  for (int k = kb; k < ke; k += kBK) {
+  auto step = [&](bf16x8 (&pa)[2][RA], bf16x8 (&pb)[2][RB], int k) {
     __syncthreads();
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -171,7 +174,10 @@ __device__ __forceinline__ void tile_mma(const __bf16 *__restrict__ Ah,
         *reinterpret_cast<bf16x8 *>(&sm.b[h][r * 32 + lrow][lchunk]) = pb[h][r];
     }
     __syncthreads();
-    if (k + kBK < ke) fetch(k + kBK);
+    // refill this stage with the step after next (clamped to the last step:
+    // the loads stay unconditional, so each wait counts exactly the loads
+    // still needed)
+    fetch(pa, pb, min(k + 2 * kBK, ke - kBK));
 #pragma unroll
     for (int kk = 0; kk < kBK; kk += 16) {
       bf16x8 fa[2][TM], fb[2][TN];
@@ -197,7 +203,16 @@ __device__ __forceinline__ void tile_mma(const __bf16 *__restrict__ Ah,
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1][i], fb[1][j], acc[i][j], 0, 0, 0);
         }
     }
+  };
+  if (kb >= ke) return;
+  fetch(pa0, pb0, kb);
+  fetch(pa1, pb1, min(kb + kBK, ke - kBK));
+  int k = kb;
+  for (; k + 2 * kBK <= ke; k += 2 * kBK) {
+    step(pa0, pb0, k);
+    step(pa1, pb1, k + kBK);
   }
+  if (k < ke) step(pa0, pb0, k);  // odd number of K steps
 }
 
 // Workgroup tile shapes (code stored per network): BM x BN and wave layout.
@@ -468,18 +483,35 @@ __device__ __forceinline__ void fgemm_body(const BNet &N, int4 t, const BScal *s
           s1[kEpiChunk], s2[kEpiChunk];
 #pragma unroll
       for (int c = 0; c < kEpiChunk; ++c) {
+        // clamped (in-range) offsets: every load goes out before any wait;
+        // rows outside the batch or lines past n_l are never stored
         const int e = h + c;
         const int i = mb + mfma32_row(e, lane);
-        const bool ok = lvalid && i < N.B;
-        const unsigned bo = ((unsigned)i * (unsigned)N.ldl + (unsigned)line) * 4u;
-        fd[c] = ok ? at(fdp, bo) : 0.f;
-        mp[c] = ok ? at(mup, bo) : 0.f;
-        mm[c] = ok ? at(mum, bo) : 0.f;
-        v1[c] = ok && need_v ? at(vpp, bo) : 0.f;
-        v2[c] = ok && need_v ? at(vmp, bo) : 0.f;
-        s1[c] = ok && need_s ? at(spp, bo) : 0.f;
-        s2[c] = ok && need_s ? at(smp, bo) : 0.f;
+        const unsigned bo = ((unsigned)(i < N.B ? i : 0) * (unsigned)N.ldl +
+                             (unsigned)(lvalid ? line : 0)) * 4u;
+        fd[c] = ld_at(fdp, bo);
+        mp[c] = ld_at(mup, bo);
+        mm[c] = ld_at(mum, bo);
+        v1[c] = v2[c] = s1[c] = s2[c] = 0.f;
       }
+      if (need_v)
+#pragma unroll
+        for (int c = 0; c < kEpiChunk; ++c) {
+          const int i = mb + mfma32_row(h + c, lane);
+          const unsigned bo = ((unsigned)(i < N.B ? i : 0) * (unsigned)N.ldl +
+                               (unsigned)(lvalid ? line : 0)) * 4u;
+          v1[c] = ld_at(vpp, bo);
+          v2[c] = ld_at(vmp, bo);
+        }
+      if (need_s)
+#pragma unroll
+        for (int c = 0; c < kEpiChunk; ++c) {
+          const int i = mb + mfma32_row(h + c, lane);
+          const unsigned bo = ((unsigned)(i < N.B ? i : 0) * (unsigned)N.ldl +
+                               (unsigned)(lvalid ? line : 0)) * 4u;
+          s1[c] = ld_at(spp, bo);
+          s2[c] = ld_at(smp, bo);
+        }
 #pragma unroll
       for (int c = 0; c < kEpiChunk; ++c) {
         const int e = h + c;
@@ -493,8 +525,8 @@ __device__ __forceinline__ void fgemm_body(const BNet &N, int4 t, const BScal *s
         if (prm.rule == DCOPF_RULE_GDM) {
           const float vp = rho * v1[c] + a * gp, vm = rho * v2[c] + a * gm;
           if (ok) {
-            at(vpp, bo) = vp;
-            at(vmp, bo) = vm;
+            st_at(vpp, bo, vp);
+            st_at(vmp, bo, vm);
           }
           np_ = mp[c] + vp;
           nm_ = mm[c] + vm;
@@ -508,18 +540,18 @@ __device__ __forceinline__ void fgemm_body(const BNet &N, int4 t, const BScal *s
           const float q1 = b2 * s1[c] + (1.f - b2) * gp * gp;
           const float q2 = b2 * s2[c] + (1.f - b2) * gm * gm;
           if (ok) {
-            at(vpp, bo) = m1;
-            at(vmp, bo) = m2;
-            at(spp, bo) = q1;
-            at(smp, bo) = q2;
+            st_at(vpp, bo, m1);
+            st_at(vmp, bo, m2);
+            st_at(spp, bo, q1);
+            st_at(smp, bo, q2);
           }
           np_ = mp[c] + a * (m1 / c1) / (sqrtf(q1 / c2) + eps);
           nm_ = mm[c] + a * (m2 / c1) / (sqrtf(q2 / c2) + eps);
         } else {
           const float q1 = s1[c] + gp * gp, q2 = s2[c] + gm * gm;
           if (ok) {
-            at(spp, bo) = q1;
-            at(smp, bo) = q2;
+            st_at(spp, bo, q1);
+            st_at(smp, bo, q2);
           }
           np_ = mp[c] + a * gp / (sqrtf(q1) + eps);
           nm_ = mm[c] + a * gm / (sqrtf(q2) + eps);
@@ -527,12 +559,12 @@ __device__ __forceinline__ void fgemm_body(const BNet &N, int4 t, const BScal *s
         np_ = fmaxf(np_, 0.f);
         nm_ = fmaxf(nm_, 0.f);
         if (ok) {
-          at(mup, bo) = np_;
-          at(mum, bo) = nm_;
+          st_at(mup, bo, np_);
+          st_at(mum, bo, nm_);
           __bf16 hi, lo;
           split_bf16(np_ - nm_, &hi, &lo);
-          at(vhi, bo >> 1) = hi;
-          at(vlo, bo >> 1) = lo;
+          st_at(vhi, bo >> 1, hi);
+          st_at(vlo, bo >> 1, lo);
         }
         // line terms of instance i summed over the 32 lines of this tile
         if (!ok) term = 0.0;
