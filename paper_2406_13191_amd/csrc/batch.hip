@@ -58,7 +58,7 @@ struct BNet {
                                                 // (unit data stored column-sorted)
   double *lam, *vlam, *slam;                    // [2][B]: state used by the iteration of that parity
   double *D;                                    // [B]
-  int ncb;                                      // column blocks of 256 in the unit pass
+  int ncb;                                      // column blocks of the unit pass
   double *unitpart;                             // [2][ncb][Bp][2]: sum p*, sum phi by parity
   double *linepart;                             // [ntl][Bp]
   double *V64, *W64;                            // [Bp][ldl], [Bp][ncp]
@@ -324,15 +324,20 @@ __device__ __forceinline__ LamState fold_finish(const BNet &N, int i, int pp, lo
 }
 
 // ---------------------------------------------------------------------------
-// Unit pass: workgroup (instance i, column block cb) handles columns
-// cb*256 .. cb*256+255, one per thread.  Every load that does not depend on
-// lambda (the K-split partials of w, the column's first unit, the previous
-// iteration's partial sums) is issued before the first wait.  The previous
-// iteration is then folded (every workgroup of the instance identically, so
-// lambda needs no extra launch; workgroup cb = 0 records lambda's state and
-// gamma), and the columns' reduced costs, inner minimiser, injections X
-// (BF16 hi/lo) and per-workgroup sums of p* and phi follow.
+// Unit pass: workgroup (instance i, column block cb) handles the kUnitCols
+// columns cb*kUnitCols .. , kUnitCPT per thread (columns t and t + 256).
+// Every load that does not depend on lambda (the K-split partials of w, the
+// columns' first units, the previous iteration's partial sums) is issued
+// before the first wait.  The previous iteration is then folded (every
+// workgroup of the instance identically, so lambda needs no extra launch;
+// workgroup cb = 0 records lambda's state and gamma), and the columns'
+// reduced costs, inner minimiser, injections X (BF16 hi/lo) and
+// per-workgroup sums of p* and phi follow.  MAXS bounds the K split.
 // ---------------------------------------------------------------------------
+constexpr int kUnitCPT = 2;
+constexpr int kUnitCols = 256 * kUnitCPT;
+
+template <int MAXS>
 __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ nets,
                                                     const int4 *__restrict__ unit_tab,
                                                     BScal *sc, int par, BParams prm,
@@ -343,34 +348,46 @@ __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ net
   const BNet &N = nets[e.x];
   const int i = e.y, cb = e.z;
   const BIter it = sc->it[par];
-  const int j = cb * 256 + threadIdx.x;
-  const bool valid = j < N.n_c;
   // loads are issued unconditionally from clamped (in-range) indices and
   // masked afterwards, so that none of them waits for another
-  const int jc = valid ? j : 0;
-  int u0 = ldg(N.seg + jc), u1 = ldg(N.seg + jc + 1);
-  if (!valid) u1 = u0;
-  const int uc = u0 < u1 ? u0 : 0;
+  int jj[kUnitCPT], u0[kUnitCPT], u1[kUnitCPT];
+  bool valid[kUnitCPT];
+#pragma unroll
+  for (int h = 0; h < kUnitCPT; ++h) {
+    const int j = cb * kUnitCols + h * 256 + threadIdx.x;
+    valid[h] = j < N.n_c;
+    jj[h] = valid[h] ? j : 0;
+    u0[h] = ldg(N.seg + jj[h]);
+    u1[h] = ldg(N.seg + jj[h] + 1);
+    if (!valid[h]) u1[h] = u0[h];
+  }
   const double *ci = N.c + (size_t)i * N.n_g, *qi = N.q + (size_t)i * N.n_g;
-  const double c0 = ldg(ci + uc), q0 = ldg(qi + uc), lo0 = ldg(N.pmin + uc),
-               hi0 = ldg(N.pmax + uc);
-  // all K-split partials of w at once (S <= kMaxSplit), summed in split order
-  float wpart[kMaxSplit];
+  double c0[kUnitCPT], q0[kUnitCPT], lo0[kUnitCPT], hi0[kUnitCPT];
+#pragma unroll
+  for (int h = 0; h < kUnitCPT; ++h) {
+    const int uc = u0[h] < u1[h] ? u0[h] : 0;
+    c0[h] = ldg(ci + uc);
+    q0[h] = ldg(qi + uc);
+    lo0[h] = ldg(N.pmin + uc);
+    hi0[h] = ldg(N.pmax + uc);
+  }
+  // all K-split partials of w at once (S <= MAXS), summed in split order
+  float wpart[kUnitCPT][MAXS];
   {
-    const float *wp = N.Wws + (size_t)i * N.ncp + jc;
     const size_t ss = (size_t)N.Bp * N.ncp;
 #pragma unroll
-    for (int t = 0; t < kMaxSplit; ++t) {
-      const float v = ldg(wp + (t < N.S ? t : 0) * ss);
-      wpart[t] = t < N.S ? v : 0.f;
+    for (int h = 0; h < kUnitCPT; ++h) {
+      const float *wp = N.Wws + (size_t)i * N.ncp + jj[h];
+#pragma unroll
+      for (int t = 0; t < MAXS; ++t) {
+        const float v = ldg(wp + (t < N.S ? t : 0) * ss);
+        wpart[h][t] = t < N.S ? v : 0.f;
+      }
     }
   }
   double f[3] = {0.0, 0.0, 0.0};
   if (it.pending) fold_partials(N, i, par ^ 1, f);
   block_sums<3>(f, red);
-  double w = 0.0;
-#pragma unroll
-  for (int t = 0; t < kMaxSplit; ++t) w += (double)wpart[t];
   double lam;
   if (it.pending) {
     const LamState r = fold_finish(N, i, par ^ 1, it.k - 1, prm, f);
@@ -384,11 +401,17 @@ __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ net
   } else {
     lam = N.lam[(size_t)par * N.B + i];
   }
-  double x = 0.0, ph = 0.0;
-  if (valid) {
-    for (int u = u0; u < u1; ++u) {
-      double cu = c0, qu = q0, lo = lo0, hi = hi0;
-      if (u != u0) {
+  double xs = 0.0, phs = 0.0;
+#pragma unroll
+  for (int h = 0; h < kUnitCPT; ++h) {
+    if (!valid[h]) continue;
+    double w = 0.0;
+#pragma unroll
+    for (int t = 0; t < MAXS; ++t) w += (double)wpart[h][t];
+    double x = 0.0;
+    for (int u = u0[h]; u < u1[h]; ++u) {
+      double cu = c0[h], qu = q0[h], lo = lo0[h], hi = hi0[h];
+      if (u != u0[h]) {
         cu = ci[u];
         qu = qi[u];
         lo = N.pmin[u];
@@ -396,15 +419,16 @@ __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ net
       }
       const double r = cu - lam + w;
       const double p = inner_min_b(r, qu, lo, hi);
-      ph += r * p + qu * p * p;
+      phs += r * p + qu * p * p;
       x += p;
     }
-    __bf16 hi, lo;
-    split_bf16((float)x, &hi, &lo);
-    N.X_hi[(size_t)i * N.ldc + j] = hi;
-    N.X_lo[(size_t)i * N.ldc + j] = lo;
+    __bf16 xh, xl;
+    split_bf16((float)x, &xh, &xl);
+    N.X_hi[(size_t)i * N.ldc + jj[h]] = xh;
+    N.X_lo[(size_t)i * N.ldc + jj[h]] = xl;
+    xs += x;
   }
-  double sums[2] = {x, ph};
+  double sums[2] = {xs, phs};
   block_sums<2>(sums, red);
   if (threadIdx.x == 0) {
     double *up = N.unitpart + (size_t)par * N.ncb * N.Bp * 2 + ((size_t)cb * N.Bp + i) * 2;
@@ -871,7 +895,10 @@ void launch_w(dcopf_batch_s *b, hipStream_t s, const int4 *tiles, int n,
 
 void launch_u(dcopf_batch_s *b, hipStream_t s, int par, hipEvent_t e0 = nullptr,
               hipEvent_t e1 = nullptr) {
-  (void)launch_k(units_kernel, dim3(b->n_units), dim3(256), 0, s, e0, e1, b->d_nets, b->d_units,
+  int maxs = 1;
+  for (auto &n : b->nets) maxs = std::max(maxs, n.d.S);
+  auto kern = maxs <= 8 ? units_kernel<8> : (maxs <= 16 ? units_kernel<16> : units_kernel<32>);
+  (void)launch_k(kern, dim3(b->n_units), dim3(256), 0, s, e0, e1, b->d_nets, b->d_units,
                  b->sc, par, b->prm, b->gam, b->gcap - 1, b->n_total);
 }
 
@@ -1167,7 +1194,7 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
   N.lam = balloc<double>(own, (size_t)2 * B, &ok);
   N.vlam = balloc<double>(own, (size_t)2 * B, &ok);
   N.slam = balloc<double>(own, (size_t)2 * B, &ok);
-  N.ncb = (nc + 255) / 256;
+  N.ncb = (nc + kUnitCols - 1) / kUnitCols;
   N.unitpart = balloc<double>(own, (size_t)2 * N.ncb * Bp * 2, &ok);
   double *D = balloc<double>(own, B, &ok);
   N.linepart = balloc<double>(own, (size_t)(nlp / 32) * Bp, &ok);  // every 32-line tile an F tile can write
