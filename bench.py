@@ -224,7 +224,7 @@ def bench_warmstart(args, stream):
                       R.init_params(np.random.default_rng(0), dims)])
     ms_step = model.time_train(X[:256].data_ptr(), Y[:256].data_ptr(), 256, 20)
     losses, t_train = W.timed(W.train, model, X, Y, args.epochs, 256, 1e-3, 0, 0.9, log)
-    start = W.predict(model, Dev, sx, st, base.n_line)
+    start, t_pred = W.timed(W.predict, model, Dev, sx, st, base.n_line)
     model.close()
     opt = []
     with mp.get_context("spawn").Pool(16) as pool:
@@ -238,13 +238,19 @@ def bench_warmstart(args, stream):
     Dev, opt = Dev[keep], opt[keep]
     start = tuple(a[keep] for a in start)
     log(f"{int(keep.sum())} held-out scenarios with an optimum; cold solves")
+    sc_, sw_ = {}, {}
     (hc, pc), t_cold = W.timed(W.run_to_gap, base, Dev, opt, r["alpha"], r["rho"], None,
-                               args.max_iters, 10, 100, stream.cuda_stream)
+                               args.max_iters, 10, 100, stream.cuda_stream, sc_)
     log(f"cold: {t_cold:.1f} s; warm solves")
     (hw, pw), t_warm = W.timed(W.run_to_gap, base, Dev, opt, r["alpha"], r["rho"], start,
-                               args.max_iters, 10, 100, stream.cuda_stream)
+                               args.max_iters, 10, 100, stream.cuda_stream, sw_)
     log(f"warm: {t_warm:.1f} s")
     hf, used = W.combine_with_fallback(hc, pc, hw, pw, 100)
+    # wall time per iteration of the batched solve (bound checks every 10
+    # iterations included), and the time at which the median instance is
+    # certified; the warm start adds one inference pass
+    spi_c = sc_["seconds"] / max(sc_["iterations"], 1)
+    spi_w = sw_["seconds"] / max(sw_["iterations"], 1)
     flops = 6.0 * 256 * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
     return dict(
         n_train=int(ok.sum()), n_eval=int(keep.sum()), data_seconds=t_data,
@@ -254,7 +260,11 @@ def bench_warmstart(args, stream):
         median_iters_warm=W.median_iters(hw, args.max_iters),
         median_iters_warm_fallback=W.median_iters(hf, args.max_iters),
         reached_cold=float((hc >= 0).mean()), reached_warm_fallback=float((hf >= 0).mean()),
-        warm_kept=float(used.mean()), solve_seconds_cold=t_cold, solve_seconds_warm=t_warm)
+        warm_kept=float(used.mean()), solve_seconds_cold=t_cold, solve_seconds_warm=t_warm,
+        batch_ms_per_iteration_cold=spi_c * 1e3, batch_ms_per_iteration_warm=spi_w * 1e3,
+        median_seconds_to_gap_cold=W.median_iters(hc, args.max_iters) * spi_c,
+        median_seconds_to_gap_warm_fallback=W.median_iters(hf, args.max_iters) * spi_w
+        + t_pred, inference_seconds=t_pred)
 
 
 def main():

@@ -120,10 +120,11 @@ def predict(model: "_abi.MLP", X, sx: Standardizer, st: Standardizer, n_line, ba
 
 
 def run_to_gap(base, D, opt, alpha, rho, start=None, max_iters=5000, check_every=10,
-               probe_at=100, stream=None):
+               probe_at=100, stream=None, stats=None):
     """Batched solve of the scenarios D (cold, or from start = (lam, mu+, mu-)).
     Returns (iteration of the first exact bound within 0.1 % of opt per
-    instance, -1 if none; exact bound at iteration probe_at)."""
+    instance, -1 if none; exact bound at iteration probe_at).  If ``stats``
+    is a dict it receives the iterations run and their wall time."""
     C = np.tile(base.c, (D.shape[0], 1))
     net = _abi.BatchNetwork(base, D, C, None, alpha=alpha, rho=rho)
     with _abi.BatchSolver([net], stream=stream, graph_iters=10, gamma_cap=1) as b:
@@ -132,6 +133,7 @@ def run_to_gap(base, D, opt, alpha, rho, start=None, max_iters=5000, check_every
         hit = np.full(D.shape[0], -1, np.int64)
         probe = None
         it = 0
+        t0 = time.perf_counter()
         vals = b.bound()
         hit[(opt - vals) <= 1e-3 * np.abs(opt)] = 0
         while it < max_iters and np.any(hit < 0):
@@ -144,6 +146,9 @@ def run_to_gap(base, D, opt, alpha, rho, start=None, max_iters=5000, check_every
                 probe = vals.copy()
         if probe is None:
             probe = vals.copy()
+        if stats is not None:
+            stats["iterations"] = it
+            stats["seconds"] = time.perf_counter() - t0
     return hit, probe
 
 
