@@ -90,10 +90,18 @@ def cpu_baseline(p, alpha, rho, budget_s=15.0):
     D.ascent(K, n, alpha=alpha, rho=rho)
     dt = time.perf_counter() - t
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    # the same oracle with one BLAS thread, a shorter sample
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        n1 = max(20, n // 10)
+        t = time.perf_counter()
+        D.ascent(K, n1, alpha=alpha, rho=rho)
+        dt1 = time.perf_counter() - t
     return dict(value=n / dt, unit="instance-iterations/s", cores=int(threads),
                 kind="oracle",
                 sample=f"{n} FP64 GDM iterations of the same {p.n_bus}-bus instance "
-                       f"(numpy, {threads} BLAS threads), {dt:.1f} s")
+                       f"(numpy, {threads} BLAS threads), {dt:.1f} s",
+                value_one_thread=n1 / dt1, sample_one_thread=f"{n1} iterations, {dt1:.1f} s")
 
 
 MIXED = [("bus4600", 4600, 512, 46_000_000), ("bus2000", 2000, 128, 20_000_000),
@@ -109,10 +117,11 @@ def bench_mixed(args, stream):
     import torch
 
     from paper_2406_13191_amd import _abi, synth
-    nets, shapes = [], []
+    nets, shapes, bases = [], [], []
     for name, seed, B, seed0 in MIXED:
         t = time.perf_counter()
         _, base = synth.make_network(name, seed)
+        bases.append(base)
         print(f"[bench] network {name}: {time.perf_counter() - t:.1f} s", file=sys.stderr,
               flush=True)
         Dm, Cc, Q = synth.make_scenarios(base, seed0, B, 0.1, 0.1)
@@ -141,6 +150,21 @@ def bench_mixed(args, stream):
     b.close()
     splits = [t["w_split"] for t in tiles]
     bw, bu, bf = batch_phase_bytes(shapes, splits)
+    # the same instances one at a time on the single-instance path (FP32
+    # products): seconds for one iteration of all of them, against the batch
+    single = {}
+    for (name, nl, nc, ng, B), base in zip(shapes, bases):
+        r = synth.STEP_RULES[name]
+        with _abi.DualSolver(base, stream=stream.cuda_stream, rule="gdm", alpha=r["alpha"],
+                             rho=r["rho"], precision="fp32", graph_iters=100) as s1:
+            s1.step(200)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s1.step(2000)
+            torch.cuda.synchronize()
+            single[name] = 2000 / (time.perf_counter() - t0)
+    t_single = sum(B / single[name] for name, nl, nc, ng, B in shapes)
+    t_batch = ms / args.steps / 1e3
     phases = {"w": ("W product (W^T = V^T P, split-BF16 MFMA)", ms_w, bw),
               "units": ("unit pass (reduced costs, inner minimiser, lambda step)", ms_u, bu),
               "f": ("F product (F^T = X^T P^T, split-BF16 MFMA, mu step)", ms_f, bf)}
@@ -164,7 +188,12 @@ def bench_mixed(args, stream):
                                 achieved_tflops=round(mfma_tflops, 2),
                                 peak_tflops=BF16_PEAK_TFLOPS,
                                 frac=round(mfma_tflops / BF16_PEAK_TFLOPS, 4))),
-        shapes=shapes, tiles=tiles)
+        shapes=shapes, tiles=tiles,
+        single_path=dict(rates={k: round(v, 1) for k, v in single.items()},
+                         unit="instance-iterations/s",
+                         seconds_per_batch_iteration=t_single,
+                         batched_seconds_per_iteration=t_batch,
+                         speedup=round(t_single / t_batch, 1)))
 
 
 def batch_phase_bytes(shapes, splits):
@@ -325,7 +354,8 @@ def main():
             "config": {"workload": "mixed batch: " + ", ".join(
                 f"{B} x {n} ({nl} lines, {nc} generator buses)" for n, nl, nc, ng, B in r["shapes"])
                 + "; split-BF16 MFMA products, FP32 line state, FP64 lambda and bound; GDM",
-                "instances": r["n_total"], "tiles": r["tiles"]},
+                "instances": r["n_total"], "tiles": r["tiles"],
+                "vs_single_instance_path": r["single_path"]},
             "roofline": r["roofline"], "cpu_baseline": None,
         }
         print(json.dumps(out), flush=True)

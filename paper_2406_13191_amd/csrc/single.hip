@@ -298,26 +298,36 @@ __global__ __launch_bounds__(256) void colpass_kernel(
 #pragma unroll
         for (int u = 0; u < CB; ++u) acc[u] = fma_vec(pv[m][u], xv[m], acc[u]);
   } else {
-    T acc2[CB];
+    // streamed: four chunks of every owned row per lane and iteration, all
+    // loaded before they are used
+    T acc2[CB], acc3[CB], acc4[CB];
 #pragma unroll
-    for (int u = 0; u < CB; ++u) acc2[u] = (T)0;
+    for (int u = 0; u < CB; ++u) acc2[u] = acc3[u] = acc4[u] = (T)0;
     int i = cb + lane;
-    for (; i + kWave < ce; i += 2 * kWave) {
-      const V x0 = vv[i], x1 = vv[i + kWave];
+    for (; i + 3 * kWave < ce; i += 4 * kWave) {
+      V x[4], p[4][CB];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        x[m] = vv[i + m * kWave];
+#pragma unroll
+        for (int u = 0; u < CB; ++u) p[m][u] = __builtin_nontemporal_load(rows[u] + i + m * kWave);
+      }
 #pragma unroll
       for (int u = 0; u < CB; ++u) {
-        acc[u] = fma_vec(__builtin_nontemporal_load(rows[u] + i), x0, acc[u]);
-        acc2[u] = fma_vec(__builtin_nontemporal_load(rows[u] + i + kWave), x1, acc2[u]);
+        acc[u] = fma_vec(p[0][u], x[0], acc[u]);
+        acc2[u] = fma_vec(p[1][u], x[1], acc2[u]);
+        acc3[u] = fma_vec(p[2][u], x[2], acc3[u]);
+        acc4[u] = fma_vec(p[3][u], x[3], acc4[u]);
       }
     }
-    if (i < ce) {
+    for (; i < ce; i += kWave) {
       const V x0 = vv[i];
 #pragma unroll
       for (int u = 0; u < CB; ++u)
         acc[u] = fma_vec(__builtin_nontemporal_load(rows[u] + i), x0, acc[u]);
     }
 #pragma unroll
-    for (int u = 0; u < CB; ++u) acc[u] += acc2[u];
+    for (int u = 0; u < CB; ++u) acc[u] = (acc[u] + acc2[u]) + (acc3[u] + acc4[u]);
     cf = ldg(c + tf);
     qf = ldg(q + tf);
     lof = ldg(pmin + tf);
