@@ -260,25 +260,35 @@ class AscentResult:
     best_iter: int
     iters: int             # updates performed
     stopped: bool          # True when |gamma_{k} - gamma_{k-1}| < tol fired
+    x_sum: np.ndarray | None = None  # sum of the inner minimisers p*_k, k >= average_from
+    n_avg: int = 0                   # number of terms in x_sum
 
 
 def ascent(K: Canonical, n_iters: int, rule: str = "gdm", alpha: float = 1e-3,
            rho: float = 0.9, beta1: float = 0.9, beta2: float = 0.999,
            eps: float = 1e-8, literal: bool = False, tol: float = 0.0,
-           state: AscentState | None = None) -> AscentResult:
+           state: AscentState | None = None,
+           average_from: int | None = None) -> AscentResult:
     """Projected dual ascent (Section 3.3, Algorithm 1) for ``n_iters`` updates.
 
     Iteration k evaluates the dual and its supergradient at the current
     iterate (gamma_k), then updates.  With tol > 0 the loop stops when
     |gamma_k - gamma_{k-1}| < tol (the stopping test of Algorithm 1).
+    With average_from = k0 the inner minimisers p*_k of the iterations
+    k0 <= k < n_iters are summed (primal recovery, ``primal_eval``).
     """
     st = AscentState.cold(K.n_line) if state is None else state.copy()
     gam = []
     stopped = False
     it = 0
+    x_sum = np.zeros_like(K.c) if average_from is not None else None
+    n_avg = 0
     for k in range(n_iters):
         ev = dual_value(K, st.lam, st.mu)
         gam.append(ev.g)
+        if average_from is not None and k >= average_from:
+            x_sum += ev.x
+            n_avg += 1
         if tol > 0 and k > 0 and abs(gam[-1] - gam[-2]) < tol:
             stopped = True
             break
@@ -294,4 +304,40 @@ def ascent(K: Canonical, n_iters: int, rule: str = "gdm", alpha: float = 1e-3,
     gam = np.array(gam)
     kb = int(np.argmax(gam))
     return AscentResult(state=st, gammas=gam, best=float(gam[kb]), best_iter=kb,
-                        iters=it, stopped=stopped)
+                        iters=it, stopped=stopped, x_sum=x_sum, n_avg=n_avg)
+
+
+# ---------------------------------------------------------------------------
+# Primal recovery by ergodic averaging.  Not in the paper (which compares its
+# lower bounds with solver optima): the average of the inner minimisers over
+# a window of iterations is a primal candidate whose constraint residuals,
+# the constraints being affine, are the averages of the supergradients; for
+# (sub)gradient ascent they vanish as the window grows, and its cost then
+# approaches the optimum from the other side of the lower bound.
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class PrimalEval:
+    x: np.ndarray            # candidate generator outputs
+    cost: float              # c^T x + x^T M x
+    balance: float           # 1^T d - 1^T x  (= A x - b)
+    overload: np.ndarray     # (C x - d)_+ per row: [F - f_max ; -F - f_max]_+
+    max_overload: float
+    sum_overload: float
+    n_overloaded: int
+
+
+def primal_eval(K: Canonical, x: np.ndarray) -> PrimalEval:
+    """Cost and constraint residuals of a primal candidate x in the box."""
+    x = np.asarray(x, dtype=np.float64)
+    ov = np.maximum(K.C @ x - K.d, 0.0)
+    return PrimalEval(x=x, cost=float(K.c @ x + x @ (K.M * x)),
+                      balance=float((K.A @ x - K.b)[0]), overload=ov,
+                      max_overload=float(ov.max()) if ov.size else 0.0,
+                      sum_overload=float(ov.sum()), n_overloaded=int(np.count_nonzero(ov)))
+
+
+def averaged_primal(res: AscentResult) -> np.ndarray:
+    """The ergodic average of an ascent run with ``average_from`` set."""
+    if res.x_sum is None or res.n_avg == 0:
+        raise ValueError("no iterations averaged")
+    return res.x_sum / res.n_avg
