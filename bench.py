@@ -405,6 +405,7 @@ def main():
     # time to a bound within 0.1 % of the FP64 optimum (HiGHS reference)
     ttb = None
     cpu = None
+    primal = None
     if not args.no_cpu:
         from oracle import ref
         opt = ref.opt_btheta(net, p)["opt"] if not p.is_qp else float("nan")
@@ -416,6 +417,18 @@ def main():
         ttb = None if p.is_qp else dict(reached=res["status"] == 1, iterations=int(res["iter_of_bound"]),
                    seconds=round(dt, 5), gap=res["gap"], check_every=100,
                    device_seconds=round(res["iter_of_bound"] * ms / args.steps / 1e3, 6))
+        # primal recovery: the average of p* over iterations 2000..10000
+        with _abi.DualSolver(p, stream=stream.cuda_stream, **kw) as s3:
+            s3.step(2000)
+            s3.average(True)
+            s3.step(8000)
+            pr = s3.primal()
+            lb = s3.bound()
+        primal = dict(window=[2000, 10000], cost=pr["cost"], lower_bound=lb,
+                      gap_to_opt=None if p.is_qp else (pr["cost"] - opt) / abs(opt),
+                      gap_to_bound=(pr["cost"] - lb) / abs(lb),
+                      balance_mw=pr["balance"], max_overload_mw=pr["max_overload"],
+                      overloaded_directions=pr["n_overloaded"])
         cpu = cpu_baseline(p, r["alpha"], r["rho"])
 
     out = {
@@ -430,7 +443,8 @@ def main():
                                f"panel; FP32 PTDF "
                                f"products, FP64 multipliers and bound; gradient with "
                                f"momentum alpha={r['alpha']}, rho={r['rho']}",
-                   "iterations": args.steps, "time_to_bound": ttb},
+                   "iterations": args.steps, "time_to_bound": ttb,
+                   "primal_recovery": primal},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

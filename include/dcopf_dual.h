@@ -182,6 +182,32 @@ dcopf_status dcopf_dual_set_state(dcopf_dual_t h, const double *buf, size_t len)
  * step).  The iterate and iteration count are restored.  Synchronises.     */
 dcopf_status dcopf_dual_time_phases(dcopf_dual_t h, int64_t n_iters, double *ms_out);
 
+/* Primal recovery (an extension; the paper reports only lower bounds and
+ * takes optima from a solver).  The ergodic average pbar of the inner
+ * minimisers p*_k over a window of iterations is a primal candidate: the
+ * constraints are affine, so its residuals are the averaged supergradients,
+ * which vanish as the window grows, and its cost then approaches the optimum
+ * from above the lower bound.                                               */
+typedef struct {
+  double cost;          /* sum_g c_g pbar_g + q_g pbar_g^2                   */
+  double balance;       /* 1^T d - 1^T pbar (MW)                             */
+  double max_overload;  /* largest (F_l - f_max,l)_+ or (-F_l - f_max,l)_+
+                           over lines, F = H (C_g pbar - d) (MW)             */
+  double sum_overload;  /* sum of those overloads over lines and directions */
+  int64_t iterations;   /* iterations averaged                               */
+  int32_t n_overloaded; /* line directions with a positive overload          */
+} dcopf_primal;
+
+/* enable = 1: restart the average; every following iteration adds its p*.
+ * enable = 0: stop adding (the sum is kept for dcopf_dual_primal).  The
+ * iterations of dcopf_dual_time_phases never add.  Synchronises.          */
+dcopf_status dcopf_dual_average(dcopf_dual_t h, int32_t enable);
+
+/* pbar = (sum of p*) / iterations and its cost and residuals, evaluated in
+ * FP64 on the device.  p_avg (host, [n_gen], generator order) may be NULL.
+ * DCOPF_E_STATE when no iteration has been averaged.  Synchronises.       */
+dcopf_status dcopf_dual_primal(dcopf_dual_t h, dcopf_primal *out, double *p_avg);
+
 /* Panel width (number of H columns the products use) and iterations done. */
 dcopf_status dcopf_dual_info(dcopf_dual_t h, int32_t *n_cols, int64_t *iters);
 

@@ -45,6 +45,12 @@ class Opts_C(C.Structure):
                 ("panel", C.c_int32), ("graph_iters", C.c_int32)]
 
 
+class Primal_C(C.Structure):
+    _fields_ = [("cost", C.c_double), ("balance", C.c_double), ("max_overload", C.c_double),
+                ("sum_overload", C.c_double), ("iterations", C.c_int64),
+                ("n_overloaded", C.c_int32)]
+
+
 class Result_C(C.Structure):
     _fields_ = [("bound", C.c_double), ("gamma_last", C.c_double), ("gap", C.c_double),
                 ("iters", C.c_int64), ("iter_of_bound", C.c_int64), ("status", C.c_int32)]
@@ -78,6 +84,8 @@ def _load():
         "dcopf_dual_get_state": (C.c_int, [C.c_void_p, P(C.c_double), C.c_size_t]),
         "dcopf_dual_set_state": (C.c_int, [C.c_void_p, P(C.c_double), C.c_size_t]),
         "dcopf_dual_info": (C.c_int, [C.c_void_p, P(C.c_int32), P(C.c_int64)]),
+        "dcopf_dual_average": (C.c_int, [C.c_void_p, C.c_int32]),
+        "dcopf_dual_primal": (C.c_int, [C.c_void_p, P(Primal_C), P(C.c_double)]),
         "dcopf_dual_time_phases": (C.c_int, [C.c_void_p, C.c_int64, P(C.c_double)]),
         "dcopf_dual_destroy": (None, [C.c_void_p]),
         "dcopf_last_error": (C.c_char_p, []),
@@ -207,9 +215,22 @@ class DualSolver:
         buf = _f64(buf)
         check(lib.dcopf_dual_set_state(self._h, _dptr(buf), buf.size))
 
+    def average(self, enable: bool = True):
+        """Restart (True) or stop (False) the primal average of p*."""
+        check(lib.dcopf_dual_average(self._h, 1 if enable else 0))
+
+    def primal(self):
+        """The averaged dispatch (generator order) with its cost and residuals."""
+        r = Primal_C()
+        p = np.zeros(self.n_gen)
+        check(lib.dcopf_dual_primal(self._h, C.byref(r), _dptr(p)))
+        return dict(cost=r.cost, balance=r.balance, max_overload=r.max_overload,
+                    sum_overload=r.sum_overload, iterations=r.iterations,
+                    n_overloaded=r.n_overloaded, p=p)
+
     def time_phases(self, n: int):
-        """Average (column pass, line pass) kernel durations in ms: each
-        pass launched n times back to back between one HIP event pair; the
+        """Average (column pass, line pass) kernel durations in ms over n
+        real iterations, each dispatch timed by events attached to it; the
         iterate is restored afterwards."""
         ms = np.zeros(2)
         check(lib.dcopf_dual_time_phases(self._h, int(n), _dptr(ms)))

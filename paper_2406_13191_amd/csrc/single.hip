@@ -55,6 +55,16 @@ struct DevScalars {
   double D;                  // 1^T d
   double gamma_last;         // monitor value of the last folded iterate
   double bound_gen, bound_value;
+  long long avg_count;       // iterations summed into the primal average
+  int avg_on;                // column passes add p* to the primal sum
+  int avg_pad;
+};
+
+// Result of the primal evaluation (device side of dcopf_primal).
+struct DevPrimal {
+  double cost, balance, max_overload, sum_overload;
+  long long count;
+  int n_overloaded, pad;
 };
 
 struct StepParams {
@@ -167,7 +177,8 @@ __device__ __forceinline__ void column_units(double w, double lam, int g0, int g
                                              const double *__restrict__ q,
                                              const double *__restrict__ pmin,
                                              const double *__restrict__ pmax, int lane,
-                                             double *xj, double *phij) {
+                                             double *xj, double *phij,
+                                             double *__restrict__ psum = nullptr) {
   double xs = 0.0, ph = 0.0;
   for (int t = g0 + lane; t < g1; t += kWave) {
     const bool first = t == g0 + lane;
@@ -176,6 +187,7 @@ __device__ __forceinline__ void column_units(double w, double lam, int g0, int g
     const double p = inner_min(r, qt, first ? lof : pmin[t], first ? hif : pmax[t]);
     ph += r * p + qt * p * p;
     xs += p;
+    if (psum) psum[t] += p;  // primal average (each unit has one owner lane)
   }
   *xj = wave_sum(xs);
   *phij = wave_sum(ph);
@@ -242,7 +254,8 @@ __global__ __launch_bounds__(256) void colpass_kernel(
     const int *__restrict__ seg, const double *__restrict__ c, const double *__restrict__ q,
     const double *__restrict__ pmin, const double *__restrict__ pmax, DevScalars *sc, int par,
     T *__restrict__ x_out, double *__restrict__ part_a, int ga, const double *__restrict__ part_b,
-    int gb, StepParams prm, double *__restrict__ gam_buf, long long gam_mask) {
+    int gb, StepParams prm, double *__restrict__ gam_buf, long long gam_mask,
+    double *__restrict__ psum) {
   using V = typename Vec16<T>::type;
   __shared__ double red[3 * 4];
   __shared__ double lam_s;
@@ -359,6 +372,7 @@ __global__ __launch_bounds__(256) void colpass_kernel(
         gam_buf[prev.k & gam_mask] = gam;
         sc->gamma_last = gam;
       }
+      if (sc->avg_on) sc->avg_count += 1;
     }
   }
   __syncthreads();
@@ -366,7 +380,8 @@ __global__ __launch_bounds__(256) void colpass_kernel(
   if (unit_wave) {
     const double w = (double)(((dots[0][wave] + dots[1][wave]) + dots[2][wave]) + dots[3][wave]);
     double xj, phij;
-    column_units(w, lam_s, g0, g1, cf, qf, lof, hif, c, q, pmin, pmax, lane, &xj, &phij);
+    column_units(w, lam_s, g0, g1, cf, qf, lof, hif, c, q, pmin, pmax, lane, &xj, &phij,
+                 sc->avg_on ? psum : nullptr);
     if (lane == 0) x_out[jw] = (T)xj;
     xsum = xj;
     phsum = phij;
@@ -440,7 +455,8 @@ __global__ __launch_bounds__(256) void colpass1_kernel(
     const int *__restrict__ seg, const double *__restrict__ c, const double *__restrict__ q,
     const double *__restrict__ pmin, const double *__restrict__ pmax, DevScalars *sc, int par,
     T *__restrict__ x_out, double *__restrict__ part_a, int ga, const double *__restrict__ part_b,
-    int gb, StepParams prm, double *__restrict__ gam_buf, long long gam_mask) {
+    int gb, StepParams prm, double *__restrict__ gam_buf, long long gam_mask,
+    double *__restrict__ psum) {
   using V = typename Vec16<T>::type;
   __shared__ T dots[4];
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -500,10 +516,15 @@ __global__ __launch_bounds__(256) void colpass1_kernel(
   }
   set_step(cur, prev.k + 1, prm);
   cur.pending = 1;
-  if (blockIdx.x == 0 && lane == 0) sc->slot[par] = cur;
+  const bool avg = sc->avg_on;
+  if (blockIdx.x == 0 && lane == 0) {
+    sc->slot[par] = cur;
+    if (avg) sc->avg_count += 1;
+  }
   const double w = (double)(((dots[0] + dots[1]) + dots[2]) + dots[3]);
   double xj, phij;
-  column_units(w, cur.lam, g0, g1, cf, qf, lof, hif, c, q, pmin, pmax, lane, &xj, &phij);
+  column_units(w, cur.lam, g0, g1, cf, qf, lof, hif, c, q, pmin, pmax, lane, &xj, &phij,
+               avg ? psum : nullptr);
   if (lane == 0) {
     x_out[j] = (T)xj;
     part_a[(size_t)par * 2 * ga + 2 * j] = xj;
@@ -669,6 +690,96 @@ __global__ __launch_bounds__(256) void finalize_kernel(DevScalars *sc, int par,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Primal recovery (not in the paper): the average pbar of the inner
+// minimisers summed by the column passes, its cost and its residuals, in
+// FP64.  Columns: pbar per unit, xbar per column (the averaged injection),
+// block partials of the cost and of the generation.  Lines: F = P xbar - f_d
+// (thread per line, from P^T), block partials of the largest overload, the
+// sum of overloads and their count.  A single-thread kernel combines them
+// in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kPrimalBlocks = 256;
+
+__global__ __launch_bounds__(256) void primal_cols_kernel(
+    const double *__restrict__ psum, const DevScalars *sc, const int *__restrict__ seg,
+    const double *__restrict__ c, const double *__restrict__ q, int n_cols,
+    double *__restrict__ pbar, double *__restrict__ xbar, double *__restrict__ part) {
+  __shared__ double red[2 * 4];
+  const double n = (double)sc->avg_count;
+  double v[2] = {0.0, 0.0};  // cost, generation
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n_cols; j += gridDim.x * blockDim.x) {
+    double xs = 0.0;
+    for (int u = seg[j]; u < seg[j + 1]; ++u) {
+      const double p = psum[u] / n;
+      pbar[u] = p;
+      v[0] += c[u] * p + q[u] * p * p;
+      xs += p;
+    }
+    xbar[j] = xs;
+    v[1] += xs;
+  }
+  block_sums<2>(v, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = v[0];
+    part[gridDim.x + blockIdx.x] = v[1];
+  }
+}
+
+__global__ __launch_bounds__(256) void primal_lines_kernel(
+    const double *__restrict__ P64T, int ldl, int n_cols, int n_lines,
+    const double *__restrict__ xbar, const double *__restrict__ fd,
+    const double *__restrict__ flim, double *__restrict__ part) {
+  __shared__ double red[2 * 4];
+  __shared__ double mx_s[4];
+  double mx = 0.0, v[2] = {0.0, 0.0};  // sum of overloads, count
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < n_lines; l += gridDim.x * blockDim.x) {
+    double F = 0.0;
+    for (int j = 0; j < n_cols; ++j) F += P64T[(size_t)j * ldl + l] * xbar[j];
+    F -= fd[l];
+    const double o1 = fmax(F - flim[l], 0.0), o2 = fmax(-F - flim[l], 0.0);
+    mx = fmax(mx, fmax(o1, o2));
+    v[0] += o1 + o2;
+    v[1] += (o1 > 0.0 ? 1.0 : 0.0) + (o2 > 0.0 ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
+  if (threadIdx.x % kWave == 0) mx_s[threadIdx.x / kWave] = mx;
+  block_sums<2>(v, red);  // its barriers also publish mx_s
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) m = fmax(m, mx_s[w]);
+    part[blockIdx.x] = m;
+    part[gridDim.x + blockIdx.x] = v[0];
+    part[2 * gridDim.x + blockIdx.x] = v[1];
+  }
+}
+
+__global__ void primal_final_kernel(const double *__restrict__ pc, int gc,
+                                    const double *__restrict__ pl, int gl, const DevScalars *sc,
+                                    DevPrimal *out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double cost = 0.0, gen = 0.0, mx = 0.0, sum = 0.0, cnt = 0.0;
+  for (int b = 0; b < gc; ++b) {
+    cost += pc[b];
+    gen += pc[gc + b];
+  }
+  for (int b = 0; b < gl; ++b) {
+    mx = fmax(mx, pl[b]);
+    sum += pl[gl + b];
+    cnt += pl[2 * gl + b];
+  }
+  DevPrimal r;
+  r.cost = cost;
+  r.balance = sc->D - gen;
+  r.max_overload = mx;
+  r.sum_overload = sum;
+  r.count = sc->avg_count;
+  r.n_overloaded = (int)cnt;
+  r.pad = 0;
+  *out = r;
+}
+
 // Exact bound, column part (FP64): sum over units of phi at the multipliers
 // (lambda from `lam`, v = mu+ - mu- in vvec), plus lambda D; last workgroup
 // finishes.
@@ -818,6 +929,7 @@ struct dcopf_dual_s {
   double *fd = nullptr, *fmax = nullptr, *c = nullptr, *q = nullptr, *pmin = nullptr,
          *pmax = nullptr;
   int *seg = nullptr, *gperm = nullptr;
+  std::vector<int> gperm_h;  // host copy: unit t of the column order is generator gperm_h[t]
   // state
   double *mu_p = nullptr, *mu_m = nullptr, *v_p = nullptr, *v_m = nullptr, *s_p = nullptr,
          *s_m = nullptr;
@@ -828,6 +940,9 @@ struct dcopf_dual_s {
   unsigned *counters = nullptr;
   DevScalars *sc = nullptr;
   double *gam = nullptr;
+  // primal average: sum of p* per unit (column order), evaluation buffers
+  double *psum = nullptr, *pbar = nullptr, *xbar = nullptr, *ppart = nullptr;
+  DevPrimal *primal = nullptr;
   // launch shapes
   int grid_col = 0, grid_line = 0, grid_bnd_col = 0, grid_bnd_line = 0;
   int n_line_part = 0;  // line-pass partials: one per wavefront
@@ -857,7 +972,7 @@ void launch_colpass_cb(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, h
   (void)launch_k(colpass_kernel<T, CB, UNR>, dim3(h->grid_col), dim3(256), 0, s, e0, e1, PT,
                  h->n_cols, h->ldl, (T *)h->vbuf, h->seg, h->c, h->q, h->pmin, h->pmax, h->sc,
                  par, (T *)h->xbuf, h->part_a, h->grid_col, h->part_b, h->n_line_part, h->prm,
-                 h->gam, kGamCap - 1);
+                 h->gam, kGamCap - 1, h->psum);
 }
 
 template <typename T, int UNR>
@@ -866,7 +981,7 @@ void launch_colpass1(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hip
   (void)launch_k(colpass1_kernel<T, UNR>, dim3(h->grid_col), dim3(256), 0, s, e0, e1, PT,
                  h->n_cols, h->ldl, (T *)h->vbuf, h->seg, h->c, h->q, h->pmin, h->pmax, h->sc,
                  par, (T *)h->xbuf, h->part_a, h->grid_col, h->part_b, h->n_line_part, h->prm,
-                 h->gam, kGamCap - 1);
+                 h->gam, kGamCap - 1, h->psum);
 }
 
 // one column per workgroup and a quarter of at most 8 chunks per lane: the
@@ -1012,7 +1127,8 @@ void free_handle(dcopf_dual_s *h) {
   void *ptrs[] = {h->P32, h->P32T, h->P64, h->P64T, h->fd, h->fmax, h->c, h->q,
                   h->pmin, h->pmax, h->seg, h->gperm, h->mu_p, h->mu_m, h->v_p, h->v_m,
                   h->s_p, h->s_m, h->vbuf, h->xbuf, h->v64b, h->part_a, h->part_b,
-                  h->part_c, h->part_d, h->counters, h->sc, h->gam};
+                  h->part_c, h->part_d, h->counters, h->sc, h->gam, h->psum, h->pbar,
+                  h->xbar, h->ppart, h->primal};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete h;
@@ -1125,6 +1241,11 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   h->part_d = dalloc<double>((size_t)h->grid_bnd_col, &st);
   h->counters = dalloc<unsigned>(8, &st);
   h->sc = dalloc<DevScalars>(1, &st);
+  h->psum = dalloc<double>(ng, &st);
+  h->pbar = dalloc<double>(ng, &st);
+  h->xbar = dalloc<double>((size_t)h->n_cols, &st);
+  h->ppart = dalloc<double>(3 * (size_t)kPrimalBlocks, &st);
+  h->primal = dalloc<DevPrimal>(1, &st);
   h->gam = dalloc<double>(kGamCap, &st);
   double *Hd = nullptr, *dd = nullptr;
   int *dcols = nullptr;
@@ -1166,6 +1287,7 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   chk(hipMemcpyAsync(h->fmax, p->f_max, nl * 8, hipMemcpyHostToDevice, s));
   chk(hipMemcpyAsync(h->seg, seg.data(), (nc + 1) * 4, hipMemcpyHostToDevice, s));
   chk(hipMemcpyAsync(h->gperm, gperm.data(), ng * 4, hipMemcpyHostToDevice, s));
+  h->gperm_h = gperm;
   for (double **sp : state) chk(hipMemsetAsync(*sp, 0, nl * 8, s));
   chk(hipMemsetAsync(h->xbuf, 0, (size_t)h->ldc * esz, s));
   chk(hipMemsetAsync(h->counters, 0, 8 * sizeof(unsigned), s));
@@ -1464,6 +1586,9 @@ dcopf_status dcopf_dual_time_phases(dcopf_dual_t h, int64_t n, double *ms_out) {
     DCOPF_HIP_TRY(hipMemcpyAsync(save + i * nl, arrs[i], nl * 8, hipMemcpyDeviceToDevice, s));
   DCOPF_HIP_TRY(hipMemcpyAsync(vsave, h->vbuf, (size_t)h->ldl * esz, hipMemcpyDeviceToDevice, s));
   DCOPF_HIP_TRY(hipMemcpyAsync(ssave, h->sc, sizeof(DevScalars), hipMemcpyDeviceToDevice, s));
+  // the timed iterations add nothing to a primal average in progress
+  static const int zero = 0;
+  DCOPF_HIP_TRY(hipMemcpyAsync(&h->sc->avg_on, &zero, sizeof(int), hipMemcpyHostToDevice, s));
   std::vector<hipEvent_t> ev(4 * (size_t)n, nullptr);
   for (auto &e : ev) DCOPF_HIP_TRY(hipEventCreate(&e));
   for (int64_t i = 0; i < n; ++i) {
@@ -1489,6 +1614,56 @@ dcopf_status dcopf_dual_time_phases(dcopf_dual_t h, int64_t n, double *ms_out) {
   (void)hipFree(save);
   (void)hipFree(vsave);
   (void)hipFree(ssave);
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_dual_average(dcopf_dual_t h, int32_t enable) {
+  if (!h) return set_error("null handle"), DCOPF_E_INVALID;
+  DCOPF_HIP_TRY(hipStreamSynchronize(h->stream));
+  DevScalars sch;
+  dcopf_status st = read_scalars(h, &sch);
+  if (st != DCOPF_OK) return st;
+  if (enable) {
+    DCOPF_HIP_TRY(hipMemset(h->psum, 0, (size_t)h->n_gen * 8));
+    sch.avg_count = 0;
+  }
+  sch.avg_on = enable ? 1 : 0;
+  DCOPF_HIP_TRY(hipMemcpy(h->sc, &sch, sizeof(sch), hipMemcpyHostToDevice));
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_dual_primal(dcopf_dual_t h, dcopf_primal *out, double *p_avg) {
+  if (!h || !out) return set_error("null argument"), DCOPF_E_INVALID;
+  DevScalars sch;
+  dcopf_status st = read_scalars(h, &sch);  // synchronises
+  if (st != DCOPF_OK) return st;
+  if (sch.avg_count <= 0) return set_error("no iterations averaged"), DCOPF_E_STATE;
+  const int gc = std::max(1, std::min(kPrimalBlocks, (h->n_cols + 255) / 256));
+  const int gl = std::max(1, std::min(kPrimalBlocks, (h->n_lines + 255) / 256));
+  hipStream_t s = h->stream;
+  primal_cols_kernel<<<gc, 256, 0, s>>>(h->psum, h->sc, h->seg, h->c, h->q, h->n_cols, h->pbar,
+                                        h->xbar, h->ppart);
+  primal_lines_kernel<<<gl, 256, 0, s>>>(h->P64T, h->ldl, h->n_cols, h->n_lines, h->xbar, h->fd,
+                                         h->fmax, h->ppart + 2 * kPrimalBlocks);
+  primal_final_kernel<<<1, 64, 0, s>>>(h->ppart, gc, h->ppart + 2 * kPrimalBlocks, gl, h->sc,
+                                       h->primal);
+  DCOPF_HIP_TRY(hipGetLastError());
+  DevPrimal r;
+  DCOPF_HIP_TRY(hipMemcpyAsync(&r, h->primal, sizeof(r), hipMemcpyDeviceToHost, s));
+  std::vector<double> pb;
+  if (p_avg) {
+    pb.resize(h->n_gen);
+    DCOPF_HIP_TRY(hipMemcpyAsync(pb.data(), h->pbar, pb.size() * 8, hipMemcpyDeviceToHost, s));
+  }
+  DCOPF_HIP_TRY(hipStreamSynchronize(s));
+  out->cost = r.cost;
+  out->balance = r.balance;
+  out->max_overload = r.max_overload;
+  out->sum_overload = r.sum_overload;
+  out->iterations = r.count;
+  out->n_overloaded = r.n_overloaded;
+  if (p_avg)  // unit t of the column order is generator gperm_h[t]
+    for (int t = 0; t < h->n_gen; ++t) p_avg[h->gperm_h[t]] = pb[t];
   return DCOPF_OK;
 }
 
