@@ -226,7 +226,7 @@ struct StridedSum {
     double s = 0.0;
 #pragma unroll
     for (int m = 0; m < kPre; ++m)
-      if (threadIdx.x + m * blockDim.x < n) s += v[m];
+      if ((int)(threadIdx.x + m * blockDim.x) < n) s += v[m];
     for (int idx = threadIdx.x + kPre * blockDim.x; idx < n; idx += blockDim.x)
       s += a[(size_t)idx * stride + off];
     return s;
@@ -814,7 +814,7 @@ __global__ __launch_bounds__(256) void bound_col_kernel(
   if (threadIdx.x == 0) store_agent(part + blockIdx.x, bphi);
   if (!last_block_done(counter, &last_flag)) return;
   double t = 0.0;
-  for (int b = threadIdx.x; b < gridDim.x; b += blockDim.x) t += load_agent(part + b);
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) t += load_agent(part + b);
   t = block_sum(t, red);
   if (threadIdx.x == 0) sc->bound_gen = t + lam * sc->D;
 }
@@ -834,7 +834,7 @@ __global__ __launch_bounds__(256) void bound_lines_kernel(
   if (threadIdx.x == 0) store_agent(part + blockIdx.x, s);
   if (!last_block_done(counter, &last_flag)) return;
   double t = 0.0;
-  for (int b = threadIdx.x; b < gridDim.x; b += blockDim.x) t += load_agent(part + b);
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) t += load_agent(part + b);
   t = block_sum(t, red);
   if (threadIdx.x == 0) sc->bound_value = sc->bound_gen - t;
 }
