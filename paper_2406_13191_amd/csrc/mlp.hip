@@ -50,30 +50,60 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
          z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
-// C tile of 64 x 64 per workgroup (2 x 2 wavefronts of 32 x 32).
+// C tile of 32 x 32 per workgroup; its four wavefronts split K (wavefront w
+// takes the 64-deep K steps w, w + 4, ...), each keeping the loads of its
+// next step in flight while it multiplies the current one, and their
+// accumulators meet in LDS in wavefront order.  Wavefront 0 runs the
+// epilogue.  Small products (a batch of a few hundred rows) thus still
+// spread over many workgroups, and long K loops are cut four ways.
 __global__ __launch_bounds__(256) void gemm_nt_kernel(const __bf16 *__restrict__ A, int lda,
                                                       const __bf16 *__restrict__ Bt, int ldb,
                                                       int K, int Mp, int Np, Epi e) {
+  __shared__ float part[3][16][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int m0 = blockIdx.y * 64 + (wave >> 1) * 32, n0 = blockIdx.x * 64 + (wave & 1) * 32;
-  if (m0 >= Mp || n0 >= Np) return;  // whole wavefront
+  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
   const int r = lane & 31, koff = (lane >> 5) * 8;
   const __bf16 *a = A + (size_t)(m0 + r) * lda + koff;
   const __bf16 *b = Bt + (size_t)(n0 + r) * ldb + koff;
   f32x16m acc;
 #pragma unroll
   for (int j = 0; j < 16; ++j) acc[j] = 0.f;
-  for (int k = 0; k < K; k += 64) {
-    bf16x8m av[4], bv[4];
+  const int nsteps = K / 64;
+  bf16x8m av[2][4], bv[2][4];
+  auto fetch = [&](bf16x8m (&qa)[4], bf16x8m (&qb)[4], int step) {
+    const int k = min(step, nsteps - 1) * 64;  // clamped: always in range
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      av[u] = *reinterpret_cast<const bf16x8m *>(a + k + 16 * u);
-      bv[u] = *reinterpret_cast<const bf16x8m *>(b + k + 16 * u);
+      qa[u] = ldg(reinterpret_cast<const bf16x8m *>(a + k + 16 * u));
+      qb[u] = ldg(reinterpret_cast<const bf16x8m *>(b + k + 16 * u));
     }
+  };
+  int st = wave;
+  if (st < nsteps) {
+    fetch(av[0], bv[0], st);
+    fetch(av[1], bv[1], st + 4);
+    for (; st + 4 < nsteps; st += 8) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[u], bv[u], acc, 0, 0, 0);
+      for (int u = 0; u < 4; ++u)
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[0][u], bv[0][u], acc, 0, 0, 0);
+      fetch(av[0], bv[0], st + 8);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[1][u], bv[1][u], acc, 0, 0, 0);
+      fetch(av[1], bv[1], st + 12);
+    }
+    if (st < nsteps)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[0][u], bv[0][u], acc, 0, 0, 0);
   }
+  if (wave > 0)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) part[wave - 1][j][lane] = acc[j];
+  __syncthreads();
+  if (wave > 0) return;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = ((acc[j] + part[0][j][lane]) + part[1][j][lane]) + part[2][j][lane];
   const int n = n0 + r;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
@@ -148,13 +178,28 @@ __global__ __launch_bounds__(256) void loss_sum_kernel(const double *__restrict_
 }
 
 // db[n] = sum over the batch rows of d[m][n] (fixed order).
-__global__ void colsum_kernel(const float *__restrict__ d, int ld, int batch, int n_real,
-                              float *__restrict__ db) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= n_real) return;
-  float s = 0.f;
-  for (int m = 0; m < batch; ++m) s += d[(size_t)m * ld + n];
-  db[n] = s;
+// Column sums (bias gradients): a workgroup owns 64 columns; its four
+// wavefronts each add a quarter of the rows, eight independent rows at a
+// time (lane = column, coalesced), and the quarters meet in LDS in order.
+__global__ __launch_bounds__(256) void colsum_kernel(const float *__restrict__ d, int ld,
+                                                     int batch, int n_real,
+                                                     float *__restrict__ db) {
+  __shared__ float q[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + lane;
+  const int nc = n < n_real ? n : 0;
+  const int per = (batch + 3) / 4, r0 = wave * per, r1 = min(batch, r0 + per);
+  float acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = 0.f;
+  int m = r0;
+  for (; m + 8 <= r1; m += 8)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += d[(size_t)(m + u) * ld + nc];
+  for (; m < r1; ++m) acc[0] += d[(size_t)m * ld + nc];
+  q[wave][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  __syncthreads();
+  if (wave == 0 && n < n_real) db[n] = ((q[0][lane] + q[1][lane]) + q[2][lane]) + q[3][lane];
 }
 
 // Adam on the FP32 masters (compact parameter vector).
@@ -173,15 +218,24 @@ __global__ void adam_kernel(float *__restrict__ p, float *__restrict__ mo, float
 }
 
 // BF16 copies of W [out][in] (compact FP32): W_b [OUTp][INp], W_t [INp][OUTp].
-__global__ void wcopy_kernel(const float *__restrict__ W, int out, int in, int OUTp, int INp,
-                             __bf16 *__restrict__ Wb, __bf16 *__restrict__ Wt) {
-  const int o = blockIdx.y;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < INp; i += gridDim.x * blockDim.x) {
+// BF16 copies of a weight matrix in both orientations, through a 64 x 64
+// LDS tile so that both the row-major and the transposed writes are
+// coalesced; padded rows and columns are written as zero.
+__global__ __launch_bounds__(256) void wcopy_kernel(const float *__restrict__ W, int out, int in,
+                                                    int OUTp, int INp, __bf16 *__restrict__ Wb,
+                                                    __bf16 *__restrict__ Wt) {
+  __shared__ __bf16 t[64][66];
+  const int o0 = blockIdx.y * 64, i0 = blockIdx.x * 64;
+  const int c = threadIdx.x & 63, r4 = threadIdx.x >> 6;
+  for (int r = r4; r < 64; r += 4) {
+    const int o = o0 + r, i = i0 + c;
     const float v = (o < out && i < in) ? W[(size_t)o * in + i] : 0.f;
     const __bf16 b = (__bf16)v;
+    t[r][c] = b;
     Wb[(size_t)o * INp + i] = b;
-    Wt[(size_t)i * OUTp + o] = b;
   }
+  __syncthreads();
+  for (int r = r4; r < 64; r += 4) Wt[(size_t)(i0 + r) * OUTp + o0 + c] = t[c][r];
 }
 
 // compact Y [batch][n_out] from the padded Y
@@ -235,18 +289,19 @@ void free_mlp(dcopf_mlp_s *m) {
 
 void gemm(dcopf_mlp_s *m, const __bf16 *A, int lda, const __bf16 *Bt, int ldb, int K, int Mp,
           int Np, const Epi &e) {
-  dim3 grid((unsigned)(Np / 64), (unsigned)(Mp / 64));
+  dim3 grid((unsigned)(Np / 32), (unsigned)(Mp / 32));
   gemm_nt_kernel<<<grid, 256, 0, m->stream>>>(A, lda, Bt, ldb, K, Mp, Np, e);
 }
 
 void refresh_weights(dcopf_mlp_s *m) {
   const dcopf_mlp_config &c = m->cfg;
   hipStream_t s = m->stream;
-  wcopy_kernel<<<dim3((unsigned)((m->I + 255) / 256), (unsigned)m->A1), 256, 0, s>>>(
+  // padded extents are multiples of 64: the 64 x 64 tiles cover them exactly
+  wcopy_kernel<<<dim3((unsigned)(m->I / 64), (unsigned)(m->A1 / 64)), 256, 0, s>>>(
       m->p + m->off[0], c.h1, c.n_in, m->A1, m->I, m->W1b, m->W1t);
-  wcopy_kernel<<<dim3((unsigned)((m->A1 + 255) / 256), (unsigned)m->A2), 256, 0, s>>>(
+  wcopy_kernel<<<dim3((unsigned)(m->A1 / 64), (unsigned)(m->A2 / 64)), 256, 0, s>>>(
       m->p + m->off[2], c.h2, c.h1, m->A2, m->A1, m->W2b, m->W2t);
-  wcopy_kernel<<<dim3((unsigned)((m->A2 + 255) / 256), (unsigned)m->O), 256, 0, s>>>(
+  wcopy_kernel<<<dim3((unsigned)(m->A2 / 64), (unsigned)(m->O / 64)), 256, 0, s>>>(
       m->p + m->off[4], c.n_out, c.h2, m->O, m->A2, m->W3b, m->W3t);
 }
 
@@ -275,20 +330,20 @@ void backward_pass(dcopf_mlp_s *m, const float *T, int batch) {
   // dW3 = dY^T H2 ; db3
   Epi g3{EPI_F32, c.n_out, c.h2, nullptr, m->g + m->off[4], 0, nullptr, nullptr, 0, nullptr};
   gemm(m, m->dYt, m->Bm, m->H2t, m->Bm, Mp, m->O, m->A2, g3);
-  colsum_kernel<<<(c.n_out + 255) / 256, 256, 0, s>>>(m->dY32, m->O, batch, c.n_out,
+  colsum_kernel<<<(c.n_out + 63) / 64, 256, 0, s>>>(m->dY32, m->O, batch, c.n_out,
                                                       m->g + m->off[5]);
   // dZ2 = (dY W3) * gelu'(Z2)
   Epi d2{EPI_DHID, batch, c.h2, nullptr, m->dZ2, m->A2, m->dZ2b, m->dZ2t, m->Bm, m->Z2};
   gemm(m, m->dYb, m->O, m->W3t, m->O, m->O, Mp, m->A2, d2);
   Epi g2{EPI_F32, c.h2, c.h1, nullptr, m->g + m->off[2], 0, nullptr, nullptr, 0, nullptr};
   gemm(m, m->dZ2t, m->Bm, m->H1t, m->Bm, Mp, m->A2, m->A1, g2);
-  colsum_kernel<<<(c.h2 + 255) / 256, 256, 0, s>>>(m->dZ2, m->A2, batch, c.h2, m->g + m->off[3]);
+  colsum_kernel<<<(c.h2 + 63) / 64, 256, 0, s>>>(m->dZ2, m->A2, batch, c.h2, m->g + m->off[3]);
   // dZ1 = (dZ2 W2) * gelu'(Z1)
   Epi d1{EPI_DHID, batch, c.h1, nullptr, m->dZ1, m->A1, m->dZ1b, m->dZ1t, m->Bm, m->Z1};
   gemm(m, m->dZ2b, m->A2, m->W2t, m->A2, m->A2, Mp, m->A1, d1);
   Epi g1{EPI_F32, c.h1, c.n_in, nullptr, m->g + m->off[0], 0, nullptr, nullptr, 0, nullptr};
   gemm(m, m->dZ1t, m->Bm, m->Xt, m->Bm, Mp, m->A1, m->I, g1);
-  colsum_kernel<<<(c.h1 + 255) / 256, 256, 0, s>>>(m->dZ1, m->A1, batch, c.h1, m->g + m->off[1]);
+  colsum_kernel<<<(c.h1 + 63) / 64, 256, 0, s>>>(m->dZ1, m->A1, batch, c.h1, m->g + m->off[1]);
 }
 
 void adam(dcopf_mlp_s *m, double lr) {
