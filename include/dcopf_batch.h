@@ -107,6 +107,19 @@ dcopf_status dcopf_batch_get_multipliers(dcopf_batch_t b, int32_t net, double *l
 dcopf_status dcopf_batch_set_multipliers(dcopf_batch_t b, int32_t net, const double *lambda,
                                          const double *mu_plus, const double *mu_minus);
 
+/* Primal recovery (an extension, as dcopf_dual_average / dcopf_dual_primal):
+ * enable = 1 restarts the average of every instance's inner minimiser p*
+ * over the following iterations (including those of time_phases, which
+ * advance the batch); enable = 0 stops adding.  Synchronises.             */
+dcopf_status dcopf_batch_average(dcopf_batch_t b, int32_t enable);
+
+/* For network `net`: out[n_inst] receives each instance's averaged dispatch
+ * cost, balance residual and line overloads (FP64 products on the device);
+ * p_avg (host, [n_inst * n_gen], generator order) may be NULL.
+ * DCOPF_E_STATE when no iteration has been averaged.  Synchronises.       */
+dcopf_status dcopf_batch_primal(dcopf_batch_t b, int32_t net, dcopf_primal *out,
+                                double *p_avg);
+
 /* Tile shapes in use for network `net`: cfg[0], cfg[1] = instances x
  * columns of one W-product workgroup tile, cfg[2] = its K split (over
  * lines), cfg[3] = instances * 1000 + lines of one F-product tile.         */

@@ -288,6 +288,8 @@ def _bind_batch():
                                                   P(C.c_double), P(C.c_double)]),
         "dcopf_batch_info": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int32), P(C.c_int64)]),
         "dcopf_batch_set_tiles": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int32)]),
+        "dcopf_batch_average": (C.c_int, [C.c_void_p, C.c_int32]),
+        "dcopf_batch_primal": (C.c_int, [C.c_void_p, C.c_int32, P(Primal_C), P(C.c_double)]),
         "dcopf_batch_time_phases": (C.c_int, [C.c_void_p, C.c_int64, P(C.c_double)]),
         "dcopf_batch_destroy": (None, [C.c_void_p]),
     }
@@ -411,6 +413,23 @@ class BatchSolver:
         cfg = np.array([w_tile[0], w_tile[1], w_split, f_tile[0] * 1000 + f_tile[1]], np.int32)
         check(lib.dcopf_batch_set_tiles(self._h, int(net),
                                         cfg.ctypes.data_as(C.POINTER(C.c_int32))))
+
+    def average(self, enable: bool = True):
+        """Restart (True) or stop (False) every instance's primal average."""
+        check(lib.dcopf_batch_average(self._h, 1 if enable else 0))
+
+    def primal(self, net: int):
+        """Network `net`'s averaged dispatches [n_inst, n_gen] (generator
+        order) with per-instance cost and residuals, as arrays."""
+        n = self.networks[net]
+        ng = np.asarray(n.base.gen_bus).size
+        r = (Primal_C * n.B)()
+        p = np.zeros((n.B, ng))
+        check(lib.dcopf_batch_primal(self._h, int(net), r, _dptr(p)))
+        f = lambda k: np.array([getattr(x, k) for x in r])
+        return dict(cost=f("cost"), balance=f("balance"), max_overload=f("max_overload"),
+                    sum_overload=f("sum_overload"), iterations=int(r[0].iterations),
+                    n_overloaded=f("n_overloaded"), p=p)
 
     def time_phases(self, n: int):
         ms = np.zeros(3)

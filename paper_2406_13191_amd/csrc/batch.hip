@@ -63,6 +63,13 @@ struct BNet {
   double *linepart;                             // [ntl][Bp]
   double *V64, *W64;                            // [Bp][ldl], [Bp][ncp]
   double *bound;                                // [B]
+  // primal average (an extension): sum of p* per instance and unit
+  // (column-sorted), the FP64 panel [lines][ldc] for F = P xbar, buffers
+  double *psum;                                 // [B][n_g]
+  double *P64;                                  // [nlp][ldc]
+  double *X64, *F64;                            // [Bp][ldc], [Bp][nlp]
+  double *pbar;                                 // [B][n_g]
+  double *ppart;                                // [B][5]: cost, generation, max, sum, count
 };
 
 struct BIter {
@@ -73,6 +80,8 @@ struct BIter {
 
 struct BScal {
   BIter it[2];
+  long long avg_count;  // iterations summed into the primal average
+  int avg_on, avg_pad;  // unit passes add p* to the primal sums
 };
 
 struct BParams {
@@ -402,6 +411,7 @@ __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ net
     lam = N.lam[(size_t)par * N.B + i];
   }
   double xs = 0.0, phs = 0.0;
+  const bool avg = sc->avg_on;
 #pragma unroll
   for (int h = 0; h < kUnitCPT; ++h) {
     if (!valid[h]) continue;
@@ -421,6 +431,7 @@ __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ net
       const double p = inner_min_b(r, qu, lo, hi);
       phs += r * p + qu * p * p;
       x += p;
+      if (avg) N.psum[(size_t)i * N.n_g + u] += p;  // unit u of instance i: one owner
     }
     __bf16 xh, xl;
     split_bf16((float)x, &xh, &xl);
@@ -440,6 +451,7 @@ __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ net
       nx.pending = 1;
       nx.pad = 0;
       sc->it[par ^ 1] = nx;
+      if (avg) sc->avg_count += 1;
     }
   }
 }
@@ -696,6 +708,74 @@ __global__ __launch_bounds__(256) void bound_inst_kernel(BNet N, int par) {
   if (threadIdx.x == 0) N.bound[i] = phis + lam * N.D[i] - lines;
 }
 
+// ---- primal average (an extension) ------------------------------------------
+constexpr int kPrimalColBlocks = 16;  // column blocks per instance in the evaluation
+
+// Workgroup (column block, instance): pbar per unit, the averaged injection
+// xbar per column (FP64, zero in the padding), and the block's cost and
+// generation.
+__global__ __launch_bounds__(256) void bprimal_cols_kernel(BNet N, const BScal *sc,
+                                                           double *__restrict__ part) {
+  __shared__ double red[2 * 4];
+  const int i = blockIdx.y;
+  const double n = (double)sc->avg_count;
+  const double *ci = N.c + (size_t)i * N.n_g, *qi = N.q + (size_t)i * N.n_g;
+  double v[2] = {0.0, 0.0};
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N.ldc; j += gridDim.x * blockDim.x) {
+    double xs = 0.0;
+    if (j < N.n_c)
+      for (int u = N.seg[j]; u < N.seg[j + 1]; ++u) {
+        const double p = N.psum[(size_t)i * N.n_g + u] / n;
+        N.pbar[(size_t)i * N.n_g + u] = p;
+        v[0] += ci[u] * p + qi[u] * p * p;
+        xs += p;
+      }
+    N.X64[(size_t)i * N.ldc + j] = xs;
+    v[1] += xs;
+  }
+  block_sums<2>(v, red);
+  if (threadIdx.x == 0) {
+    part[((size_t)i * gridDim.x + blockIdx.x) * 2] = v[0];
+    part[((size_t)i * gridDim.x + blockIdx.x) * 2 + 1] = v[1];
+  }
+}
+
+// One workgroup per instance: F = (P xbar) - f_d against the limits (FP64),
+// then the instance's cost, balance and overloads in a fixed order.
+__global__ __launch_bounds__(256) void bprimal_inst_kernel(BNet N, const BScal *sc,
+                                                           const double *__restrict__ part,
+                                                           int gc, double *__restrict__ out) {
+  __shared__ double red[2 * 4];
+  __shared__ double mx_s[4];
+  const int i = blockIdx.x;
+  double mx = 0.0, v[2] = {0.0, 0.0};  // sum of overloads, their count
+  for (int l = threadIdx.x; l < N.n_l; l += blockDim.x) {
+    const double F = N.F64[(size_t)i * N.nlp + l] - N.fd64[(size_t)i * N.n_l + l];
+    const double o1 = fmax(F - N.flim64[l], 0.0), o2 = fmax(-F - N.flim64[l], 0.0);
+    mx = fmax(mx, fmax(o1, o2));
+    v[0] += o1 + o2;
+    v[1] += (o1 > 0.0 ? 1.0 : 0.0) + (o2 > 0.0 ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, kWave));
+  if (threadIdx.x % kWave == 0) mx_s[threadIdx.x / kWave] = mx;
+  block_sums<2>(v, red);  // its barriers also publish mx_s
+  if (threadIdx.x == 0) {
+    double cost = 0.0, gen = 0.0, m = 0.0;
+    for (int b = 0; b < gc; ++b) {
+      cost += part[((size_t)i * gc + b) * 2];
+      gen += part[((size_t)i * gc + b) * 2 + 1];
+    }
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) m = fmax(m, mx_s[w]);
+    double *o = out + (size_t)i * 5;
+    o[0] = cost;
+    o[1] = N.D[i] - gen;
+    o[2] = m;
+    o[3] = v[0];
+    o[4] = v[1];
+  }
+}
+
 // ---- setup -----------------------------------------------------------------
 // tmp[l][j] = H[l][cols[j]] (zero padded to [nlp][ldc]) in FP64.
 __global__ void bgather_kernel(const double *__restrict__ H, int n_bus, int n_l,
@@ -766,6 +846,7 @@ namespace {
 
 struct HostNet {
   BNet d{};  // device pointers (owned) and shapes
+  std::vector<int> gperm;  // unit t of the column order is generator gperm[t]
   int n_bus = 0;
   std::vector<void *> owned;
   double best_dummy = 0;
@@ -1155,6 +1236,7 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
   for (int g = 0; g < ng; ++g) seg[col_of_bus[n.gen_bus[g]] + 1]++;
   for (int j = 0; j < nc; ++j) seg[j + 1] += seg[j];
   hn.n_bus = nb;
+  hn.gperm = gperm;
   N.n_l = nl;
   N.n_c = nc;
   N.n_g = ng;
@@ -1201,6 +1283,12 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
   N.V64 = balloc<double>(own, Bp * ldl, &ok);
   N.W64 = balloc<double>(own, Bp * ncp, &ok);
   N.bound = balloc<double>(own, B, &ok);
+  N.psum = balloc<double>(own, (size_t)B * ng, &ok);
+  N.pbar = balloc<double>(own, (size_t)B * ng, &ok);
+  N.P64 = balloc<double>(own, nlp * ldc, &ok);
+  N.X64 = balloc<double>(own, Bp * ldc, &ok);
+  N.F64 = balloc<double>(own, Bp * nlp, &ok);
+  N.ppart = balloc<double>(own, (size_t)B * (2 * kPrimalColBlocks + 5), &ok);
   if (!ok) return set_error("device allocation failed"), DCOPF_E_NOMEM;
   N.PT_hi = PT_hi;
   N.PT_lo = PT_lo;
@@ -1242,6 +1330,7 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
     // panel: gather, split; transpose to FP64 P^T, split
     dim3 gg((unsigned)std::min<size_t>(64, (ldc + 255) / 256), (unsigned)nlp);
     bgather_kernel<<<gg, 256, 0, s>>>(Hd, (int)ldb, nl, dcols, nc, (int)ldc, tmp);
+    chk(hipMemcpyAsync(N.P64, tmp, nlp * ldc * 8, hipMemcpyDeviceToDevice, s));
     bsplit_kernel<<<2048, 256, 0, s>>>(tmp, nlp * ldc, P_hi, P_lo);
     dim3 tg((unsigned)(ncp / 32), (unsigned)(ldl / 32));
     btranspose_kernel<<<tg, dim3(32, 8), 0, s>>>(tmp, nl, (int)ldc, (int)ncp, (int)ldl, P64T);
@@ -1280,6 +1369,8 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
     chk(hipMemsetAsync(N.X_lo, 0, Bp * ldc * 2, s));
     chk(hipMemsetAsync(N.V64, 0, Bp * ldl * 8, s));
     chk(hipMemsetAsync(N.linepart, 0, (size_t)(nlp / 32) * Bp * 8, s));
+    chk(hipMemsetAsync(N.psum, 0, (size_t)B * ng * 8, s));
+    chk(hipMemsetAsync(N.X64, 0, Bp * ldc * 8, s));
     chk(hipStreamSynchronize(s));
   }
   if (Hd) (void)hipFree(Hd);
@@ -1537,6 +1628,60 @@ dcopf_status dcopf_batch_set_multipliers(dcopf_batch_t b, int32_t net, const dou
   DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
   std::fill(b->best.begin(), b->best.end(), -INFINITY);
   std::fill(b->best_iter.begin(), b->best_iter.end(), -1);
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_average(dcopf_batch_t b, int32_t enable) {
+  if (!b) return set_error("null handle"), DCOPF_E_INVALID;
+  DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
+  BScal h{};
+  DCOPF_HIP_TRY(hipMemcpy(&h, b->sc, sizeof(h), hipMemcpyDeviceToHost));
+  if (enable) {
+    for (auto &hn : b->nets)
+      DCOPF_HIP_TRY(hipMemset(hn.d.psum, 0, (size_t)hn.d.B * hn.d.n_g * 8));
+    h.avg_count = 0;
+  }
+  h.avg_on = enable ? 1 : 0;
+  DCOPF_HIP_TRY(hipMemcpy(b->sc, &h, sizeof(h), hipMemcpyHostToDevice));
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_primal(dcopf_batch_t b, int32_t net, dcopf_primal *out,
+                                double *p_avg) {
+  if (!b || !out || net < 0 || net >= (int)b->nets.size())
+    return set_error("bad arguments"), DCOPF_E_INVALID;
+  DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
+  BScal h{};
+  DCOPF_HIP_TRY(hipMemcpy(&h, b->sc, sizeof(h), hipMemcpyDeviceToHost));
+  if (h.avg_count <= 0) return set_error("no iterations averaged"), DCOPF_E_STATE;
+  const HostNet &hn = b->nets[net];
+  const BNet &N = hn.d;
+  hipStream_t s = b->stream;
+  const int gc = std::max(1, std::min(kPrimalColBlocks, (N.ldc + 255) / 256));
+  double *part = N.ppart, *res = N.ppart + (size_t)N.B * 2 * kPrimalColBlocks;
+  bprimal_cols_kernel<<<dim3((unsigned)gc, (unsigned)N.B), 256, 0, s>>>(N, b->sc, part);
+  dim3 dg((unsigned)(N.nlp / 16), (unsigned)(N.Bp / 64));
+  dgemm_nt_kernel<<<dg, 256, 0, s>>>(N.X64, N.P64, N.F64, N.ldc, N.nlp, N.Bp);
+  bprimal_inst_kernel<<<N.B, 256, 0, s>>>(N, b->sc, part, gc, res);
+  DCOPF_HIP_TRY(hipGetLastError());
+  std::vector<double> r((size_t)N.B * 5), pb;
+  DCOPF_HIP_TRY(hipMemcpyAsync(r.data(), res, r.size() * 8, hipMemcpyDeviceToHost, s));
+  if (p_avg) {
+    pb.resize((size_t)N.B * N.n_g);
+    DCOPF_HIP_TRY(hipMemcpyAsync(pb.data(), N.pbar, pb.size() * 8, hipMemcpyDeviceToHost, s));
+  }
+  DCOPF_HIP_TRY(hipStreamSynchronize(s));
+  for (int i = 0; i < N.B; ++i) {
+    out[i].cost = r[(size_t)i * 5];
+    out[i].balance = r[(size_t)i * 5 + 1];
+    out[i].max_overload = r[(size_t)i * 5 + 2];
+    out[i].sum_overload = r[(size_t)i * 5 + 3];
+    out[i].iterations = h.avg_count;
+    out[i].n_overloaded = (int32_t)r[(size_t)i * 5 + 4];
+    if (p_avg)
+      for (int t = 0; t < N.n_g; ++t)
+        p_avg[(size_t)i * N.n_g + hn.gperm[t]] = pb[(size_t)i * N.n_g + t];
+  }
   return DCOPF_OK;
 }
 
