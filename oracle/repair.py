@@ -1,0 +1,108 @@
+"""FP64 oracle: repair of a primal candidate into a feasible dispatch.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Not in the paper, whose lower bounds are compared with solver optima.  A
+feasible dispatch p gives an upper bound c^T p + p^T M p >= OPT, so together
+with the dual's exact lower bound it certifies the gap without an external
+solver.  The candidate (for instance the ergodic average of the inner
+minimisers) is nearly feasible; the repair moves it the least, in a norm
+weighted by each generator's headroom, onto the constraints it violates.
+
+Constraints of the canonical problem (Section 2.1, eq. general) with
+A = -1^T and C = [H_a C_g; -H_a C_g]: the balance 1^T x = 1^T p_d, the line
+rows C x <= d, and the box.  One round:
+
+  1. residuals: r = C x - d per row, beta = 1^T p_d - 1^T x;
+  2. every violated row (r > 0, at most one direction per line) joins the
+     active set, in line order, keeping its direction; a line already held
+     in the other direction switches to this one;
+  3. stop when no row is violated and |beta| <= 1e-9 max(1, 1^T p_d);
+  4. weights w_g = max(min(x_g - p_min_g, p_max_g - x_g), 1e-3 (p_max_g -
+     p_min_g)): the headroom, floored so that a generator at a bound can
+     still move inward (a move outward is undone by the clip of step 6);
+  5. rows a_i = (H_a C_g)[l_i, :] of the active lines with targets
+     t_i = -(delta + r_i) in flow units (the flow change that leaves the row
+     delta inside its limit), and the balance row a = 1 with target beta;
+  6. y solves (A W A^T + eps I) y = t, eps = 1e-12 max diag, and
+     x <- clip(x + W A^T y, p_min, p_max).
+
+Before the clip, the step is the minimiser of sum_g dx_g^2 / w_g subject to
+the active rows holding their targets exactly.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from oracle.dual import Canonical, primal_eval
+
+MARGIN = 1e-6          # MW inside each held limit
+BALANCE_TOL = 1e-9     # relative to max(1, total load)
+MAX_ROWS = 256         # active lines + the balance row
+WEIGHT_FLOOR = 1e-3    # of each generator's range
+
+
+@dataclasses.dataclass
+class RepairResult:
+    x: np.ndarray
+    feasible: bool
+    rounds: int            # correction steps taken
+    active: list           # [(line, direction)] in the order they joined
+    cost: float
+    balance: float
+    max_overload: float
+    max_shift: float
+
+
+def repair(K: Canonical, x0: np.ndarray, max_rounds: int = 32) -> RepairResult:
+    nl = K.n_line
+    D = -float(K.b[0])
+    tol = BALANCE_TOL * max(1.0, abs(D))
+    lo, hi = K.lo, K.hi
+    x = np.clip(np.asarray(x0, dtype=np.float64), lo, hi)
+    HC = K.C[:nl]
+    active: dict[int, int] = {}     # line -> direction (+1 / -1), insertion ordered
+    rounds = 0
+    feasible = False
+    while True:
+        r = K.C @ x - K.d
+        beta = float(K.A[0] @ x - K.b[0])       # 1^T p_d - 1^T x
+        viol = False
+        for line in range(nl):
+            if r[line] > 0.0:
+                active[line] = 1
+                viol = True
+            elif r[nl + line] > 0.0:
+                active[line] = -1
+                viol = True
+        if not viol and abs(beta) <= tol:
+            feasible = True
+            break
+        if rounds >= max_rounds or len(active) + 1 > MAX_ROWS:
+            break
+        w = np.maximum(np.minimum(x - lo, hi - x), WEIGHT_FLOOR * (hi - lo))
+        lines = list(active.keys())
+        Am = np.vstack([HC[lines], np.ones((1, x.size))])
+        t = np.empty(len(lines) + 1)
+        for i, line in enumerate(lines):
+            # flow change that leaves the row MARGIN inside: direction +1 wants
+            # r+ = -MARGIN (dF = -MARGIN - r+); direction -1 wants r- = -MARGIN
+            # (dF = MARGIN + r-)
+            t[i] = (-MARGIN - r[line]) if active[line] > 0 else (MARGIN + r[nl + line])
+        t[-1] = beta
+        G = (Am * w) @ Am.T
+        dmax = float(np.max(np.diag(G)))
+        if not dmax > 0.0:
+            break
+        G += 1e-12 * dmax * np.eye(G.shape[0])
+        L = np.linalg.cholesky(G)
+        y = np.linalg.solve(L.T, np.linalg.solve(L, t))
+        x = np.clip(x + w * (Am.T @ y), lo, hi)
+        rounds += 1
+    pe = primal_eval(K, x)
+    return RepairResult(x=x, feasible=feasible, rounds=rounds,
+                        active=[(k, v) for k, v in active.items()], cost=pe.cost,
+                        balance=pe.balance, max_overload=pe.max_overload,
+                        max_shift=float(np.max(np.abs(x - np.clip(x0, lo, hi)))) if x.size else 0.0)
