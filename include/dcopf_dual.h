@@ -208,6 +208,39 @@ dcopf_status dcopf_dual_average(dcopf_dual_t h, int32_t enable);
  * DCOPF_E_STATE when no iteration has been averaged.  Synchronises.       */
 dcopf_status dcopf_dual_primal(dcopf_dual_t h, dcopf_primal *out, double *p_avg);
 
+/* Repair (an extension, as the primal average): a feasible dispatch near a
+ * primal candidate.  Its cost is an upper bound on the optimum, so with the
+ * exact lower bound it certifies the gap without an external solver.
+ * Starting from p = the candidate clipped to the generator box, each round
+ * evaluates F = H (C_g p - d) and 1^T d - 1^T p in FP64; stops when no line
+ * direction is violated and |1^T d - 1^T p| <= 1e-9 max(1, 1^T d);
+ * otherwise adds every violated line direction to an active set (in line
+ * order; a line held in one direction switches if the other is violated;
+ * at most 255 lines) and moves p by the correction of least
+ * sum_g dp_g^2 / w_g, w_g = max(min(p_g - p_min_g, p_max_g - p_g),
+ * 1e-3 (p_max_g - p_min_g)), that holds every active line 1e-6 MW inside
+ * its limit and closes the balance (Gram system with a ridge of 1e-12 of
+ * its largest diagonal, Cholesky in FP64), then clips p to the box.       */
+typedef struct {
+  double cost;          /* sum_g c_g p_g + q_g p_g^2 of the result: an upper
+                           bound on the optimum when feasible                */
+  double balance;       /* 1^T d - 1^T p (MW)                                */
+  double max_overload;  /* largest line overload of the result (MW)         */
+  double max_shift;     /* largest |p_g - candidate_g| after the first clip  */
+  int32_t feasible;     /* 1: the stop rule was met                          */
+  int32_t rounds;       /* correction steps taken                            */
+  int32_t n_active;     /* line limits held                                  */
+  int32_t pad;
+} dcopf_repair;
+
+/* p_in: host [n_gen] in generator order, or NULL for the current primal
+ * average (DCOPF_E_STATE when nothing has been averaged).  max_rounds >= 0.
+ * p_out: host [n_gen], generator order, may be NULL.  A candidate the rounds
+ * do not repair is not an error: feasible = 0.  DCOPF_E_INVALID for a
+ * negative max_rounds or a non-finite p_in.  Synchronises.                */
+dcopf_status dcopf_dual_repair(dcopf_dual_t h, const double *p_in, int32_t max_rounds,
+                               dcopf_repair *out, double *p_out);
+
 /* Panel width (number of H columns the products use) and iterations done. */
 dcopf_status dcopf_dual_info(dcopf_dual_t h, int32_t *n_cols, int64_t *iters);
 

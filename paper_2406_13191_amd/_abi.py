@@ -51,6 +51,12 @@ class Primal_C(C.Structure):
                 ("n_overloaded", C.c_int32)]
 
 
+class Repair_C(C.Structure):
+    _fields_ = [("cost", C.c_double), ("balance", C.c_double), ("max_overload", C.c_double),
+                ("max_shift", C.c_double), ("feasible", C.c_int32), ("rounds", C.c_int32),
+                ("n_active", C.c_int32), ("pad", C.c_int32)]
+
+
 class Result_C(C.Structure):
     _fields_ = [("bound", C.c_double), ("gamma_last", C.c_double), ("gap", C.c_double),
                 ("iters", C.c_int64), ("iter_of_bound", C.c_int64), ("status", C.c_int32)]
@@ -86,6 +92,8 @@ def _load():
         "dcopf_dual_info": (C.c_int, [C.c_void_p, P(C.c_int32), P(C.c_int64)]),
         "dcopf_dual_average": (C.c_int, [C.c_void_p, C.c_int32]),
         "dcopf_dual_primal": (C.c_int, [C.c_void_p, P(Primal_C), P(C.c_double)]),
+        "dcopf_dual_repair": (C.c_int, [C.c_void_p, P(C.c_double), C.c_int32, P(Repair_C),
+                                        P(C.c_double)]),
         "dcopf_dual_time_phases": (C.c_int, [C.c_void_p, C.c_int64, P(C.c_double)]),
         "dcopf_dual_destroy": (None, [C.c_void_p]),
         "dcopf_last_error": (C.c_char_p, []),
@@ -227,6 +235,18 @@ class DualSolver:
         return dict(cost=r.cost, balance=r.balance, max_overload=r.max_overload,
                     sum_overload=r.sum_overload, iterations=r.iterations,
                     n_overloaded=r.n_overloaded, p=p)
+
+    def repair(self, p=None, max_rounds: int = 32):
+        """A feasible dispatch near p (generator order), or near the current
+        primal average when p is None; its cost and residuals."""
+        r = Repair_C()
+        out = np.zeros(self.n_gen)
+        pin = None if p is None else _f64(p)
+        check(lib.dcopf_dual_repair(self._h, None if pin is None else _dptr(pin),
+                                    int(max_rounds), C.byref(r), _dptr(out)))
+        return dict(cost=r.cost, balance=r.balance, max_overload=r.max_overload,
+                    max_shift=r.max_shift, feasible=bool(r.feasible), rounds=r.rounds,
+                    n_active=r.n_active, p=out)
 
     def time_phases(self, n: int):
         """Average (column pass, line pass) kernel durations in ms over n

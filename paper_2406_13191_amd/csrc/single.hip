@@ -729,7 +729,7 @@ __global__ __launch_bounds__(256) void primal_cols_kernel(
 __global__ __launch_bounds__(256) void primal_lines_kernel(
     const double *__restrict__ P64T, int ldl, int n_cols, int n_lines,
     const double *__restrict__ xbar, const double *__restrict__ fd,
-    const double *__restrict__ flim, double *__restrict__ part) {
+    const double *__restrict__ flim, double *__restrict__ part, double *__restrict__ Fout) {
   __shared__ double red[2 * 4];
   __shared__ double mx_s[4];
   double mx = 0.0, v[2] = {0.0, 0.0};  // sum of overloads, count
@@ -737,6 +737,7 @@ __global__ __launch_bounds__(256) void primal_lines_kernel(
     double F = 0.0;
     for (int j = 0; j < n_cols; ++j) F += P64T[(size_t)j * ldl + l] * xbar[j];
     F -= fd[l];
+    if (Fout) Fout[l] = F;
     const double o1 = fmax(F - flim[l], 0.0), o2 = fmax(-F - flim[l], 0.0);
     mx = fmax(mx, fmax(o1, o2));
     v[0] += o1 + o2;
@@ -777,6 +778,316 @@ __global__ void primal_final_kernel(const double *__restrict__ pc, int gc,
   r.count = sc->avg_count;
   r.n_overloaded = (int)cnt;
   r.pad = 0;
+  *out = r;
+}
+
+// ---------------------------------------------------------------------------
+// Repair of a primal candidate into a feasible dispatch (not in the paper).
+// One round: units -> column sums x and weights W (FP64), F = P x - f_d per
+// line from P^T (primal_lines_kernel), then one workgroup appends the
+// violated line directions to the active set in line order and forms the
+// targets; the Gram matrix of the active rows and the balance row under the
+// weights (one wavefront per entry), its Cholesky factorisation and solve
+// in one workgroup, and the step of every unit, clipped to its box.  A unit's
+// row value is its column's, so the Gram entries are sums over columns of
+// W_c a_ic a_jc with W_c the sum of the column's unit weights.
+// ---------------------------------------------------------------------------
+constexpr int kRepRows = 256;          // active lines + the balance row
+constexpr double kRepMargin = 1e-6;    // MW inside each held limit
+constexpr double kRepBalTol = 1e-9;    // of max(1, 1^T d)
+constexpr double kRepFloor = 1e-3;     // weight floor, of a unit's range
+constexpr double kRepRidge = 1e-12;    // of the largest Gram diagonal
+
+struct RepairState {
+  double beta;   // 1^T d - 1^T p of the evaluated iterate
+  int n_viol;    // violated line directions
+  int m_old, m;  // active lines before / after this evaluation
+  int overflow;  // more than kRepRows - 1 lines would be active
+  int done;      // stop rule met
+  int fail;      // the Gram matrix was not positive definite
+};
+
+struct DevRepair {
+  double cost, balance, max_overload, max_shift;
+};
+
+__device__ __forceinline__ double rep_weight(double p, double lo, double hi) {
+  return fmax(fmin(p - lo, hi - p), kRepFloor * (hi - lo));
+}
+
+// p = p0c = clip(p0); every line outside the active set; empty set.
+__global__ void repair_init_kernel(const double *__restrict__ p0, const double *__restrict__ lo,
+                                   const double *__restrict__ hi, int n_gen, int n_lines,
+                                   double *__restrict__ p, double *__restrict__ p0c,
+                                   int *__restrict__ pos, RepairState *st) {
+  const int n = max(n_gen, n_lines);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (i < n_gen) {
+      const double v = fmin(fmax(p0[i], lo[i]), hi[i]);
+      p[i] = v;
+      p0c[i] = v;
+    }
+    if (i < n_lines) pos[i] = -1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    RepairState s{};
+    *st = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void repair_cols_kernel(
+    const double *__restrict__ p, const int *__restrict__ seg, const double *__restrict__ c,
+    const double *__restrict__ q, const double *__restrict__ lo, const double *__restrict__ hi,
+    int n_cols, double *__restrict__ x, double *__restrict__ W, double *__restrict__ part) {
+  __shared__ double red[2 * 4];
+  double v[2] = {0.0, 0.0};  // cost, generation
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n_cols; j += gridDim.x * blockDim.x) {
+    double xs = 0.0, ws = 0.0;
+    for (int u = seg[j]; u < seg[j + 1]; ++u) {
+      const double pu = p[u];
+      v[0] += c[u] * pu + q[u] * pu * pu;
+      xs += pu;
+      ws += rep_weight(pu, lo[u], hi[u]);
+    }
+    x[j] = xs;
+    W[j] = ws;
+    v[1] += xs;
+  }
+  block_sums<2>(v, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = v[0];
+    part[gridDim.x + blockIdx.x] = v[1];
+  }
+}
+
+// One workgroup of 256: violations, ordered append to the active set (rows,
+// sgn; pos[l] = row of line l or -1), targets t[0..m] (t[m]: balance).
+__global__ __launch_bounds__(256) void repair_active_kernel(
+    const double *__restrict__ F, const double *__restrict__ flim, int n_lines,
+    const double *__restrict__ pcols, int gc, const DevScalars *sc, int *__restrict__ pos,
+    int *__restrict__ rows, int *__restrict__ sgn, double *__restrict__ t, RepairState *st) {
+  __shared__ int wave_new[4];
+  __shared__ int m_s, viol_s, over_s, fail_s;
+  __shared__ double beta_s;
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  if (tid == 0) {
+    double gen = 0.0;
+    for (int b = 0; b < gc; ++b) gen += pcols[gc + b];
+    beta_s = sc->D - gen;
+    m_s = st->m;
+    viol_s = 0;
+    over_s = st->overflow;
+    fail_s = st->fail;
+  }
+  __syncthreads();
+  const int m_old = m_s;
+  for (int base = 0; base < n_lines; base += 256) {
+    const int l = base + tid;
+    int sigma = 0;
+    if (l < n_lines) {
+      const double Fl = F[l];
+      if (Fl - flim[l] > 0.0)
+        sigma = 1;
+      else if (-Fl - flim[l] > 0.0)
+        sigma = -1;
+    }
+    bool fresh = false;
+    if (sigma != 0) {
+      const int r = pos[l];
+      if (r >= 0)
+        sgn[r] = sigma;  // held line: keep its row, take this direction
+      else
+        fresh = true;
+    }
+    const unsigned long long mask = __ballot(fresh);
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_new[wave] = __popcll(mask);
+    const int nviol = __popcll(__ballot(sigma != 0));
+    __syncthreads();
+    int off = m_s;
+    for (int w = 0; w < wave; ++w) off += wave_new[w];
+    if (fresh) {
+      const int r = off + before;
+      if (r < kRepRows - 1) {
+        rows[r] = l;
+        sgn[r] = sigma;
+        pos[l] = r;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int add = 0;
+      for (int w = 0; w < 4; ++w) add += wave_new[w];
+      m_s += add;
+    }
+    if (lane == 0) atomicAdd(&viol_s, nviol);
+    __syncthreads();
+  }
+  int m = m_s;
+  const bool over = m > kRepRows - 1;
+  if (over) m = kRepRows - 1;
+  for (int i = tid; i < m; i += blockDim.x) {
+    const int l = rows[i];
+    const double Fl = F[l];
+    // flow change that leaves the row kRepMargin inside its limit
+    t[i] = sgn[i] > 0 ? (-kRepMargin - (Fl - flim[l])) : (kRepMargin + (-Fl - flim[l]));
+  }
+  if (tid == 0) {
+    t[m] = beta_s;
+    RepairState s;
+    s.beta = beta_s;
+    s.n_viol = viol_s;
+    s.m_old = m_old;
+    s.m = m;
+    s.overflow = (over || over_s) ? 1 : 0;
+    s.done = (viol_s == 0 && fabs(beta_s) <= kRepBalTol * fmax(1.0, fabs(sc->D))) ? 1 : 0;
+    s.fail = fail_s;
+    *st = s;
+  }
+}
+
+// A[i][c] = P[rows[i]][c] for the rows that joined, zero beyond n_cols.
+__global__ void repair_gather_kernel(const double *__restrict__ P64T, int ldl, int n_cols,
+                                     int ldc, const int *__restrict__ rows, int m_old,
+                                     double *__restrict__ A) {
+  const int i = m_old + blockIdx.y;
+  const int l = rows[i];
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ldc; j += gridDim.x * blockDim.x)
+    A[(size_t)i * ldc + j] = j < n_cols ? P64T[(size_t)j * ldl + l] : 0.0;
+}
+
+// G[i][j] (i >= j, n = m + 1 rows; row m is the balance row of ones):
+// one wavefront per entry, entries in row-major order of the lower triangle.
+__global__ __launch_bounds__(256) void repair_gram_kernel(const double *__restrict__ A, int ldc,
+                                                          const double *__restrict__ W,
+                                                          int n_cols, int m,
+                                                          double *__restrict__ G) {
+  const int n = m + 1;
+  const long long k = (long long)blockIdx.x * 4 + threadIdx.x / kWave;
+  if (k >= (long long)n * (n + 1) / 2) return;
+  int i = (int)((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
+  while ((long long)(i + 1) * (i + 2) / 2 <= k) ++i;
+  while ((long long)i * (i + 1) / 2 > k) --i;
+  const int j = (int)(k - (long long)i * (i + 1) / 2);
+  const int lane = threadIdx.x % kWave;
+  const double *ai = A + (size_t)i * ldc, *aj = A + (size_t)j * ldc;
+  double s = 0.0;
+  for (int c = lane; c < n_cols; c += kWave) {
+    const double a = i < m ? ai[c] : 1.0, b = j < m ? aj[c] : 1.0;
+    s += W[c] * a * b;
+  }
+  s = wave_sum(s);
+  if (lane == 0) G[(size_t)i * kRepRows + j] = s;
+}
+
+// One workgroup: ridge, Cholesky G = L L^T in place (lower triangle), then
+// L L^T y = t.  st->fail when a pivot is not positive.
+__global__ __launch_bounds__(1024) void repair_solve_kernel(double *__restrict__ G, int m,
+                                                            const double *__restrict__ t,
+                                                            double *__restrict__ y,
+                                                            RepairState *st) {
+  __shared__ double red[16];
+  __shared__ int fail_s;
+  const int n = m + 1, tid = threadIdx.x, nt = blockDim.x;
+  auto g = [&](int i, int j) -> double & { return G[(size_t)i * kRepRows + j]; };
+  double dm = 0.0;
+  for (int i = tid; i < n; i += nt) dm = fmax(dm, g(i, i));
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) dm = fmax(dm, __shfl_xor(dm, off, kWave));
+  if (tid % kWave == 0) red[tid / kWave] = dm;
+  if (tid == 0) fail_s = 0;
+  __syncthreads();
+  dm = 0.0;
+  for (int w = 0; w < nt / kWave; ++w) dm = fmax(dm, red[w]);
+  if (!(dm > 0.0)) {
+    if (tid == 0) st->fail = 1;
+    return;
+  }
+  for (int i = tid; i < n; i += nt) g(i, i) += kRepRidge * dm;
+  for (int i = tid; i < n; i += nt) y[i] = t[i];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      const double d = g(k, k);
+      if (d > 0.0)
+        g(k, k) = sqrt(d);
+      else
+        fail_s = 1;
+    }
+    __syncthreads();
+    if (fail_s) break;
+    const double dk = g(k, k);
+    for (int i = k + 1 + tid; i < n; i += nt) g(i, k) /= dk;
+    __syncthreads();
+    const int r = n - k - 1;
+    for (int idx = tid; idx < r * r; idx += nt) {
+      const int ii = idx / r, jj = idx % r;
+      if (jj <= ii) g(k + 1 + ii, k + 1 + jj) -= g(k + 1 + ii, k) * g(k + 1 + jj, k);
+    }
+    __syncthreads();
+  }
+  if (fail_s) {
+    if (tid == 0) st->fail = 1;
+    return;
+  }
+  for (int k = 0; k < n; ++k) {  // L z = t
+    if (tid == 0) y[k] /= g(k, k);
+    __syncthreads();
+    const double yk = y[k];
+    for (int i = k + 1 + tid; i < n; i += nt) y[i] -= g(i, k) * yk;
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {  // L^T y = z
+    if (tid == 0) y[k] /= g(k, k);
+    __syncthreads();
+    const double yk = y[k];
+    for (int i = tid; i < k; i += nt) y[i] -= g(k, i) * yk;
+    __syncthreads();
+  }
+}
+
+// p_u += w_u z_c (z_c = sum_i y_i A[i][c] + y_m), clipped to the box.
+__global__ __launch_bounds__(256) void repair_step_kernel(
+    const double *__restrict__ A, int ldc, const double *__restrict__ y, int m,
+    const int *__restrict__ seg, const double *__restrict__ lo, const double *__restrict__ hi,
+    int n_cols, const RepairState *st, double *__restrict__ p) {
+  if (st->fail) return;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n_cols; j += gridDim.x * blockDim.x) {
+    double z = 0.0;
+    for (int i = 0; i < m; ++i) z += y[i] * A[(size_t)i * ldc + j];
+    z += y[m];
+    for (int u = seg[j]; u < seg[j + 1]; ++u) {
+      const double pu = p[u];
+      p[u] = fmin(fmax(pu + rep_weight(pu, lo[u], hi[u]) * z, lo[u]), hi[u]);
+    }
+  }
+}
+
+// One workgroup: cost, balance, largest overload and largest shift.
+__global__ __launch_bounds__(256) void repair_final_kernel(
+    const double *__restrict__ pc, int gc, const double *__restrict__ pl, int gl,
+    const DevScalars *sc, const double *__restrict__ p, const double *__restrict__ p0c,
+    int n_gen, DevRepair *out) {
+  __shared__ double mx_s[4];
+  double sh = 0.0;
+  for (int u = threadIdx.x; u < n_gen; u += blockDim.x) sh = fmax(sh, fabs(p[u] - p0c[u]));
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) sh = fmax(sh, __shfl_xor(sh, off, kWave));
+  if (threadIdx.x % kWave == 0) mx_s[threadIdx.x / kWave] = sh;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double cost = 0.0, gen = 0.0, mo = 0.0, shift = 0.0;
+  for (int b = 0; b < gc; ++b) {
+    cost += pc[b];
+    gen += pc[gc + b];
+  }
+  for (int b = 0; b < gl; ++b) mo = fmax(mo, pl[b]);
+  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) shift = fmax(shift, mx_s[w]);
+  DevRepair r;
+  r.cost = cost;
+  r.balance = sc->D - gen;
+  r.max_overload = mo;
+  r.max_shift = shift;
   *out = r;
 }
 
@@ -943,6 +1254,16 @@ struct dcopf_dual_s {
   // primal average: sum of p* per unit (column order), evaluation buffers
   double *psum = nullptr, *pbar = nullptr, *xbar = nullptr, *ppart = nullptr;
   DevPrimal *primal = nullptr;
+  // primal repair (allocated by its first call)
+  struct Repair {
+    double *pin = nullptr, *p = nullptr, *p0c = nullptr, *x = nullptr, *W = nullptr,
+           *F = nullptr, *t = nullptr, *y = nullptr, *G = nullptr, *A = nullptr, *pc = nullptr,
+           *pl = nullptr;
+    int *pos = nullptr, *rows = nullptr, *sgn = nullptr;
+    RepairState *st = nullptr;
+    DevRepair *out = nullptr;
+    bool ready = false;
+  } rep;
   // launch shapes
   int grid_col = 0, grid_line = 0, grid_bnd_col = 0, grid_bnd_line = 0;
   int n_line_part = 0;  // line-pass partials: one per wavefront
@@ -1131,6 +1452,11 @@ void free_handle(dcopf_dual_s *h) {
                   h->xbar, h->ppart, h->primal};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  auto &R = h->rep;
+  void *rptrs[] = {R.pin, R.p, R.p0c, R.x, R.W, R.F, R.t, R.y, R.G, R.A, R.pc, R.pl,
+                   R.pos, R.rows, R.sgn, R.st, R.out};
+  for (void *p : rptrs)
+    if (p) (void)hipFree(p);
   delete h;
 }
 
@@ -1244,7 +1570,7 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   h->psum = dalloc<double>(ng, &st);
   h->pbar = dalloc<double>(ng, &st);
   h->xbar = dalloc<double>((size_t)h->n_cols, &st);
-  h->ppart = dalloc<double>(3 * (size_t)kPrimalBlocks, &st);
+  h->ppart = dalloc<double>(5 * (size_t)kPrimalBlocks, &st);  // column and line partials
   h->primal = dalloc<DevPrimal>(1, &st);
   h->gam = dalloc<double>(kGamCap, &st);
   double *Hd = nullptr, *dd = nullptr;
@@ -1644,7 +1970,7 @@ dcopf_status dcopf_dual_primal(dcopf_dual_t h, dcopf_primal *out, double *p_avg)
   primal_cols_kernel<<<gc, 256, 0, s>>>(h->psum, h->sc, h->seg, h->c, h->q, h->n_cols, h->pbar,
                                         h->xbar, h->ppart);
   primal_lines_kernel<<<gl, 256, 0, s>>>(h->P64T, h->ldl, h->n_cols, h->n_lines, h->xbar, h->fd,
-                                         h->fmax, h->ppart + 2 * kPrimalBlocks);
+                                         h->fmax, h->ppart + 2 * kPrimalBlocks, nullptr);
   primal_final_kernel<<<1, 64, 0, s>>>(h->ppart, gc, h->ppart + 2 * kPrimalBlocks, gl, h->sc,
                                        h->primal);
   DCOPF_HIP_TRY(hipGetLastError());
@@ -1664,6 +1990,103 @@ dcopf_status dcopf_dual_primal(dcopf_dual_t h, dcopf_primal *out, double *p_avg)
   out->n_overloaded = r.n_overloaded;
   if (p_avg)  // unit t of the column order is generator gperm_h[t]
     for (int t = 0; t < h->n_gen; ++t) p_avg[h->gperm_h[t]] = pb[t];
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_dual_repair(dcopf_dual_t h, const double *p_in, int32_t max_rounds,
+                               dcopf_repair *out, double *p_out) {
+  if (!h || !out || max_rounds < 0) return set_error("bad arguments"), DCOPF_E_INVALID;
+  const int ng = h->n_gen, nl = h->n_lines, nc = h->n_cols;
+  if (p_in && !finite_all(p_in, (size_t)ng)) return set_error("p_in is not finite"), DCOPF_E_INVALID;
+  auto &R = h->rep;
+  if (!R.ready) {
+    dcopf_status st = DCOPF_OK;
+    R.pin = dalloc<double>(ng, &st);
+    R.p = dalloc<double>(ng, &st);
+    R.p0c = dalloc<double>(ng, &st);
+    R.x = dalloc<double>(nc, &st);
+    R.W = dalloc<double>(nc, &st);
+    R.F = dalloc<double>(nl, &st);
+    R.t = dalloc<double>(kRepRows, &st);
+    R.y = dalloc<double>(kRepRows, &st);
+    R.G = dalloc<double>((size_t)kRepRows * kRepRows, &st);
+    R.A = dalloc<double>((size_t)kRepRows * h->ldc, &st);
+    R.pc = dalloc<double>(2 * (size_t)kPrimalBlocks, &st);
+    R.pl = dalloc<double>(3 * (size_t)kPrimalBlocks, &st);
+    R.pos = dalloc<int>(nl, &st);
+    R.rows = dalloc<int>(kRepRows, &st);
+    R.sgn = dalloc<int>(kRepRows, &st);
+    R.st = dalloc<RepairState>(1, &st);
+    R.out = dalloc<DevRepair>(1, &st);
+    if (st != DCOPF_OK) return set_error("device allocation failed"), st;
+    R.ready = true;
+  }
+  hipStream_t s = h->stream;
+  const int gc = std::max(1, std::min(kPrimalBlocks, (nc + 255) / 256));
+  const int gl = std::max(1, std::min(kPrimalBlocks, (nl + 255) / 256));
+  const double *src = R.pin;
+  if (p_in) {
+    std::vector<double> pc(ng);  // unit t of the column order is generator gperm_h[t]
+    for (int t = 0; t < ng; ++t) pc[t] = p_in[h->gperm_h[t]];
+    DCOPF_HIP_TRY(hipMemcpyAsync(R.pin, pc.data(), (size_t)ng * 8, hipMemcpyHostToDevice, s));
+    DCOPF_HIP_TRY(hipStreamSynchronize(s));
+  } else {
+    DevScalars sch;
+    dcopf_status st = read_scalars(h, &sch);
+    if (st != DCOPF_OK) return st;
+    if (sch.avg_count <= 0) return set_error("no iterations averaged"), DCOPF_E_STATE;
+    primal_cols_kernel<<<gc, 256, 0, s>>>(h->psum, h->sc, h->seg, h->c, h->q, nc, h->pbar,
+                                          h->xbar, h->ppart);
+    src = h->pbar;
+  }
+  const int gi = std::min(1024, (std::max(ng, nl) + 255) / 256);
+  repair_init_kernel<<<gi, 256, 0, s>>>(src, h->pmin, h->pmax, ng, nl, R.p, R.p0c, R.pos, R.st);
+  const int ldc = h->ldc;
+  int rounds = 0;
+  RepairState hs{};
+  for (;;) {
+    repair_cols_kernel<<<gc, 256, 0, s>>>(R.p, h->seg, h->c, h->q, h->pmin, h->pmax, nc, R.x,
+                                          R.W, R.pc);
+    primal_lines_kernel<<<gl, 256, 0, s>>>(h->P64T, h->ldl, nc, nl, R.x, h->fd, h->fmax, R.pl,
+                                           R.F);
+    repair_active_kernel<<<1, 256, 0, s>>>(R.F, h->fmax, nl, R.pc, gc, h->sc, R.pos, R.rows,
+                                           R.sgn, R.t, R.st);
+    DCOPF_HIP_TRY(hipGetLastError());
+    DCOPF_HIP_TRY(hipMemcpyAsync(&hs, R.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    DCOPF_HIP_TRY(hipStreamSynchronize(s));
+    if (hs.done || hs.fail || hs.overflow || rounds >= max_rounds) break;
+    if (hs.m > hs.m_old) {
+      dim3 gg((unsigned)((ldc + 255) / 256), (unsigned)(hs.m - hs.m_old));
+      repair_gather_kernel<<<gg, 256, 0, s>>>(h->P64T, h->ldl, nc, ldc, R.rows, hs.m_old, R.A);
+    }
+    const long long pairs = (long long)(hs.m + 1) * (hs.m + 2) / 2;
+    repair_gram_kernel<<<(unsigned)((pairs + 3) / 4), 256, 0, s>>>(R.A, ldc, R.W, nc, hs.m, R.G);
+    repair_solve_kernel<<<1, 1024, 0, s>>>(R.G, hs.m, R.t, R.y, R.st);
+    repair_step_kernel<<<(nc + 255) / 256, 256, 0, s>>>(R.A, ldc, R.y, hs.m, h->seg, h->pmin,
+                                                        h->pmax, nc, R.st, R.p);
+    ++rounds;
+  }
+  if (hs.fail) --rounds;  // the failed solve moved nothing
+  repair_final_kernel<<<1, 256, 0, s>>>(R.pc, gc, R.pl, gl, h->sc, R.p, R.p0c, ng, R.out);
+  DCOPF_HIP_TRY(hipGetLastError());
+  DevRepair r;
+  DCOPF_HIP_TRY(hipMemcpyAsync(&r, R.out, sizeof(r), hipMemcpyDeviceToHost, s));
+  std::vector<double> pb;
+  if (p_out) {
+    pb.resize(ng);
+    DCOPF_HIP_TRY(hipMemcpyAsync(pb.data(), R.p, (size_t)ng * 8, hipMemcpyDeviceToHost, s));
+  }
+  DCOPF_HIP_TRY(hipStreamSynchronize(s));
+  out->cost = r.cost;
+  out->balance = r.balance;
+  out->max_overload = r.max_overload;
+  out->max_shift = r.max_shift;
+  out->feasible = hs.done ? 1 : 0;
+  out->rounds = rounds;
+  out->n_active = hs.m;
+  out->pad = 0;
+  if (p_out)
+    for (int t = 0; t < ng; ++t) p_out[h->gperm_h[t]] = pb[t];
   return DCOPF_OK;
 }
 
