@@ -566,3 +566,22 @@ class MLP:
         check(lib.dcopf_mlp_time_train(self._h, C.c_void_p(x_ptr), C.c_void_p(t_ptr),
                                        int(batch), int(n), C.byref(ms)))
         return ms.value
+
+
+# ---------------------------------------------------------------------------
+# PTDF construction (dcopf_ptdf.h)
+# ---------------------------------------------------------------------------
+lib.dcopf_ptdf.restype = C.c_int
+lib.dcopf_ptdf.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                           C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p]
+
+
+def ptdf(n_bus: int, fbus, tbus, b, slack: int, H_ptr: int, stream=None):
+    """H_a of the network into the device buffer at H_ptr (n_line * n_bus
+    doubles, row-major, e.g. a torch tensor's data_ptr())."""
+    fb = np.ascontiguousarray(np.asarray(fbus, np.int32))
+    tb = np.ascontiguousarray(np.asarray(tbus, np.int32))
+    bb = _f64(b)
+    check(lib.dcopf_ptdf(int(n_bus), int(fb.size), fb.ctypes.data_as(C.POINTER(C.c_int32)),
+                         tb.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(bb), int(slack),
+                         C.c_void_p(stream or 0), C.c_void_p(H_ptr)))

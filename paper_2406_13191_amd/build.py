@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdcopf_dual.so")
-SOURCES = ["csrc/single.hip", "csrc/batch.hip", "csrc/mlp.hip"]
+SOURCES = ["csrc/single.hip", "csrc/batch.hip", "csrc/mlp.hip", "csrc/ptdf.hip"]
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # no packed FP32 instructions in generated code

@@ -1,0 +1,346 @@
+// PTDF construction (Section 2): H_a[:, kept] = Omega E_r B_r^{-1} with
+// B_r = E_r^T Omega E_r and a zero slack column, in FP64 on the matrix
+// cores.  n = n_bus - 1 reduced buses, padded to N = 64 T (identity rows).
+//
+//   1. B_r, one thread per row, from the lines incident to its bus;
+//   2. B_r = L L^T, right-looking by blocks of 64: the diagonal block is
+//      factored in LDS by one workgroup, which also forms its inverse; the
+//      panel below it is L_ik = A_ik L_kk^{-T}; the trailing lower triangle
+//      takes A_ij -= L_ik L_jk^T;
+//   3. W = L^{-1} on the identity, block row by block row: W_i = L_ii^{-1} W_i
+//      over the tiles left of the diagonal, then W_j -= L_ji W_i below;
+//   4. X = B_r^{-1} = W^T W (into the buffer that held L);
+//   5. H[l][bus] = b_l (X[f][bus] - X[t][bus]) on the kept buses.
+//
+// Every product is a 64 x 64 output tile of one workgroup of four
+// wavefronts; a wavefront holds 16 rows as four 16 x 16 accumulators of
+// v_mfma_f64_16x16x4f64.  Operands are read from global memory (L2) through
+// strides, so one routine serves the three layouts (A B^T, A B, A^T B).
+#include "common.h"
+#include "dcopf_ptdf.h"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace dcopf {
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kT = 64;  // block size
+
+__device__ __forceinline__ int reduced(int bus, int slack) {
+  return bus == slack ? -1 : (bus < slack ? bus : bus - 1);
+}
+
+// Row r of B_r (r < n) from the incidence lists; rows r >= n are identity
+// rows.  A is zero on entry.
+__global__ void assemble_kernel(const int *__restrict__ start, const int *__restrict__ adj,
+                                const int *__restrict__ fbus, const int *__restrict__ tbus,
+                                const double *__restrict__ b, int slack, int n, int N,
+                                double *__restrict__ A) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < N; r += gridDim.x * blockDim.x) {
+    double *row = A + (size_t)r * N;
+    if (r >= n) {
+      row[r] = 1.0;
+      continue;
+    }
+    const int bus = r < slack ? r : r + 1;
+    double diag = 0.0;
+    for (int e = start[bus]; e < start[bus + 1]; ++e) {
+      const int l = adj[e];
+      const int other = fbus[l] == bus ? tbus[l] : fbus[l];
+      diag += b[l];
+      const int o = reduced(other, slack);
+      if (o >= 0) row[o] -= b[l];
+    }
+    row[r] = diag;
+  }
+}
+
+// acc[t] += A(m0 + i, k) B(k, 16 t + j) over k in [k0, k1), i, j < 16, where
+// A(i, k) = Ap[i sar + k sak] (Ap at the wavefront's first row) and
+// B(k, c) = Bp[k sbk + c sbc] (Bp at the tile's first column).  Lane l
+// supplies A(l % 16, k + l / 16) and B(k + l / 16, l % 16); register j of
+// accumulator t holds row 4 j + l / 16, column 16 t + l % 16.
+__device__ __forceinline__ void mma16x64(const double *Ap, size_t sar, size_t sak,
+                                         const double *Bp, size_t sbk, size_t sbc, int k0,
+                                         int k1, f64x4 (&acc)[4]) {
+  const int lane = threadIdx.x & 63, r = lane & 15, kk = lane >> 4;
+  const double *a = Ap + (size_t)r * sar + (size_t)kk * sak;
+  const double *bb = Bp + (size_t)kk * sbk + (size_t)r * sbc;
+  for (int k = k0; k < k1; k += 4) {
+    const double av = a[(size_t)k * sak];
+    double bv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) bv[t] = bb[(size_t)k * sbk + (size_t)(16 * t) * sbc];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[t], acc[t], 0, 0, 0);
+  }
+}
+
+// out[(m0 + row) ld + col] for the wavefront's 16 rows: mode 0 store,
+// mode 1 subtract.
+__device__ __forceinline__ void store16x64(double *out, size_t ld, const f64x4 (&acc)[4],
+                                           int mode) {
+  const int lane = threadIdx.x & 63, m0 = (threadIdx.x >> 6) * 16;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double *p = out + (size_t)(m0 + 4 * j + (lane >> 4)) * ld + 16 * t + (lane & 15);
+      *p = mode == 0 ? acc[t][j] : *p - acc[t][j];
+    }
+}
+
+// Diagonal block kb: Cholesky in LDS (written back to A, zeros above the
+// diagonal), and its inverse (lower triangular) to Yd[kb].  flag = 1 on a
+// pivot that is not positive.
+__global__ __launch_bounds__(256) void potrf_kernel(double *__restrict__ A, int N, int kb,
+                                                    double *__restrict__ Yd, int *flag) {
+  __shared__ double L[kT][kT + 1];
+  __shared__ double Y[kT][kT + 1];
+  __shared__ double part[4][kT];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  double *blk = A + (size_t)kb * kT * N + (size_t)kb * kT;
+  for (int e = tid; e < kT * kT; e += 256) L[e / kT][e % kT] = blk[(size_t)(e / kT) * N + e % kT];
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < kT; ++j) {
+    if (tid == 0) {
+      const double d = L[j][j];
+      if (d > 0.0)
+        L[j][j] = sqrt(d);
+      else
+        bad = 1;
+    }
+    __syncthreads();
+    if (bad) break;
+    const double dj = L[j][j];
+    if (tid > j && tid < kT) L[tid][j] /= dj;
+    __syncthreads();
+    const int r = kT - 1 - j;
+    for (int idx = tid; idx < r * r; idx += 256) {
+      const int ii = j + 1 + idx / r, cc = j + 1 + idx % r;
+      if (cc <= ii) L[ii][cc] -= L[ii][j] * L[cc][j];
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) *flag = 1;
+    return;
+  }
+  // Y = L^{-1}: row i from the rows above it; column c by thread group
+  // (c, q), q summing every fourth k
+  const int c = tid & (kT - 1), q = tid >> 6;
+  for (int i = 0; i < kT; ++i) {
+    double s = 0.0;
+    if (c < i)
+      for (int k = c + q; k < i; k += 4) s += L[i][k] * Y[k][c];
+    part[q][c] = s;
+    __syncthreads();
+    if (q == 0) {
+      const double v = (c == i ? 1.0 : 0.0) - (part[0][c] + part[1][c] + part[2][c] + part[3][c]);
+      Y[i][c] = c <= i ? v / L[i][i] : 0.0;
+    }
+    __syncthreads();
+  }
+  double *y = Yd + (size_t)kb * kT * kT;
+  for (int e = tid; e < kT * kT; e += 256) {
+    const int i = e / kT, jj = e % kT;
+    blk[(size_t)i * N + jj] = jj <= i ? L[i][jj] : 0.0;
+    y[e] = Y[i][jj];
+  }
+}
+
+// Panel: L_ik = A_ik L_kk^{-T} for the block rows i > kb (one per workgroup).
+__global__ __launch_bounds__(256) void panel_kernel(double *__restrict__ A, int N, int kb,
+                                                    const double *__restrict__ Yd) {
+  const int i = kb + 1 + blockIdx.x, m0 = (threadIdx.x >> 6) * 16;
+  double *tile = A + (size_t)i * kT * N + (size_t)kb * kT;
+  const double *y = Yd + (size_t)kb * kT * kT;
+  f64x4 acc[4] = {};
+  // A(r, k) = tile[r N + k]; B(k, c) = Y[c][k]
+  mma16x64(tile + (size_t)m0 * N, N, 1, y, 1, kT, 0, kT, acc);
+  __syncthreads();  // every wavefront has read the tile
+  store16x64(tile, N, acc, 0);
+}
+
+// Trailing update of the lower triangle: A_ij -= L_i,kb L_j,kb^T, i >= j > kb.
+__global__ __launch_bounds__(256) void update_kernel(double *__restrict__ A, int N, int kb) {
+  const long long p = blockIdx.x;
+  int ii = (int)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+  while ((long long)(ii + 1) * (ii + 2) / 2 <= p) ++ii;
+  while ((long long)ii * (ii + 1) / 2 > p) --ii;
+  const int jj = (int)(p - (long long)ii * (ii + 1) / 2);
+  const int i = kb + 1 + ii, j = kb + 1 + jj, m0 = (threadIdx.x >> 6) * 16;
+  const double *Li = A + (size_t)i * kT * N + (size_t)kb * kT;
+  const double *Lj = A + (size_t)j * kT * N + (size_t)kb * kT;
+  f64x4 acc[4] = {};
+  mma16x64(Li + (size_t)m0 * N, N, 1, Lj, 1, N, 0, kT, acc);
+  store16x64(A + (size_t)i * kT * N + (size_t)j * kT, N, acc, 1);
+}
+
+__global__ void identity_kernel(double *__restrict__ W, int N) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < N; r += gridDim.x * blockDim.x)
+    W[(size_t)r * N + r] = 1.0;
+}
+
+// W_i,c = L_ii^{-1} W_i,c for the tiles c <= i of block row i.
+__global__ __launch_bounds__(256) void trsm_scale_kernel(double *__restrict__ W, int N, int i,
+                                                         const double *__restrict__ Yd) {
+  const int c = blockIdx.x, m0 = (threadIdx.x >> 6) * 16;
+  double *tile = W + (size_t)i * kT * N + (size_t)c * kT;
+  const double *y = Yd + (size_t)i * kT * kT;
+  f64x4 acc[4] = {};
+  // A(r, k) = Y[r][k]; B(k, c) = tile[k N + c]
+  mma16x64(y + (size_t)m0 * kT, kT, 1, tile, N, 1, 0, kT, acc);
+  __syncthreads();
+  store16x64(tile, N, acc, 0);
+}
+
+// W_j,c -= L_j,i W_i,c for j > i, c <= i.
+__global__ __launch_bounds__(256) void trsm_update_kernel(const double *__restrict__ L,
+                                                          double *__restrict__ W, int N,
+                                                          int i) {
+  const int j = i + 1 + blockIdx.x / (i + 1), c = blockIdx.x % (i + 1);
+  const int m0 = (threadIdx.x >> 6) * 16;
+  const double *Lji = L + (size_t)j * kT * N + (size_t)i * kT;
+  const double *Wic = W + (size_t)i * kT * N + (size_t)c * kT;
+  f64x4 acc[4] = {};
+  mma16x64(Lji + (size_t)m0 * N, N, 1, Wic, N, 1, 0, kT, acc);
+  store16x64(W + (size_t)j * kT * N + (size_t)c * kT, N, acc, 1);
+}
+
+// X_ab = sum over block rows k >= max(a, b) of W_ka^T W_kb.
+__global__ __launch_bounds__(256) void xprod_kernel(const double *__restrict__ W, int N, int T,
+                                                    double *__restrict__ X) {
+  const int a = blockIdx.x / T, bcol = blockIdx.x % T, m0 = (threadIdx.x >> 6) * 16;
+  const int k0 = (a > bcol ? a : bcol) * kT;
+  f64x4 acc[4] = {};
+  // A(r, k) = W[k][a 64 + r]; B(k, c) = W[k][b 64 + c]
+  mma16x64(W + (size_t)a * kT + m0, 1, N, W + (size_t)bcol * kT, N, 1, k0, N, acc);
+  store16x64(X + (size_t)a * kT * N + (size_t)bcol * kT, N, acc, 0);
+}
+
+// H[l][bus] = b_l (X[f'][bus'] - X[t'][bus']), zero at the slack.
+__global__ void gather_kernel(const double *__restrict__ X, int N, const int *__restrict__ fbus,
+                              const int *__restrict__ tbus, const double *__restrict__ b,
+                              int n_bus, int n_line, int slack, double *__restrict__ H) {
+  for (int l = blockIdx.y; l < n_line; l += gridDim.y) {
+    const int f = reduced(fbus[l], slack), t = reduced(tbus[l], slack);
+    const double bl = b[l];
+    for (int bus = blockIdx.x * blockDim.x + threadIdx.x; bus < n_bus;
+         bus += gridDim.x * blockDim.x) {
+      const int c = reduced(bus, slack);
+      double v = 0.0;
+      if (c >= 0) {
+        const double xf = f >= 0 ? X[(size_t)f * N + c] : 0.0;
+        const double xt = t >= 0 ? X[(size_t)t * N + c] : 0.0;
+        v = bl * (xf - xt);
+      }
+      H[(size_t)l * n_bus + bus] = v;
+    }
+  }
+}
+
+}  // namespace
+}  // namespace dcopf
+
+using namespace dcopf;
+
+extern "C" dcopf_status dcopf_ptdf(int32_t n_bus, int32_t n_line, const int32_t *fbus,
+                                   const int32_t *tbus, const double *b, int32_t slack,
+                                   void *hip_stream, double *H) {
+  set_error("");
+  if (!fbus || !tbus || !b || !H) return set_error("ptdf: null pointer"), DCOPF_E_INVALID;
+  if (n_bus < 2 || n_line < 1) return set_error("ptdf: need n_bus >= 2, n_line >= 1"), DCOPF_E_INVALID;
+  if (slack < 0 || slack >= n_bus) return set_error("ptdf: slack out of range"), DCOPF_E_INVALID;
+  for (int l = 0; l < n_line; ++l) {
+    if (fbus[l] < 0 || fbus[l] >= n_bus || tbus[l] < 0 || tbus[l] >= n_bus)
+      return set_error("ptdf: bus index out of range"), DCOPF_E_INVALID;
+    if (fbus[l] == tbus[l]) return set_error("ptdf: a line joins a bus to itself"), DCOPF_E_INVALID;
+    if (!(std::isfinite(b[l]) && b[l] > 0.0))
+      return set_error("ptdf: susceptances must be finite and positive"), DCOPF_E_INVALID;
+  }
+  const int n = n_bus - 1, T = (n + kT - 1) / kT, N = T * kT;
+  // incidence lists per bus, in line order
+  std::vector<int> start(n_bus + 1, 0), adj(2 * (size_t)n_line);
+  for (int l = 0; l < n_line; ++l) {
+    ++start[fbus[l] + 1];
+    ++start[tbus[l] + 1];
+  }
+  for (int i = 0; i < n_bus; ++i) start[i + 1] += start[i];
+  {
+    std::vector<int> fill(start.begin(), start.end() - 1);
+    for (int l = 0; l < n_line; ++l) {
+      adj[fill[fbus[l]]++] = l;
+      adj[fill[tbus[l]]++] = l;
+    }
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t NN = (size_t)N * N;
+  double *A = nullptr, *W = nullptr, *Yd = nullptr, *db = nullptr;
+  int *dstart = nullptr, *dadj = nullptr, *df = nullptr, *dt = nullptr, *flag = nullptr;
+  dcopf_status st = DCOPF_OK;
+  auto alloc = [&](void **p, size_t bytes) {
+    if (st == DCOPF_OK && hipMalloc(p, bytes) != hipSuccess) st = DCOPF_E_NOMEM;
+  };
+  alloc((void **)&A, NN * 8);
+  alloc((void **)&W, NN * 8);
+  alloc((void **)&Yd, (size_t)T * kT * kT * 8);
+  alloc((void **)&db, (size_t)n_line * 8);
+  alloc((void **)&dstart, (size_t)(n_bus + 1) * 4);
+  alloc((void **)&dadj, 2 * (size_t)n_line * 4);
+  alloc((void **)&df, (size_t)n_line * 4);
+  alloc((void **)&dt, (size_t)n_line * 4);
+  alloc((void **)&flag, 4);
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t r) {
+    if (e == hipSuccess && r != hipSuccess) e = r;
+  };
+  if (st == DCOPF_OK) {
+    chk(hipMemcpyAsync(db, b, (size_t)n_line * 8, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(dstart, start.data(), (size_t)(n_bus + 1) * 4, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(dadj, adj.data(), 2 * (size_t)n_line * 4, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(df, fbus, (size_t)n_line * 4, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(dt, tbus, (size_t)n_line * 4, hipMemcpyHostToDevice, s));
+    chk(hipMemsetAsync(flag, 0, 4, s));
+    chk(hipMemsetAsync(A, 0, NN * 8, s));
+    const int g = std::min(1024, (N + 255) / 256);
+    assemble_kernel<<<g, 256, 0, s>>>(dstart, dadj, df, dt, db, slack, n, N, A);
+    for (int kb = 0; kb < T; ++kb) {
+      potrf_kernel<<<1, 256, 0, s>>>(A, N, kb, Yd, flag);
+      const int R = T - kb - 1;
+      if (R > 0) {
+        panel_kernel<<<R, 256, 0, s>>>(A, N, kb, Yd);
+        update_kernel<<<(unsigned)((long long)R * (R + 1) / 2), 256, 0, s>>>(A, N, kb);
+      }
+    }
+    chk(hipMemsetAsync(W, 0, NN * 8, s));
+    identity_kernel<<<g, 256, 0, s>>>(W, N);
+    for (int i = 0; i < T; ++i) {
+      trsm_scale_kernel<<<i + 1, 256, 0, s>>>(W, N, i, Yd);
+      if (i + 1 < T)
+        trsm_update_kernel<<<(unsigned)((long long)(T - i - 1) * (i + 1)), 256, 0, s>>>(A, W, N,
+                                                                                         i);
+    }
+    xprod_kernel<<<(unsigned)((long long)T * T), 256, 0, s>>>(W, N, T, A);
+    dim3 gg((unsigned)std::min(64, (n_bus + 255) / 256), (unsigned)std::min(n_line, 32768));
+    gather_kernel<<<gg, 256, 0, s>>>(A, N, df, dt, db, n_bus, n_line, slack, H);
+    chk(hipGetLastError());
+    chk(hipStreamSynchronize(s));
+  }
+  int hflag = 0;
+  if (st == DCOPF_OK && e == hipSuccess) chk(hipMemcpy(&hflag, flag, 4, hipMemcpyDeviceToHost));
+  void *ptrs[] = {A, W, Yd, db, dstart, dadj, df, dt, flag};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (st != DCOPF_OK) return set_error("ptdf: device allocation failed"), st;
+  if (e != hipSuccess) return set_error(std::string("ptdf: ") + hipGetErrorString(e)), DCOPF_E_HIP;
+  if (hflag) return set_error("ptdf: the network is not connected"), DCOPF_E_INVALID;
+  return DCOPF_OK;
+}

@@ -38,7 +38,7 @@ from scipy.spatial import Delaunay
 
 __all__ = [
     "Network", "Problem", "NET_SPECS", "make_network", "make_problem",
-    "make_scenarios", "ptdf", "config_problem", "STEP_RULES",
+    "make_scenarios", "make_topology", "ptdf", "config_problem", "STEP_RULES",
 ]
 
 
@@ -441,14 +441,30 @@ def make_network(name: str, seed: int):
     return net, prob
 
 
+def _topology(spec, rng) -> Network:
+    """The network of a configuration: the first draws of its generator."""
+    nb = spec["n_bus"]
+    if spec["recipe"] == "tiny":
+        fbus, tbus = _tiny_tree_topology(rng, nb, spec["n_line"] - (nb - 1))
+        b = rng.uniform(5.0, 20.0, fbus.size)
+    else:
+        fbus, tbus = _geometric_topology(rng, nb, spec["n_line"])
+        b = rng.lognormal(2.5, 0.5, fbus.size)
+    return Network(nb, fbus, tbus, b, 0)
+
+
+def make_topology(name: str, seed: int) -> Network:
+    """Only the network (buses, lines, susceptances, slack) of
+    ``make_network(name, seed)``, without its PTDF or dispatch data."""
+    return _topology(NET_SPECS[name], np.random.Generator(np.random.PCG64(seed)))
+
+
 def _make_network(name: str, seed: int):
     spec = NET_SPECS[name]
     rng = np.random.Generator(np.random.PCG64(seed))
     nb, ng = spec["n_bus"], spec["n_gen"]
+    net = _topology(spec, rng)
     if spec["recipe"] == "tiny":
-        fbus, tbus = _tiny_tree_topology(rng, nb, spec["n_line"] - (nb - 1))
-        b = rng.uniform(5.0, 20.0, fbus.size)
-        net = Network(nb, fbus, tbus, b, 0)
         gen_bus = rng.choice(nb, ng, replace=False).astype(np.int32)
         c = rng.uniform(*spec["c"], ng)
         q = np.zeros(ng)
@@ -457,9 +473,6 @@ def _make_network(name: str, seed: int):
         load_bus = rng.choice(nb, 20, replace=False)
         loads = rng.uniform(0.0, 60.0, 20)
     else:
-        fbus, tbus = _geometric_topology(rng, nb, spec["n_line"])
-        b = rng.lognormal(2.5, 0.5, fbus.size)
-        net = Network(nb, fbus, tbus, b, 0)
         gen_bus = rng.integers(0, nb, ng).astype(np.int32)
         c = rng.uniform(*spec["c"], ng)
         q = rng.uniform(*spec["q"], ng) if spec["qp"] else np.zeros(ng)
@@ -474,7 +487,7 @@ def _make_network(name: str, seed: int):
     net._H = H
     p0 = _unconstrained_dispatch(c, q, p_min, p_max, d.sum())
     F0 = np.abs(_flows(H, gen_bus, p0, d))
-    nl = fbus.size
+    nl = net.n_line
     if spec["recipe"] == "tiny":
         cand = np.nonzero(F0 >= np.median(F0))[0]
         target = rng.choice(cand, spec["n_target"], replace=False)
