@@ -362,11 +362,11 @@ def bench_warmstart(args, stream):
 def ptdf_tiles(n):
     """64 x 64 x 64 tile products the PTDF build issues for n reduced buses:
     Cholesky panels and trailing updates, the forward substitution on the
-    identity, and the full product W^T W."""
+    identity, and the lower block triangle of W^T W."""
     T = -(-n // 64)
     chol = sum((T - k - 1) + (T - k - 1) * (T - k) // 2 for k in range(T))
     trsm = sum((i + 1) + (T - i - 1) * (i + 1) for i in range(T))
-    xprod = sum(T - max(a, b) for a in range(T) for b in range(T))
+    xprod = sum((a + 1) * (T - a) for a in range(T))
     return chol + trsm + xprod
 
 

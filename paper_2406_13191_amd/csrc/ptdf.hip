@@ -4,18 +4,21 @@
 //
 //   1. B_r, one thread per row, from the lines incident to its bus;
 //   2. B_r = L L^T, right-looking by blocks of 64: the diagonal block is
-//      factored in LDS by one workgroup, which also forms its inverse; the
+//      factored by one wavefront, which also forms its inverse; the
 //      panel below it is L_ik = A_ik L_kk^{-T}; the trailing lower triangle
 //      takes A_ij -= L_ik L_jk^T;
 //   3. W = L^{-1} on the identity, block row by block row: W_i = L_ii^{-1} W_i
 //      over the tiles left of the diagonal, then W_j -= L_ji W_i below;
-//   4. X = B_r^{-1} = W^T W (into the buffer that held L);
+//   4. X = B_r^{-1} = W^T W (into the buffer that held L), lower block
+//      triangle, then mirrored;
 //   5. H[l][bus] = b_l (X[f][bus] - X[t][bus]) on the kept buses.
 //
 // Every product is a 64 x 64 output tile of one workgroup of four
 // wavefronts; a wavefront holds 16 rows as four 16 x 16 accumulators of
 // v_mfma_f64_16x16x4f64.  Operands are read from global memory (L2) through
-// strides, so one routine serves the three layouts (A B^T, A B, A^T B).
+// strides, so one routine serves the three layouts (A B^T, A B, A^T B); the
+// products with K = 64 issue all their loads before the first matrix
+// instruction.
 #include "common.h"
 #include "dcopf_ptdf.h"
 
@@ -63,13 +66,33 @@ __global__ void assemble_kernel(const int *__restrict__ start, const int *__rest
 // A(i, k) = Ap[i sar + k sak] (Ap at the wavefront's first row) and
 // B(k, c) = Bp[k sbk + c sbc] (Bp at the tile's first column).  Lane l
 // supplies A(l % 16, k + l / 16) and B(k + l / 16, l % 16); register j of
-// accumulator t holds row 4 j + l / 16, column 16 t + l % 16.
+// accumulator t holds row 4 j + l / 16, column 16 t + l % 16.  KFIX > 0
+// fixes k1 - k0 = KFIX at compile time, so every load of the product can be
+// issued before the first matrix instruction.
+template <int KFIX>
 __device__ __forceinline__ void mma16x64(const double *Ap, size_t sar, size_t sak,
                                          const double *Bp, size_t sbk, size_t sbc, int k0,
                                          int k1, f64x4 (&acc)[4]) {
   const int lane = threadIdx.x & 63, r = lane & 15, kk = lane >> 4;
   const double *a = Ap + (size_t)r * sar + (size_t)kk * sak;
   const double *bb = Bp + (size_t)kk * sbk + (size_t)r * sbc;
+  if (KFIX > 0) {
+    constexpr int Q = KFIX > 0 ? KFIX / 4 : 1;
+    double av[Q], bv[Q][4];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const size_t k = (size_t)(k0 + 4 * q);
+      av[q] = a[k * sak];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) bv[q][t] = bb[k * sbk + (size_t)(16 * t) * sbc];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q][t], acc[t], 0, 0, 0);
+    return;
+  }
   for (int k = k0; k < k1; k += 4) {
     const double av = a[(size_t)k * sak];
     double bv[4];
@@ -95,65 +118,67 @@ __device__ __forceinline__ void store16x64(double *out, size_t ld, const f64x4 (
     }
 }
 
-// Diagonal block kb: Cholesky in LDS (written back to A, zeros above the
-// diagonal), and its inverse (lower triangular) to Yd[kb].  flag = 1 on a
-// pivot that is not positive.
-__global__ __launch_bounds__(256) void potrf_kernel(double *__restrict__ A, int N, int kb,
-                                                    double *__restrict__ Yd, int *flag) {
-  __shared__ double L[kT][kT + 1];
-  __shared__ double Y[kT][kT + 1];
-  __shared__ double part[4][kT];
-  __shared__ int bad;
-  const int tid = threadIdx.x;
+// Diagonal block kb, one wavefront: lane i holds row i of the block in
+// registers (both loops unrolled, so every index is a constant).  Step j
+// takes the pivot from lane j through LDS, scales column j and updates the
+// rows below with column j, broadcast through LDS.  L goes back to A (zeros
+// above the diagonal) and to LDS; lane c then forms column c of Y = L^{-1}
+// by forward substitution with the rows of L read from LDS, and Y goes to
+// Yd[kb].  flag = 1 on a pivot that is not positive.
+__global__ __launch_bounds__(64) void potrf_kernel(double *__restrict__ A, int N, int kb,
+                                                   double *__restrict__ Yd, int *flag) {
+  __shared__ double Ls[kT][kT + 1];
+  __shared__ double colj[kT];
+  __shared__ double piv;
+  const int i = threadIdx.x;
   double *blk = A + (size_t)kb * kT * N + (size_t)kb * kT;
-  for (int e = tid; e < kT * kT; e += 256) L[e / kT][e % kT] = blk[(size_t)(e / kT) * N + e % kT];
-  if (tid == 0) bad = 0;
+  for (int r = 0; r < kT; ++r) Ls[r][i] = blk[(size_t)r * N + i];  // rows, coalesced
   __syncthreads();
+  double row[kT];
+#pragma unroll
+  for (int c = 0; c < kT; ++c) row[c] = Ls[i][c];
+  bool bad = false;
+#pragma unroll
   for (int j = 0; j < kT; ++j) {
-    if (tid == 0) {
-      const double d = L[j][j];
-      if (d > 0.0)
-        L[j][j] = sqrt(d);
-      else
-        bad = 1;
+    if (i == j) piv = row[j];
+    __syncthreads();
+    const double d = piv;
+    if (!(d > 0.0)) {
+      bad = true;
+      break;
     }
+    const double sd = sqrt(d);
+    const double lij = i > j ? row[j] / sd : (i == j ? sd : 0.0);
+    row[j] = lij;
+    colj[i] = lij;
     __syncthreads();
-    if (bad) break;
-    const double dj = L[j][j];
-    if (tid > j && tid < kT) L[tid][j] /= dj;
-    __syncthreads();
-    const int r = kT - 1 - j;
-    for (int idx = tid; idx < r * r; idx += 256) {
-      const int ii = j + 1 + idx / r, cc = j + 1 + idx % r;
-      if (cc <= ii) L[ii][cc] -= L[ii][j] * L[cc][j];
+#pragma unroll
+    for (int c = j + 1; c < kT; ++c) {  // rows below j, columns up to the diagonal
+      const double f = i >= c ? lij : 0.0;
+      row[c] = fma(-f, colj[c], row[c]);
     }
     __syncthreads();
   }
   if (bad) {
-    if (tid == 0) *flag = 1;
+    if (i == 0) *flag = 1;
     return;
   }
-  // Y = L^{-1}: row i from the rows above it; column c by thread group
-  // (c, q), q summing every fourth k
-  const int c = tid & (kT - 1), q = tid >> 6;
-  for (int i = 0; i < kT; ++i) {
-    double s = 0.0;
-    if (c < i)
-      for (int k = c + q; k < i; k += 4) s += L[i][k] * Y[k][c];
-    part[q][c] = s;
-    __syncthreads();
-    if (q == 0) {
-      const double v = (c == i ? 1.0 : 0.0) - (part[0][c] + part[1][c] + part[2][c] + part[3][c]);
-      Y[i][c] = c <= i ? v / L[i][i] : 0.0;
-    }
-    __syncthreads();
+#pragma unroll
+  for (int c = 0; c < kT; ++c) Ls[i][c] = c <= i ? row[c] : 0.0;
+  __syncthreads();
+  for (int r = 0; r < kT; ++r) blk[(size_t)r * N + i] = Ls[r][i];
+  // column c = i of Y: y[k] = (delta_kc - sum_{m < k} L[k][m] y[m]) / L[k][k]
+  double y[kT];
+#pragma unroll
+  for (int k = 0; k < kT; ++k) {
+    double s = k == i ? 1.0 : 0.0;
+#pragma unroll
+    for (int m = 0; m < k; ++m) s -= Ls[k][m] * y[m];
+    y[k] = k >= i ? s / Ls[k][k] : 0.0;
   }
-  double *y = Yd + (size_t)kb * kT * kT;
-  for (int e = tid; e < kT * kT; e += 256) {
-    const int i = e / kT, jj = e % kT;
-    blk[(size_t)i * N + jj] = jj <= i ? L[i][jj] : 0.0;
-    y[e] = Y[i][jj];
-  }
+  double *yo = Yd + (size_t)kb * kT * kT;
+#pragma unroll
+  for (int k = 0; k < kT; ++k) yo[(size_t)k * kT + i] = y[k];
 }
 
 // Panel: L_ik = A_ik L_kk^{-T} for the block rows i > kb (one per workgroup).
@@ -164,7 +189,7 @@ __global__ __launch_bounds__(256) void panel_kernel(double *__restrict__ A, int 
   const double *y = Yd + (size_t)kb * kT * kT;
   f64x4 acc[4] = {};
   // A(r, k) = tile[r N + k]; B(k, c) = Y[c][k]
-  mma16x64(tile + (size_t)m0 * N, N, 1, y, 1, kT, 0, kT, acc);
+  mma16x64<kT>(tile + (size_t)m0 * N, N, 1, y, 1, kT, 0, kT, acc);
   __syncthreads();  // every wavefront has read the tile
   store16x64(tile, N, acc, 0);
 }
@@ -180,7 +205,7 @@ __global__ __launch_bounds__(256) void update_kernel(double *__restrict__ A, int
   const double *Li = A + (size_t)i * kT * N + (size_t)kb * kT;
   const double *Lj = A + (size_t)j * kT * N + (size_t)kb * kT;
   f64x4 acc[4] = {};
-  mma16x64(Li + (size_t)m0 * N, N, 1, Lj, 1, N, 0, kT, acc);
+  mma16x64<kT>(Li + (size_t)m0 * N, N, 1, Lj, 1, N, 0, kT, acc);
   store16x64(A + (size_t)i * kT * N + (size_t)j * kT, N, acc, 1);
 }
 
@@ -197,8 +222,8 @@ __global__ __launch_bounds__(256) void trsm_scale_kernel(double *__restrict__ W,
   const double *y = Yd + (size_t)i * kT * kT;
   f64x4 acc[4] = {};
   // A(r, k) = Y[r][k]; B(k, c) = tile[k N + c]
-  mma16x64(y + (size_t)m0 * kT, kT, 1, tile, N, 1, 0, kT, acc);
-  __syncthreads();
+  mma16x64<kT>(y + (size_t)m0 * kT, kT, 1, tile, N, 1, 0, kT, acc);
+  __syncthreads();  // every wavefront has read the tile
   store16x64(tile, N, acc, 0);
 }
 
@@ -211,19 +236,36 @@ __global__ __launch_bounds__(256) void trsm_update_kernel(const double *__restri
   const double *Lji = L + (size_t)j * kT * N + (size_t)i * kT;
   const double *Wic = W + (size_t)i * kT * N + (size_t)c * kT;
   f64x4 acc[4] = {};
-  mma16x64(Lji + (size_t)m0 * N, N, 1, Wic, N, 1, 0, kT, acc);
+  mma16x64<kT>(Lji + (size_t)m0 * N, N, 1, Wic, N, 1, 0, kT, acc);
   store16x64(W + (size_t)j * kT * N + (size_t)c * kT, N, acc, 1);
 }
 
-// X_ab = sum over block rows k >= max(a, b) of W_ka^T W_kb.
-__global__ __launch_bounds__(256) void xprod_kernel(const double *__restrict__ W, int N, int T,
+// X_ab = sum over block rows k >= a of W_ka^T W_kb for the lower block
+// triangle a >= b (X is symmetric).
+__global__ __launch_bounds__(256) void xprod_kernel(const double *__restrict__ W, int N,
                                                     double *__restrict__ X) {
-  const int a = blockIdx.x / T, bcol = blockIdx.x % T, m0 = (threadIdx.x >> 6) * 16;
-  const int k0 = (a > bcol ? a : bcol) * kT;
+  const long long p = blockIdx.x;
+  int a = (int)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+  while ((long long)(a + 1) * (a + 2) / 2 <= p) ++a;
+  while ((long long)a * (a + 1) / 2 > p) --a;
+  const int bcol = (int)(p - (long long)a * (a + 1) / 2), m0 = (threadIdx.x >> 6) * 16;
+  const int k0 = a * kT;
   f64x4 acc[4] = {};
   // A(r, k) = W[k][a 64 + r]; B(k, c) = W[k][b 64 + c]
-  mma16x64(W + (size_t)a * kT + m0, 1, N, W + (size_t)bcol * kT, N, 1, k0, N, acc);
+  mma16x64<0>(W + (size_t)a * kT + m0, 1, N, W + (size_t)bcol * kT, N, 1, k0, N, acc);
   store16x64(X + (size_t)a * kT * N + (size_t)bcol * kT, N, acc, 0);
+}
+
+// Upper block triangle of X from the lower one, through a 32 x 32 LDS tile:
+// X[r][c] = X[c][r] for the blocks a < b.
+__global__ __launch_bounds__(256) void mirror_kernel(double *__restrict__ X, int N) {
+  __shared__ double t[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;  // source tile rows by.., cols bx..
+  if ((by / kT) <= (bx / kT)) return;  // source must lie in a strictly lower block
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) t[r][tx] = X[(size_t)(by + r) * N + bx + tx];
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) X[(size_t)(bx + r) * N + by + tx] = t[tx][r];
 }
 
 // H[l][bus] = b_l (X[f'][bus'] - X[t'][bus']), zero at the slack.
@@ -313,7 +355,7 @@ extern "C" dcopf_status dcopf_ptdf(int32_t n_bus, int32_t n_line, const int32_t 
     const int g = std::min(1024, (N + 255) / 256);
     assemble_kernel<<<g, 256, 0, s>>>(dstart, dadj, df, dt, db, slack, n, N, A);
     for (int kb = 0; kb < T; ++kb) {
-      potrf_kernel<<<1, 256, 0, s>>>(A, N, kb, Yd, flag);
+      potrf_kernel<<<1, 64, 0, s>>>(A, N, kb, Yd, flag);
       const int R = T - kb - 1;
       if (R > 0) {
         panel_kernel<<<R, 256, 0, s>>>(A, N, kb, Yd);
@@ -328,7 +370,8 @@ extern "C" dcopf_status dcopf_ptdf(int32_t n_bus, int32_t n_line, const int32_t 
         trsm_update_kernel<<<(unsigned)((long long)(T - i - 1) * (i + 1)), 256, 0, s>>>(A, W, N,
                                                                                          i);
     }
-    xprod_kernel<<<(unsigned)((long long)T * T), 256, 0, s>>>(W, N, T, A);
+    xprod_kernel<<<(unsigned)((long long)T * (T + 1) / 2), 256, 0, s>>>(W, N, A);
+    mirror_kernel<<<dim3((unsigned)(N / 32), (unsigned)(N / 32)), 256, 0, s>>>(A, N);
     dim3 gg((unsigned)std::min(64, (n_bus + 255) / 256), (unsigned)std::min(n_line, 32768));
     gather_kernel<<<gg, 256, 0, s>>>(A, N, df, dt, db, n_bus, n_line, slack, H);
     chk(hipGetLastError());
