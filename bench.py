@@ -413,6 +413,39 @@ def bench_ptdf(args, stream):
     return rows
 
 
+def bench_rules(args, stream):
+    """Step rules on the 2000-bus LP (FP32 products, exact FP64 bound every
+    100 iterations): iterations and wall time to an exact bound within 0.1 %
+    of the HiGHS optimum, for each rule over a small grid of step sizes."""
+    from oracle import ref
+    from paper_2406_13191_amd import _abi, synth
+    net, p = synth.make_network("bus2000", 2000)
+    opt = ref.opt_btheta(net, p)["opt"]
+    grid = [("gdm", dict(rho=0.99), [1e-4, 3e-4, 1e-3]),
+            ("gdm+decay", dict(rho=0.99, decay=1e-3), [3e-4, 1e-3, 3e-3]),
+            ("adam", dict(beta1=0.9, beta2=0.999, eps=1e-8), [0.1, 0.3, 1.0, 3.0, 10.0]),
+            ("adagrad", dict(eps=1e-8), [3.0, 10.0, 30.0, 100.0, 300.0])]
+    out = []
+    for name, extra, alphas in grid:
+        for a in alphas:
+            kw = dict(rule=name.split("+")[0], alpha=a, precision="fp32", graph_iters=100, **extra)
+            with _abi.DualSolver(p, stream=stream.cuda_stream, **kw) as s:
+                t0 = time.perf_counter()
+                res = s.solve(opt=opt, gap_tol=1e-3, max_iters=args.max_iters, check_every=100)
+                dt = time.perf_counter() - t0
+            hit = res["status"] == 1
+            out.append(dict(rule=name, alpha=a, **{k: v for k, v in extra.items()},
+                            reached=hit, iterations=int(res["iter_of_bound"]) if hit else None,
+                            seconds=round(dt, 4), gap=res["gap"]))
+            print(f"[bench] {name} alpha={a}: {'%d iterations' % res['iter_of_bound'] if hit else 'not reached'}"
+                  f" ({dt*1e3:.1f} ms)", file=sys.stderr, flush=True)
+    best = {}
+    for r in out:
+        if r["reached"] and (r["rule"] not in best or r["iterations"] < best[r["rule"]]["iterations"]):
+            best[r["rule"]] = r
+    return out, best
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -457,6 +490,24 @@ def main():
             "config": {"workload": f"warm start on the 2000-bus network: MLP 2000-1024-1024-6401 "
                                    f"trained on {r['n_train']} cold-solve duals, evaluated on "
                                    f"{r['n_eval']} held-out scenarios", **r},
+            "roofline": None, "cpu_baseline": None,
+        }
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "rules":
+        runs, best = bench_rules(args, stream)
+        g = best.get("gdm")
+        out = {
+            "metric": "iterations to an exact bound within 0.1% of the FP64 optimum, by step rule",
+            "value": min(r["iterations"] for r in best.values()) if best else None,
+            "unit": "iterations", "n_gpus": 1, "steps": args.max_iters, "warmup": 0,
+            "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "2000-bus single instance (3200 lines, 540 generators), "
+                                   "FP32 products, exact FP64 bound every 100 iterations; "
+                                   "each rule over a grid of step sizes on this instance",
+                       "best": best, "runs": runs,
+                       "gdm_frozen_rule": g},
             "roofline": None, "cpu_baseline": None,
         }
         print(json.dumps(out), flush=True)
