@@ -107,7 +107,22 @@ typedef struct {
                           Both give the same dual values.                   */
   int32_t graph_iters; /* iterations per captured HIP graph; 0 = direct
                           launches                                          */
+  int32_t qp_dual;     /* DCOPF_QP_CLOSED (0): a quadratic unit's inner
+                          minimiser is the clip of -r / 2q, the exact maximum
+                          over the paper's auxiliary s.  DCOPF_QP_ITERATED (1):
+                          the paper's QP dual as printed (Section 3.2, eq.
+                          QP_finalgamma): every unit keeps its own s, the
+                          unit is bang-bang on r + 2 q m - sqrt(q) s (m the
+                          centre of its box), and s takes the same GDM step
+                          as lambda and mu along -sqrt(q)(p* - m) - s/2.  An
+                          ablation: requires rule GDM, literal 0, decay 0;
+                          get_state, set_state and time_phases then return
+                          DCOPF_E_INVALID; the monitor gamma is the value of
+                          that dual, dcopf_dual_bound the exact (closed-form)
+                          dual at the same lambda and mu.                  */
 } dcopf_opts;
+
+enum { DCOPF_QP_CLOSED = 0, DCOPF_QP_ITERATED = 1 };
 
 typedef struct dcopf_dual_s *dcopf_dual_t;
 

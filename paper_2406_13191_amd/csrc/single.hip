@@ -171,6 +171,13 @@ __device__ __forceinline__ void stage_vec(T *dst, const T *src, int ld) {
 // Units of column j handled lane-parallel by one wavefront: lane l takes
 // units g0 + l, g0 + l + 64, ...  The data of the lane's first unit (cf, qf,
 // lof, hif; valid when g0 + lane < g1) were loaded earlier.
+// With sd (the iterated-s dual): a unit's s and its velocity in sd[0][t],
+// sd[1][t]; the unit is bang-bang on the shifted cost and s takes its GDM
+// step (alpha, rho) here, its owner lane being the only one to touch it.
+struct SDual {
+  double *s, *v;
+};
+
 __device__ __forceinline__ void column_units(double w, double lam, int g0, int g1, double cf,
                                              double qf, double lof, double hif,
                                              const double *__restrict__ c,
@@ -178,14 +185,30 @@ __device__ __forceinline__ void column_units(double w, double lam, int g0, int g
                                              const double *__restrict__ pmin,
                                              const double *__restrict__ pmax, int lane,
                                              double *xj, double *phij,
-                                             double *__restrict__ psum = nullptr) {
+                                             double *__restrict__ psum = nullptr,
+                                             SDual sd = SDual{nullptr, nullptr},
+                                             double alpha = 0.0, double rho = 0.0) {
   double xs = 0.0, ph = 0.0;
   for (int t = g0 + lane; t < g1; t += kWave) {
     const bool first = t == g0 + lane;
     const double ct = first ? cf : c[t], qt = first ? qf : q[t];
+    const double lo = first ? lof : pmin[t], hi = first ? hif : pmax[t];
     const double r = ct - lam + w;
-    const double p = inner_min(r, qt, first ? lof : pmin[t], first ? hif : pmax[t]);
-    ph += r * p + qt * p * p;
+    double p;
+    if (sd.s) {
+      // Section 3.2, eq. QP_finalgamma with s fixed: q (p - m)^2 is bounded
+      // below by -sqrt(q) s (p - m) - s^2 / 4
+      const double m = 0.5 * (lo + hi), sq = sqrt(qt), st = sd.s[t];
+      const double a = r + 2.0 * qt * m - sq * st;
+      p = inner_min(a, 0.0, lo, hi);
+      ph += a * p - qt * m * m + sq * st * m - 0.25 * st * st;
+      const double v = rho * sd.v[t] + alpha * (-sq * (p - m) - 0.5 * st);
+      sd.v[t] = v;
+      sd.s[t] = st + v;
+    } else {
+      p = inner_min(r, qt, lo, hi);
+      ph += r * p + qt * p * p;
+    }
     xs += p;
     if (psum) psum[t] += p;  // primal average (each unit has one owner lane)
   }
@@ -255,9 +278,10 @@ __global__ __launch_bounds__(256) void colpass_kernel(
     const double *__restrict__ pmin, const double *__restrict__ pmax, DevScalars *sc, int par,
     T *__restrict__ x_out, double *__restrict__ part_a, int ga, const double *__restrict__ part_b,
     int gb, StepParams prm, double *__restrict__ gam_buf, long long gam_mask,
-    double *__restrict__ psum) {
+    double *__restrict__ psum, SDual sd) {
   using V = typename Vec16<T>::type;
   __shared__ double red[3 * 4];
+  __shared__ double alpha_s;
   __shared__ double lam_s;
   __shared__ T dots[4][CB];
   __shared__ double colsum[2][4];
@@ -366,6 +390,7 @@ __global__ __launch_bounds__(256) void colpass_kernel(
     set_step(cur, prev.k + 1, prm);
     cur.pending = 1;
     lam_s = cur.lam;
+    alpha_s = cur.alpha;
     if (blockIdx.x == 0) {
       sc->slot[par] = cur;
       if (prev.pending) {
@@ -381,7 +406,7 @@ __global__ __launch_bounds__(256) void colpass_kernel(
     const double w = (double)(((dots[0][wave] + dots[1][wave]) + dots[2][wave]) + dots[3][wave]);
     double xj, phij;
     column_units(w, lam_s, g0, g1, cf, qf, lof, hif, c, q, pmin, pmax, lane, &xj, &phij,
-                 sc->avg_on ? psum : nullptr);
+                 sc->avg_on ? psum : nullptr, sd, alpha_s, prm.rho);
     if (lane == 0) x_out[jw] = (T)xj;
     xsum = xj;
     phsum = phij;
@@ -456,7 +481,7 @@ __global__ __launch_bounds__(256) void colpass1_kernel(
     const double *__restrict__ pmin, const double *__restrict__ pmax, DevScalars *sc, int par,
     T *__restrict__ x_out, double *__restrict__ part_a, int ga, const double *__restrict__ part_b,
     int gb, StepParams prm, double *__restrict__ gam_buf, long long gam_mask,
-    double *__restrict__ psum) {
+    double *__restrict__ psum, SDual sd) {
   using V = typename Vec16<T>::type;
   __shared__ T dots[4];
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -524,7 +549,7 @@ __global__ __launch_bounds__(256) void colpass1_kernel(
   const double w = (double)(((dots[0] + dots[1]) + dots[2]) + dots[3]);
   double xj, phij;
   column_units(w, cur.lam, g0, g1, cf, qf, lof, hif, c, q, pmin, pmax, lane, &xj, &phij,
-               avg ? psum : nullptr);
+               avg ? psum : nullptr, sd, cur.alpha, prm.rho);
   if (lane == 0) {
     x_out[j] = (T)xj;
     part_a[(size_t)par * 2 * ga + 2 * j] = xj;
@@ -1254,6 +1279,8 @@ struct dcopf_dual_s {
   // primal average: sum of p* per unit (column order), evaluation buffers
   double *psum = nullptr, *pbar = nullptr, *xbar = nullptr, *ppart = nullptr;
   DevPrimal *primal = nullptr;
+  // the iterated-s QP dual: s and its velocity per unit (column order)
+  double *s_unit = nullptr, *v_unit = nullptr;
   // primal repair (allocated by its first call)
   struct Repair {
     double *pin = nullptr, *p = nullptr, *p0c = nullptr, *x = nullptr, *W = nullptr,
@@ -1293,7 +1320,7 @@ void launch_colpass_cb(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, h
   (void)launch_k(colpass_kernel<T, CB, UNR>, dim3(h->grid_col), dim3(256), 0, s, e0, e1, PT,
                  h->n_cols, h->ldl, (T *)h->vbuf, h->seg, h->c, h->q, h->pmin, h->pmax, h->sc,
                  par, (T *)h->xbuf, h->part_a, h->grid_col, h->part_b, h->n_line_part, h->prm,
-                 h->gam, kGamCap - 1, h->psum);
+                 h->gam, kGamCap - 1, h->psum, SDual{h->s_unit, h->v_unit});
 }
 
 template <typename T, int UNR>
@@ -1302,7 +1329,7 @@ void launch_colpass1(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hip
   (void)launch_k(colpass1_kernel<T, UNR>, dim3(h->grid_col), dim3(256), 0, s, e0, e1, PT,
                  h->n_cols, h->ldl, (T *)h->vbuf, h->seg, h->c, h->q, h->pmin, h->pmax, h->sc,
                  par, (T *)h->xbuf, h->part_a, h->grid_col, h->part_b, h->n_line_part, h->prm,
-                 h->gam, kGamCap - 1, h->psum);
+                 h->gam, kGamCap - 1, h->psum, SDual{h->s_unit, h->v_unit});
 }
 
 // one column per workgroup and a quarter of at most 8 chunks per lane: the
@@ -1432,6 +1459,12 @@ dcopf_status validate(const dcopf_problem *p, const dcopf_opts *o) {
     return set_error("unknown panel mode"), DCOPF_E_INVALID;
   if (o->graph_iters < 0 || o->graph_iters > 4096)
     return set_error("graph_iters must be in [0, 4096]"), DCOPF_E_INVALID;
+  if (o->qp_dual != DCOPF_QP_CLOSED && o->qp_dual != DCOPF_QP_ITERATED)
+    return set_error("unknown qp_dual"), DCOPF_E_INVALID;
+  if (o->qp_dual == DCOPF_QP_ITERATED &&
+      (o->rule != DCOPF_RULE_GDM || o->literal != 0 || o->decay != 0.0))
+    return set_error("the iterated-s QP dual needs rule GDM, literal 0, decay 0"),
+           DCOPF_E_INVALID;
   double smin = 0, smax = 0, D = 0;
   for (size_t g = 0; g < ng; ++g) smin += p->p_min[g], smax += p->p_max[g];
   for (size_t b = 0; b < nb; ++b) D += p->d[b];
@@ -1449,7 +1482,7 @@ void free_handle(dcopf_dual_s *h) {
                   h->pmin, h->pmax, h->seg, h->gperm, h->mu_p, h->mu_m, h->v_p, h->v_m,
                   h->s_p, h->s_m, h->vbuf, h->xbuf, h->v64b, h->part_a, h->part_b,
                   h->part_c, h->part_d, h->counters, h->sc, h->gam, h->psum, h->pbar,
-                  h->xbar, h->ppart, h->primal};
+                  h->xbar, h->ppart, h->primal, h->s_unit, h->v_unit};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   auto &R = h->rep;
@@ -1568,6 +1601,10 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   h->counters = dalloc<unsigned>(8, &st);
   h->sc = dalloc<DevScalars>(1, &st);
   h->psum = dalloc<double>(ng, &st);
+  if (o->qp_dual == DCOPF_QP_ITERATED) {
+    h->s_unit = dalloc<double>(ng, &st);
+    h->v_unit = dalloc<double>(ng, &st);
+  }
   h->pbar = dalloc<double>(ng, &st);
   h->xbar = dalloc<double>((size_t)h->n_cols, &st);
   h->ppart = dalloc<double>(5 * (size_t)kPrimalBlocks, &st);  // column and line partials
@@ -1615,6 +1652,10 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   chk(hipMemcpyAsync(h->gperm, gperm.data(), ng * 4, hipMemcpyHostToDevice, s));
   h->gperm_h = gperm;
   for (double **sp : state) chk(hipMemsetAsync(*sp, 0, nl * 8, s));
+  if (h->s_unit) {
+    chk(hipMemsetAsync(h->s_unit, 0, (size_t)ng * 8, s));
+    chk(hipMemsetAsync(h->v_unit, 0, (size_t)ng * 8, s));
+  }
   chk(hipMemsetAsync(h->xbuf, 0, (size_t)h->ldc * esz, s));
   chk(hipMemsetAsync(h->counters, 0, 8 * sizeof(unsigned), s));
   chk(hipMemsetAsync(h->gam, 0, kGamCap * 8, s));
@@ -1843,6 +1884,7 @@ size_t dcopf_dual_state_len(dcopf_dual_t h) { return h ? 5 + 6 * (size_t)h->n_li
 
 dcopf_status dcopf_dual_get_state(dcopf_dual_t h, double *buf, size_t len) {
   if (!h || !buf) return set_error("null argument"), DCOPF_E_INVALID;
+  if (h->s_unit) return set_error("not available with the iterated-s QP dual"), DCOPF_E_INVALID;
   if (len != dcopf_dual_state_len(h)) return set_error("state length mismatch"), DCOPF_E_STATE;
   DevScalars sch;
   dcopf_status st = read_scalars(h, &sch);
@@ -1862,6 +1904,7 @@ dcopf_status dcopf_dual_get_state(dcopf_dual_t h, double *buf, size_t len) {
 
 dcopf_status dcopf_dual_set_state(dcopf_dual_t h, const double *buf, size_t len) {
   if (!h || !buf) return set_error("null argument"), DCOPF_E_INVALID;
+  if (h->s_unit) return set_error("not available with the iterated-s QP dual"), DCOPF_E_INVALID;
   if (len != dcopf_dual_state_len(h)) return set_error("state length mismatch"), DCOPF_E_STATE;
   if (!finite_all(buf, len)) return set_error("non-finite state"), DCOPF_E_INVALID;
   const size_t nl = h->n_lines;
@@ -1895,6 +1938,7 @@ dcopf_status dcopf_dual_set_state(dcopf_dual_t h, const double *buf, size_t len)
 
 dcopf_status dcopf_dual_time_phases(dcopf_dual_t h, int64_t n, double *ms_out) {
   if (!h || !ms_out || n < 1) return set_error("bad arguments"), DCOPF_E_INVALID;
+  if (h->s_unit) return set_error("not available with the iterated-s QP dual"), DCOPF_E_INVALID;
   // n real iterations (column pass, line pass alternating as in step), each
   // launch carrying dispatch-attached start/stop events; the mutable state is
   // saved first and restored afterwards, so the iterate is unchanged.
