@@ -120,6 +120,18 @@ dcopf_status dcopf_batch_average(dcopf_batch_t b, int32_t enable);
 dcopf_status dcopf_batch_primal(dcopf_batch_t b, int32_t net, dcopf_primal *out,
                                 double *p_avg);
 
+/* Repair (an extension, as dcopf_dual_repair) of every instance of network
+ * `net`: the rounds of dcopf_dual_repair, with its constants, for all
+ * instances at once (an instance stops at its own stop rule, overflow or
+ * max_rounds).  p_in: host [n_inst * n_gen] in generator order, or NULL for
+ * the current primal averages (DCOPF_E_STATE when none).  out[n_inst]
+ * (dcopf_repair of dcopf_dual.h); p_out: host [n_inst * n_gen] or NULL.
+ * Device buffers for the active rows (n_inst * 256 * (panel columns)
+ * doubles) and the Gram matrices (n_inst * 256^2 doubles) are allocated by
+ * the network's first repair and kept with the handle.  Synchronises.    */
+dcopf_status dcopf_batch_repair(dcopf_batch_t b, int32_t net, const double *p_in,
+                                int32_t max_rounds, dcopf_repair *out, double *p_out);
+
 /* Tile shapes in use for network `net`: cfg[0], cfg[1] = instances x
  * columns of one W-product workgroup tile, cfg[2] = its K split (over
  * lines), cfg[3] = instances * 1000 + lines of one F-product tile.         */

@@ -313,6 +313,8 @@ def _bind_batch():
         "dcopf_batch_set_tiles": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int32)]),
         "dcopf_batch_average": (C.c_int, [C.c_void_p, C.c_int32]),
         "dcopf_batch_primal": (C.c_int, [C.c_void_p, C.c_int32, P(Primal_C), P(C.c_double)]),
+        "dcopf_batch_repair": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double), C.c_int32,
+                                         P(Repair_C), P(C.c_double)]),
         "dcopf_batch_time_phases": (C.c_int, [C.c_void_p, C.c_int64, P(C.c_double)]),
         "dcopf_batch_destroy": (None, [C.c_void_p]),
     }
@@ -453,6 +455,21 @@ class BatchSolver:
         return dict(cost=f("cost"), balance=f("balance"), max_overload=f("max_overload"),
                     sum_overload=f("sum_overload"), iterations=int(r[0].iterations),
                     n_overloaded=f("n_overloaded"), p=p)
+
+    def repair(self, net: int, p=None, max_rounds: int = 32):
+        """Feasible dispatches near p [n_inst, n_gen] (generator order), or
+        near the current primal averages when p is None, for network `net`."""
+        n = self.networks[net]
+        ng = np.asarray(n.base.gen_bus).size
+        r = (Repair_C * n.B)()
+        out = np.zeros((n.B, ng))
+        pin = None if p is None else _f64(np.reshape(p, (n.B, ng)))
+        check(lib.dcopf_batch_repair(self._h, int(net), None if pin is None else _dptr(pin),
+                                     int(max_rounds), r, _dptr(out)))
+        f = lambda k: np.array([getattr(x, k) for x in r])
+        return dict(cost=f("cost"), balance=f("balance"), max_overload=f("max_overload"),
+                    max_shift=f("max_shift"), feasible=f("feasible").astype(bool),
+                    rounds=f("rounds"), n_active=f("n_active"), p=out)
 
     def time_phases(self, n: int):
         ms = np.zeros(3)

@@ -776,6 +776,360 @@ __global__ __launch_bounds__(256) void bprimal_inst_kernel(BNet N, const BScal *
   }
 }
 
+// ---------------------------------------------------------------------------
+// Repair of every instance's primal candidate into a feasible dispatch (not
+// in the paper): the rounds of the single-instance repair for all instances
+// of a network at once, grid rows being instances.  Per round: x and the
+// weights per column (FP64), F = X P64^T for every instance (FP64 matrix
+// cores), one workgroup per instance for the ordered append to its active
+// set and the targets, then the Gram matrices (one wavefront per entry),
+// one workgroup per instance for the Cholesky solve, and the step.  An
+// instance whose rounds have ended (stop) is left untouched.
+// ---------------------------------------------------------------------------
+constexpr int kBRepRows = 256;         // active lines + the balance row
+constexpr double kBRepMargin = 1e-6;   // MW inside each held limit
+constexpr double kBRepBalTol = 1e-9;   // of max(1, 1^T d)
+constexpr double kBRepFloor = 1e-3;    // weight floor, of a unit's range
+constexpr double kBRepRidge = 1e-12;   // of the largest Gram diagonal
+
+struct BRepState {
+  double beta;       // 1^T d - 1^T p of the evaluated iterate
+  int n_viol;        // violated line directions
+  int m_old, m;      // active lines before / after this evaluation
+  int overflow;      // more than kBRepRows - 1 lines would be active
+  int done;          // stop rule met
+  int fail;          // a Gram matrix was not positive definite
+  int rounds;        // correction steps taken
+  int stop;          // no further step for this instance
+};
+
+__device__ __forceinline__ double brep_weight(double p, double lo, double hi) {
+  return fmax(fmin(p - lo, hi - p), kBRepFloor * (hi - lo));
+}
+
+// p = p0c = clip(src); no line active; zero state.
+__global__ void brep_init_kernel(BNet N, const double *__restrict__ src, double *__restrict__ p,
+                                 double *__restrict__ p0c, int *__restrict__ pos,
+                                 BRepState *st) {
+  const int i = blockIdx.y;
+  const int n = max(N.n_g, N.n_l);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    if (e < N.n_g) {
+      const size_t k = (size_t)i * N.n_g + e;
+      const double v = fmin(fmax(src[k], N.pmin[e]), N.pmax[e]);
+      p[k] = v;
+      p0c[k] = v;
+    }
+    if (e < N.n_l) pos[(size_t)i * N.n_l + e] = -1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    BRepState s{};
+    st[i] = s;
+  }
+}
+
+// Per instance and column: x (into X64, zero beyond n_c), the column's
+// weight W, block partials of the cost and the generation.
+__global__ __launch_bounds__(256) void brep_cols_kernel(BNet N, const double *__restrict__ p,
+                                                        double *__restrict__ W,
+                                                        double *__restrict__ part) {
+  __shared__ double red[2 * 4];
+  const int i = blockIdx.y;
+  const double *pi = p + (size_t)i * N.n_g;
+  const double *ci = N.c + (size_t)i * N.n_g, *qi = N.q + (size_t)i * N.n_g;
+  double v[2] = {0.0, 0.0};
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N.ldc; j += gridDim.x * blockDim.x) {
+    double xs = 0.0, ws = 0.0;
+    if (j < N.n_c)
+      for (int u = N.seg[j]; u < N.seg[j + 1]; ++u) {
+        const double pu = pi[u];
+        v[0] += ci[u] * pu + qi[u] * pu * pu;
+        xs += pu;
+        ws += brep_weight(pu, N.pmin[u], N.pmax[u]);
+      }
+    N.X64[(size_t)i * N.ldc + j] = xs;
+    W[(size_t)i * N.ldc + j] = ws;
+    v[1] += xs;
+  }
+  block_sums<2>(v, red);
+  if (threadIdx.x == 0) {
+    part[((size_t)i * gridDim.x + blockIdx.x) * 2] = v[0];
+    part[((size_t)i * gridDim.x + blockIdx.x) * 2 + 1] = v[1];
+  }
+}
+
+// One workgroup of 256 per instance: violations of F = F64 - f_d, ordered
+// append (rows, sgn; pos[l] = row of line l or -1), targets t[0..m]
+// (t[m]: balance), the stop decision.
+__global__ __launch_bounds__(256) void brep_active_kernel(
+    BNet N, const double *__restrict__ part, int gc, int max_rounds, int *__restrict__ pos,
+    int *__restrict__ rows, int *__restrict__ sgn, double *__restrict__ t, BRepState *st) {
+  __shared__ int wave_new[4];
+  __shared__ int m_s, viol_s;
+  __shared__ double beta_s;
+  __shared__ BRepState s0;
+  const int i = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  if (tid == 0) s0 = st[i];
+  __syncthreads();
+  if (s0.stop) return;
+  if (tid == 0) {
+    double gen = 0.0;
+    for (int b = 0; b < gc; ++b) gen += part[((size_t)i * gc + b) * 2 + 1];
+    beta_s = N.D[i] - gen;
+    m_s = s0.m;
+    viol_s = 0;
+  }
+  __syncthreads();
+  int *posi = pos + (size_t)i * N.n_l;
+  int *rowsi = rows + (size_t)i * kBRepRows, *sgni = sgn + (size_t)i * kBRepRows;
+  const double *Fi = N.F64 + (size_t)i * N.nlp, *fdi = N.fd64 + (size_t)i * N.n_l;
+  const int m_old = m_s;
+  for (int base = 0; base < N.n_l; base += 256) {
+    const int l = base + tid;
+    int sigma = 0;
+    if (l < N.n_l) {
+      const double Fl = Fi[l] - fdi[l];
+      if (Fl - N.flim64[l] > 0.0)
+        sigma = 1;
+      else if (-Fl - N.flim64[l] > 0.0)
+        sigma = -1;
+    }
+    bool fresh = false;
+    if (sigma != 0) {
+      const int r = posi[l];
+      if (r >= 0)
+        sgni[r] = sigma;  // held line: keep its row, take this direction
+      else
+        fresh = true;
+    }
+    const unsigned long long mask = __ballot(fresh);
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_new[wave] = __popcll(mask);
+    const int nviol = __popcll(__ballot(sigma != 0));
+    __syncthreads();
+    int off = m_s;
+    for (int w = 0; w < wave; ++w) off += wave_new[w];
+    if (fresh) {
+      const int r = off + before;
+      if (r < kBRepRows - 1) {
+        rowsi[r] = l;
+        sgni[r] = sigma;
+        posi[l] = r;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int add = 0;
+      for (int w = 0; w < 4; ++w) add += wave_new[w];
+      m_s += add;
+    }
+    if (lane == 0) atomicAdd(&viol_s, nviol);
+    __syncthreads();
+  }
+  int m = m_s;
+  const bool over = m > kBRepRows - 1;
+  if (over) m = kBRepRows - 1;
+  double *ti = t + (size_t)i * kBRepRows;
+  for (int r = tid; r < m; r += blockDim.x) {
+    const int l = rowsi[r];
+    const double Fl = Fi[l] - fdi[l];
+    ti[r] = sgni[r] > 0 ? (-kBRepMargin - (Fl - N.flim64[l])) : (kBRepMargin + (-Fl - N.flim64[l]));
+  }
+  if (tid == 0) {
+    ti[m] = beta_s;
+    BRepState s = s0;
+    s.beta = beta_s;
+    s.n_viol = viol_s;
+    s.m_old = m_old;
+    s.m = m;
+    s.overflow = (over || s0.overflow) ? 1 : 0;
+    s.done = (viol_s == 0 && fabs(beta_s) <= kBRepBalTol * fmax(1.0, fabs(N.D[i]))) ? 1 : 0;
+    s.stop = (s.done || s.fail || s.overflow || s.rounds >= max_rounds) ? 1 : 0;
+    st[i] = s;
+  }
+}
+
+// A[i][r][c] = P[rows[i][r]][c] for the rows that joined (x blocks: column
+// chunk by new row).
+__global__ void brep_gather_kernel(BNet N, const int *__restrict__ rows, const BRepState *st,
+                                   int ccb, double *__restrict__ A) {
+  const int i = blockIdx.y;
+  const BRepState s = st[i];
+  const int r = s.m_old + (int)blockIdx.x / ccb;
+  if (s.stop || r >= s.m) return;
+  const int l = rows[(size_t)i * kBRepRows + r];
+  const int c = ((int)blockIdx.x % ccb) * blockDim.x + threadIdx.x;
+  if (c < N.ldc)
+    A[((size_t)i * kBRepRows + r) * N.ldc + c] = N.P64[(size_t)l * N.ldc + c];
+}
+
+// G[i][a][b] (a >= b < m_i + 1; row m_i is the balance row of ones): one
+// wavefront per entry.
+__global__ __launch_bounds__(256) void brep_gram_kernel(BNet N, const double *__restrict__ A,
+                                                        const double *__restrict__ W,
+                                                        const BRepState *st,
+                                                        double *__restrict__ G) {
+  const int i = blockIdx.y;
+  const BRepState s = st[i];
+  if (s.stop) return;
+  const int m = s.m, n = m + 1;
+  const long long k = (long long)blockIdx.x * 4 + threadIdx.x / kWave;
+  if (k >= (long long)n * (n + 1) / 2) return;
+  int a = (int)((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
+  while ((long long)(a + 1) * (a + 2) / 2 <= k) ++a;
+  while ((long long)a * (a + 1) / 2 > k) --a;
+  const int b = (int)(k - (long long)a * (a + 1) / 2);
+  const int lane = threadIdx.x % kWave;
+  const double *Ai = A + (size_t)i * kBRepRows * N.ldc;
+  const double *aa = Ai + (size_t)a * N.ldc, *ab = Ai + (size_t)b * N.ldc;
+  const double *Wi = W + (size_t)i * N.ldc;
+  double sum = 0.0;
+  for (int c = lane; c < N.n_c; c += kWave) {
+    const double x = a < m ? aa[c] : 1.0, y = b < m ? ab[c] : 1.0;
+    sum += Wi[c] * x * y;
+  }
+  sum = wave_sum(sum);
+  if (lane == 0) G[((size_t)i * kBRepRows + a) * kBRepRows + b] = sum;
+}
+
+// One workgroup per instance: ridge, Cholesky in place, L L^T y = t.
+__global__ __launch_bounds__(1024) void brep_solve_kernel(double *__restrict__ G,
+                                                          const double *__restrict__ t,
+                                                          double *__restrict__ y,
+                                                          BRepState *st) {
+  __shared__ double red[16];
+  __shared__ int fail_s;
+  const int i = blockIdx.x;
+  if (st[i].stop) return;
+  const int n = st[i].m + 1, tid = threadIdx.x, nt = blockDim.x;
+  double *Gi = G + (size_t)i * kBRepRows * kBRepRows;
+  const double *ti = t + (size_t)i * kBRepRows;
+  double *yi = y + (size_t)i * kBRepRows;
+  auto g = [&](int a, int b) -> double & { return Gi[(size_t)a * kBRepRows + b]; };
+  double dm = 0.0;
+  for (int a = tid; a < n; a += nt) dm = fmax(dm, g(a, a));
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) dm = fmax(dm, __shfl_xor(dm, off, kWave));
+  if (tid % kWave == 0) red[tid / kWave] = dm;
+  if (tid == 0) fail_s = 0;
+  __syncthreads();
+  dm = 0.0;
+  for (int w = 0; w < nt / kWave; ++w) dm = fmax(dm, red[w]);
+  if (!(dm > 0.0)) {
+    if (tid == 0) st[i].fail = 1;
+    return;
+  }
+  for (int a = tid; a < n; a += nt) g(a, a) += kBRepRidge * dm;
+  for (int a = tid; a < n; a += nt) yi[a] = ti[a];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      const double d = g(k, k);
+      if (d > 0.0)
+        g(k, k) = sqrt(d);
+      else
+        fail_s = 1;
+    }
+    __syncthreads();
+    if (fail_s) break;
+    const double dk = g(k, k);
+    for (int a = k + 1 + tid; a < n; a += nt) g(a, k) /= dk;
+    __syncthreads();
+    const int r = n - k - 1;
+    for (int idx = tid; idx < r * r; idx += nt) {
+      const int aa = idx / r, bb = idx % r;
+      if (bb <= aa) g(k + 1 + aa, k + 1 + bb) -= g(k + 1 + aa, k) * g(k + 1 + bb, k);
+    }
+    __syncthreads();
+  }
+  if (fail_s) {
+    if (tid == 0) st[i].fail = 1;
+    return;
+  }
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) yi[k] /= g(k, k);
+    __syncthreads();
+    const double yk = yi[k];
+    for (int a = k + 1 + tid; a < n; a += nt) yi[a] -= g(a, k) * yk;
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    if (tid == 0) yi[k] /= g(k, k);
+    __syncthreads();
+    const double yk = yi[k];
+    for (int a = tid; a < k; a += nt) yi[a] -= g(k, a) * yk;
+    __syncthreads();
+  }
+}
+
+// p_u += w_u z_c (z_c = sum_r y_r A[r][c] + y_m), clipped to the box; one
+// more round for the instance.
+__global__ __launch_bounds__(256) void brep_step_kernel(BNet N, const double *__restrict__ A,
+                                                        const double *__restrict__ y,
+                                                        BRepState *st, double *__restrict__ p) {
+  const int i = blockIdx.y;
+  const BRepState s = st[i];
+  if (s.stop || s.fail) return;
+  const int m = s.m;
+  const double *Ai = A + (size_t)i * kBRepRows * N.ldc;
+  const double *yi = y + (size_t)i * kBRepRows;
+  double *pi = p + (size_t)i * N.n_g;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N.n_c; j += gridDim.x * blockDim.x) {
+    double z = 0.0;
+    for (int r = 0; r < m; ++r) z += yi[r] * Ai[(size_t)r * N.ldc + j];
+    z += yi[m];
+    for (int u = N.seg[j]; u < N.seg[j + 1]; ++u) {
+      const double pu = pi[u];
+      pi[u] = fmin(fmax(pu + brep_weight(pu, N.pmin[u], N.pmax[u]) * z, N.pmin[u]), N.pmax[u]);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) st[i].rounds = s.rounds + 1;
+}
+
+// One workgroup per instance: cost, balance, largest overload and largest
+// shift of the final iterate; out[i][0..3].
+__global__ __launch_bounds__(256) void brep_final_kernel(BNet N, const double *__restrict__ part,
+                                                         int gc, const double *__restrict__ p,
+                                                         const double *__restrict__ p0c,
+                                                         double *__restrict__ out) {
+  __shared__ double mo_s[4], sh_s[4];
+  const int i = blockIdx.x;
+  const double *Fi = N.F64 + (size_t)i * N.nlp, *fdi = N.fd64 + (size_t)i * N.n_l;
+  double mo = 0.0, sh = 0.0;
+  for (int l = threadIdx.x; l < N.n_l; l += blockDim.x) {
+    const double F = Fi[l] - fdi[l];
+    mo = fmax(mo, fmax(F - N.flim64[l], -F - N.flim64[l]));
+  }
+  for (int u = threadIdx.x; u < N.n_g; u += blockDim.x)
+    sh = fmax(sh, fabs(p[(size_t)i * N.n_g + u] - p0c[(size_t)i * N.n_g + u]));
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    mo = fmax(mo, __shfl_xor(mo, off, kWave));
+    sh = fmax(sh, __shfl_xor(sh, off, kWave));
+  }
+  if (threadIdx.x % kWave == 0) {
+    mo_s[threadIdx.x / kWave] = mo;
+    sh_s[threadIdx.x / kWave] = sh;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double cost = 0.0, gen = 0.0;
+  for (int b = 0; b < gc; ++b) {
+    cost += part[((size_t)i * gc + b) * 2];
+    gen += part[((size_t)i * gc + b) * 2 + 1];
+  }
+  mo = 0.0;
+  sh = 0.0;
+  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+    mo = fmax(mo, mo_s[w]);
+    sh = fmax(sh, sh_s[w]);
+  }
+  out[(size_t)i * 4] = cost;
+  out[(size_t)i * 4 + 1] = N.D[i] - gen;
+  out[(size_t)i * 4 + 2] = mo;
+  out[(size_t)i * 4 + 3] = sh;
+}
+
 // ---- setup -----------------------------------------------------------------
 // tmp[l][j] = H[l][cols[j]] (zero padded to [nlp][ldc]) in FP64.
 __global__ void bgather_kernel(const double *__restrict__ H, int n_bus, int n_l,
@@ -849,6 +1203,14 @@ struct HostNet {
   std::vector<int> gperm;  // unit t of the column order is generator gperm[t]
   int n_bus = 0;
   std::vector<void *> owned;
+  // primal repair buffers (allocated by the network's first repair)
+  struct Repair {
+    double *pin = nullptr, *p = nullptr, *p0c = nullptr, *W = nullptr, *t = nullptr,
+           *y = nullptr, *G = nullptr, *A = nullptr, *part = nullptr, *out = nullptr;
+    int *pos = nullptr, *rows = nullptr, *sgn = nullptr;
+    BRepState *st = nullptr;
+    bool ready = false;
+  } rep;
   double best_dummy = 0;
 };
 
@@ -1681,6 +2043,111 @@ dcopf_status dcopf_batch_primal(dcopf_batch_t b, int32_t net, dcopf_primal *out,
     if (p_avg)
       for (int t = 0; t < N.n_g; ++t)
         p_avg[(size_t)i * N.n_g + hn.gperm[t]] = pb[(size_t)i * N.n_g + t];
+  }
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_repair(dcopf_batch_t b, int32_t net, const double *p_in,
+                                int32_t max_rounds, dcopf_repair *out, double *p_out) {
+  if (!b || !out || net < 0 || net >= (int)b->nets.size() || max_rounds < 0)
+    return set_error("bad arguments"), DCOPF_E_INVALID;
+  HostNet &hn = b->nets[net];
+  BNet &N = hn.d;
+  const int B = N.B, ng = N.n_g, nl = N.n_l;
+  if (p_in)
+    for (size_t k = 0; k < (size_t)B * ng; ++k)
+      if (!std::isfinite(p_in[k])) return set_error("p_in is not finite"), DCOPF_E_INVALID;
+  const int gc = std::max(1, std::min(kPrimalColBlocks, (N.ldc + 255) / 256));
+  auto &R = hn.rep;
+  if (!R.ready) {
+    bool ok = true;
+    std::vector<void *> &own = hn.owned;
+    R.pin = balloc<double>(own, (size_t)B * ng, &ok);
+    R.p = balloc<double>(own, (size_t)B * ng, &ok);
+    R.p0c = balloc<double>(own, (size_t)B * ng, &ok);
+    R.W = balloc<double>(own, (size_t)B * N.ldc, &ok);
+    R.t = balloc<double>(own, (size_t)B * kBRepRows, &ok);
+    R.y = balloc<double>(own, (size_t)B * kBRepRows, &ok);
+    R.G = balloc<double>(own, (size_t)B * kBRepRows * kBRepRows, &ok);
+    R.A = balloc<double>(own, (size_t)B * kBRepRows * N.ldc, &ok);
+    R.part = balloc<double>(own, (size_t)B * gc * 2, &ok);
+    R.out = balloc<double>(own, (size_t)B * 4, &ok);
+    R.pos = balloc<int>(own, (size_t)B * nl, &ok);
+    R.rows = balloc<int>(own, (size_t)B * kBRepRows, &ok);
+    R.sgn = balloc<int>(own, (size_t)B * kBRepRows, &ok);
+    R.st = balloc<BRepState>(own, (size_t)B, &ok);
+    if (!ok) return set_error("device allocation failed"), DCOPF_E_NOMEM;
+    R.ready = true;
+  }
+  hipStream_t s = b->stream;
+  DCOPF_HIP_TRY(hipStreamSynchronize(s));
+  const double *src = R.pin;
+  if (p_in) {
+    std::vector<double> pc((size_t)B * ng);  // unit t of the column order is generator gperm[t]
+    for (int i = 0; i < B; ++i)
+      for (int t = 0; t < ng; ++t) pc[(size_t)i * ng + t] = p_in[(size_t)i * ng + hn.gperm[t]];
+    DCOPF_HIP_TRY(hipMemcpyAsync(R.pin, pc.data(), pc.size() * 8, hipMemcpyHostToDevice, s));
+    DCOPF_HIP_TRY(hipStreamSynchronize(s));
+  } else {
+    BScal h{};
+    DCOPF_HIP_TRY(hipMemcpy(&h, b->sc, sizeof(h), hipMemcpyDeviceToHost));
+    if (h.avg_count <= 0) return set_error("no iterations averaged"), DCOPF_E_STATE;
+    bprimal_cols_kernel<<<dim3((unsigned)gc, (unsigned)B), 256, 0, s>>>(N, b->sc, N.ppart);
+    src = N.pbar;
+  }
+  const int gi = std::min(64, (std::max(ng, nl) + 255) / 256);
+  brep_init_kernel<<<dim3((unsigned)gi, (unsigned)B), 256, 0, s>>>(N, src, R.p, R.p0c, R.pos,
+                                                                   R.st);
+  std::vector<BRepState> hs(B);
+  const dim3 dg((unsigned)(N.nlp / 16), (unsigned)(N.Bp / 64));
+  const int ccb = (N.ldc + 255) / 256;
+  for (;;) {
+    brep_cols_kernel<<<dim3((unsigned)gc, (unsigned)B), 256, 0, s>>>(N, R.p, R.W, R.part);
+    dgemm_nt_kernel<<<dg, 256, 0, s>>>(N.X64, N.P64, N.F64, N.ldc, N.nlp, N.Bp);
+    brep_active_kernel<<<B, 256, 0, s>>>(N, R.part, gc, max_rounds, R.pos, R.rows, R.sgn, R.t,
+                                         R.st);
+    DCOPF_HIP_TRY(hipGetLastError());
+    DCOPF_HIP_TRY(hipMemcpyAsync(hs.data(), R.st, (size_t)B * sizeof(BRepState),
+                                 hipMemcpyDeviceToHost, s));
+    DCOPF_HIP_TRY(hipStreamSynchronize(s));
+    int new_rows = 0, live = 0;
+    long long pairs = 0;
+    for (const BRepState &x : hs) {
+      if (x.stop) continue;
+      ++live;
+      new_rows = std::max(new_rows, x.m - x.m_old);
+      pairs = std::max(pairs, (long long)(x.m + 1) * (x.m + 2) / 2);
+    }
+    if (live == 0) break;
+    if (new_rows > 0)
+      brep_gather_kernel<<<dim3((unsigned)(ccb * new_rows), (unsigned)B), 256, 0, s>>>(
+          N, R.rows, R.st, ccb, R.A);
+    brep_gram_kernel<<<dim3((unsigned)((pairs + 3) / 4), (unsigned)B), 256, 0, s>>>(N, R.A, R.W,
+                                                                                   R.st, R.G);
+    brep_solve_kernel<<<B, 1024, 0, s>>>(R.G, R.t, R.y, R.st);
+    brep_step_kernel<<<dim3((unsigned)((N.n_c + 255) / 256), (unsigned)B), 256, 0, s>>>(
+        N, R.A, R.y, R.st, R.p);
+  }
+  brep_final_kernel<<<B, 256, 0, s>>>(N, R.part, gc, R.p, R.p0c, R.out);
+  DCOPF_HIP_TRY(hipGetLastError());
+  std::vector<double> r((size_t)B * 4), pb;
+  DCOPF_HIP_TRY(hipMemcpyAsync(r.data(), R.out, r.size() * 8, hipMemcpyDeviceToHost, s));
+  if (p_out) {
+    pb.resize((size_t)B * ng);
+    DCOPF_HIP_TRY(hipMemcpyAsync(pb.data(), R.p, pb.size() * 8, hipMemcpyDeviceToHost, s));
+  }
+  DCOPF_HIP_TRY(hipStreamSynchronize(s));
+  for (int i = 0; i < B; ++i) {
+    out[i].cost = r[(size_t)i * 4];
+    out[i].balance = r[(size_t)i * 4 + 1];
+    out[i].max_overload = std::max(0.0, r[(size_t)i * 4 + 2]);
+    out[i].max_shift = r[(size_t)i * 4 + 3];
+    out[i].feasible = hs[i].done ? 1 : 0;
+    out[i].rounds = hs[i].rounds;
+    out[i].n_active = hs[i].m;
+    out[i].pad = 0;
+    if (p_out)
+      for (int t = 0; t < ng; ++t) p_out[(size_t)i * ng + hn.gperm[t]] = pb[(size_t)i * ng + t];
   }
   return DCOPF_OK;
 }
