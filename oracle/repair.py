@@ -24,11 +24,19 @@ rows C x <= d, and the box.  One round:
   5. rows a_i = (H_a C_g)[l_i, :] of the active lines with targets
      t_i = -(delta + r_i) in flow units (the flow change that leaves the row
      delta inside its limit), and the balance row a = 1 with target beta;
-  6. y solves (A W A^T + eps I) y = t, eps = 1e-12 max diag, and
-     x <- clip(x + W A^T y, p_min, p_max).
+  6. working set: start with every active line; y solves
+     (A_S W A_S^T + eps I) y = t_S over the working lines and the balance row
+     (eps = 1e-12 of that matrix's largest diagonal); while some working
+     line has a multiplier with sigma_i y_i > 0 (its equality holds the
+     flow out at the limit against the rest of the move: as an inequality
+     it would be slack), the one with the largest sigma_i y_i (the first in
+     active-set order among equals) leaves the working set and the solve
+     repeats -- the primal active-set rule, one constraint at a time;
+  7. x <- clip(x + W A_S^T y, p_min, p_max).
 
 Before the clip, the step is the minimiser of sum_g dx_g^2 / w_g subject to
-the active rows holding their targets exactly.
+the balance and the working lines holding their targets, the working lines
+being those whose multipliers have the sign of a binding inequality.
 """
 from __future__ import annotations
 
@@ -93,12 +101,29 @@ def repair(K: Canonical, x0: np.ndarray, max_rounds: int = 32) -> RepairResult:
             t[i] = (-MARGIN - r[line]) if active[line] > 0 else (MARGIN + r[nl + line])
         t[-1] = beta
         G = (Am * w) @ Am.T
-        dmax = float(np.max(np.diag(G)))
+        sig = np.array([active[line] for line in lines], dtype=float)
+        work = list(range(len(lines)))
+        bal = len(lines)
+        while True:
+            S = work + [bal]
+            Gs = G[np.ix_(S, S)]
+            dmax = float(np.max(np.diag(Gs)))
+            if not dmax > 0.0:
+                break
+            Gs = Gs + 1e-12 * dmax * np.eye(len(S))
+            L = np.linalg.cholesky(Gs)
+            ys = np.linalg.solve(L.T, np.linalg.solve(L, t[S]))
+            worst, kw = 0.0, -1
+            for k, i in enumerate(work):
+                if sig[i] * ys[k] > worst:
+                    worst, kw = sig[i] * ys[k], k
+            if kw < 0:
+                break
+            del work[kw]
         if not dmax > 0.0:
             break
-        G += 1e-12 * dmax * np.eye(G.shape[0])
-        L = np.linalg.cholesky(G)
-        y = np.linalg.solve(L.T, np.linalg.solve(L, t))
+        y = np.zeros(len(lines) + 1)
+        y[S] = ys
         x = np.clip(x + w * (Am.T @ y), lo, hi)
         rounds += 1
     pe = primal_eval(K, x)

@@ -81,6 +81,29 @@ def test_other_direction_and_balance_only():
     np.testing.assert_allclose(r.x, [10.0 + 10.0 / 9.0, 80.0 + 80.0 / 9.0], rtol=0, atol=1e-9)
 
 
+def test_slack_held_line_leaves_the_working_set():
+    # radial: slack - line 1 - bus 1 (generator 2, load 90) - line 2 - bus 2
+    # (generator 1, load 110); F1 = 200 - p1 - p2, F2 = 110 - p1, limits 50.
+    # From (100, 40, 40) both lines are violated (F1 = 120, F2 = 70) and the
+    # balance is +20.  Holding both at their limits gives line 2 the
+    # multiplier sign of a slack inequality (sigma y = +0.75), so it leaves
+    # the working set: the move is the least-norm one for line 1 and the
+    # balance alone, headrooms 100 : 40 : 40, which takes line 2 to 35 too.
+    HC = np.array([[0.0, -1.0, -1.0], [0.0, -1.0, 0.0]])
+    Hd = np.array([-200.0, -110.0])
+    fmax = np.array([50.0, 50.0])
+    K = D.Canonical(c=np.array([1.0, 2.0, 3.0]), M=np.zeros(3), A=-np.ones((1, 3)),
+                    b=np.array([-200.0]), C=np.vstack([HC, -HC]),
+                    d=np.concatenate([fmax + Hd, fmax - Hd]), lo=np.zeros(3),
+                    hi=np.full(3, 200.0))
+    r = repair(K, np.array([100.0, 40.0, 40.0]))
+    assert r.feasible and r.rounds == 1 and r.active == [(0, 1), (1, 1)]
+    np.testing.assert_allclose(
+        r.x, [50.0 - MARGIN, 75.0 + MARGIN / 2, 75.0 + MARGIN / 2], rtol=0, atol=1e-9)
+    F = HC @ r.x - Hd
+    assert F[1] == pytest.approx(35.0 - MARGIN / 2, abs=1e-9)
+
+
 def test_feasible_input_is_returned_unchanged():
     K = one_line([200.0, 200.0])
     x = np.array([40.0, 60.0])
@@ -118,6 +141,22 @@ def test_repaired_average_is_a_feasible_upper_bound(name, seed, n):
     assert rep.cost - opt <= 1e-3 * abs(opt)
     print(f"{name}: UB - OPT = {(rep.cost - opt) / opt:.2e}, UB - LB = "
           f"{(rep.cost - res.best) / rep.cost:.2e} in {rep.rounds} rounds")
+
+
+def test_perturbed_optima_repair_to_feasible_upper_bounds():
+    # HiGHS optimum + N(0, 3 MW) noise per generator: many lines violated at
+    # once; every candidate repairs to a feasible dispatch costing no less
+    # than the optimum
+    net, p = synth.make_network("geo300", 3)
+    K = D.canonical(p)
+    o = ref.opt_btheta(net, p)
+    rng = np.random.default_rng(0)
+    for _ in range(6):
+        rep = repair(K, o["p"] + rng.normal(0.0, 3.0, o["p"].size), max_rounds=64)
+        assert rep.feasible
+        pe = D.primal_eval(K, rep.x)
+        assert pe.max_overload == 0.0 and abs(pe.balance) <= 1e-9 * np.sum(p.d)
+        assert rep.cost >= o["opt"] * (1 - 1e-12)
 
 
 def test_qp_repair_bounds_the_certified_optimum():
