@@ -24,19 +24,22 @@ rows C x <= d, and the box.  One round:
   5. rows a_i = (H_a C_g)[l_i, :] of the active lines with targets
      t_i = -(delta + r_i) in flow units (the flow change that leaves the row
      delta inside its limit), and the balance row a = 1 with target beta;
-  6. working set: start with every active line; y solves
-     (A_S W A_S^T + eps I) y = t_S over the working lines and the balance row
-     (eps = 1e-12 of that matrix's largest diagonal); while some working
-     line has a multiplier with sigma_i y_i > 0 (its equality holds the
-     flow out at the limit against the rest of the move: as an inequality
-     it would be slack), the one with the largest sigma_i y_i (the first in
-     active-set order among equals) leaves the working set and the solve
-     repeats -- the primal active-set rule, one constraint at a time;
-  7. x <- clip(x + W A_S^T y, p_min, p_max).
+  6. the active lines are inequalities (the flow may end anywhere inside
+     limit - delta) and the balance an equality.  Working set S: start with
+     every active line; y solves (A_S W A_S^T + eps I) y = t_S over S and the
+     balance row (eps = 1e-12 of that matrix's largest diagonal).  Then, in
+     this order: if a working line has a multiplier with sigma_i y_i > 0
+     (holding it at its target pushes its flow out: as an inequality it is
+     slack), the one with the largest sigma_i y_i leaves S; otherwise, if a
+     line outside S would end more than delta / 2 past its target under the
+     step (sigma_i ((G y)_i - t_i), G the Gram matrix of all active rows),
+     the one ending furthest joins S again; otherwise S is final.  Ties go to
+     the first in active-set order; at most 4 (m + 1) + 8 solves;
+  7. x <- clip(x + W A^T y, p_min, p_max) with y zero outside S.
 
-Before the clip, the step is the minimiser of sum_g dx_g^2 / w_g subject to
-the balance and the working lines holding their targets, the working lines
-being those whose multipliers have the sign of a binding inequality.
+Before the clip, the step is the least sum_g dx_g^2 / w_g move that closes
+the balance and brings every active line inside its limit less delta, the
+binding lines being found by the primal-dual active-set rule of step 6.
 """
 from __future__ import annotations
 
@@ -102,10 +105,11 @@ def repair(K: Canonical, x0: np.ndarray, max_rounds: int = 32) -> RepairResult:
         t[-1] = beta
         G = (Am * w) @ Am.T
         sig = np.array([active[line] for line in lines], dtype=float)
-        work = list(range(len(lines)))
-        bal = len(lines)
-        while True:
-            S = work + [bal]
+        nrow = len(lines)
+        work = list(range(nrow))
+        cap = 4 * (nrow + 1) + 8
+        for _ in range(cap):
+            S = work + [nrow]
             Gs = G[np.ix_(S, S)]
             dmax = float(np.max(np.diag(Gs)))
             if not dmax > 0.0:
@@ -113,17 +117,26 @@ def repair(K: Canonical, x0: np.ndarray, max_rounds: int = 32) -> RepairResult:
             Gs = Gs + 1e-12 * dmax * np.eye(len(S))
             L = np.linalg.cholesky(Gs)
             ys = np.linalg.solve(L.T, np.linalg.solve(L, t[S]))
+            y = np.zeros(nrow + 1)
+            y[S] = ys
             worst, kw = 0.0, -1
             for k, i in enumerate(work):
                 if sig[i] * ys[k] > worst:
-                    worst, kw = sig[i] * ys[k], k
-            if kw < 0:
-                break
-            del work[kw]
+                    worst, kw = sig[i] * ys[k], i
+            if kw >= 0:
+                work.remove(kw)
+                continue
+            Gy = G @ y
+            worst, ka = 0.5 * MARGIN, -1
+            for i in range(nrow):
+                if i not in work and sig[i] * (Gy[i] - t[i]) > worst:
+                    worst, ka = sig[i] * (Gy[i] - t[i]), i
+            if ka >= 0:
+                work = sorted(work + [ka])
+                continue
+            break
         if not dmax > 0.0:
             break
-        y = np.zeros(len(lines) + 1)
-        y[S] = ys
         x = np.clip(x + w * (Am.T @ y), lo, hi)
         rounds += 1
     pe = primal_eval(K, x)
