@@ -992,74 +992,20 @@ __global__ __launch_bounds__(256) void brep_gram_kernel(BNet N, const double *__
   if (lane == 0) G[((size_t)i * kBRepRows + a) * kBRepRows + b] = sum;
 }
 
-// One workgroup per instance: ridge, Cholesky in place, L L^T y = t.
-__global__ __launch_bounds__(1024) void brep_solve_kernel(double *__restrict__ G,
+// One workgroup per instance: the working-set solve of its step (ws_solve).
+__global__ __launch_bounds__(1024) void brep_solve_kernel(const double *__restrict__ G,
                                                           const double *__restrict__ t,
+                                                          const int *__restrict__ sgn,
+                                                          double *__restrict__ L,
                                                           double *__restrict__ y,
                                                           BRepState *st) {
-  __shared__ double red[16];
-  __shared__ int fail_s;
+  __shared__ WsShared sh;
   const int i = blockIdx.x;
   if (st[i].stop) return;
-  const int n = st[i].m + 1, tid = threadIdx.x, nt = blockDim.x;
-  double *Gi = G + (size_t)i * kBRepRows * kBRepRows;
-  const double *ti = t + (size_t)i * kBRepRows;
-  double *yi = y + (size_t)i * kBRepRows;
-  auto g = [&](int a, int b) -> double & { return Gi[(size_t)a * kBRepRows + b]; };
-  double dm = 0.0;
-  for (int a = tid; a < n; a += nt) dm = fmax(dm, g(a, a));
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) dm = fmax(dm, __shfl_xor(dm, off, kWave));
-  if (tid % kWave == 0) red[tid / kWave] = dm;
-  if (tid == 0) fail_s = 0;
-  __syncthreads();
-  dm = 0.0;
-  for (int w = 0; w < nt / kWave; ++w) dm = fmax(dm, red[w]);
-  if (!(dm > 0.0)) {
-    if (tid == 0) st[i].fail = 1;
-    return;
-  }
-  for (int a = tid; a < n; a += nt) g(a, a) += kBRepRidge * dm;
-  for (int a = tid; a < n; a += nt) yi[a] = ti[a];
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (tid == 0) {
-      const double d = g(k, k);
-      if (d > 0.0)
-        g(k, k) = sqrt(d);
-      else
-        fail_s = 1;
-    }
-    __syncthreads();
-    if (fail_s) break;
-    const double dk = g(k, k);
-    for (int a = k + 1 + tid; a < n; a += nt) g(a, k) /= dk;
-    __syncthreads();
-    const int r = n - k - 1;
-    for (int idx = tid; idx < r * r; idx += nt) {
-      const int aa = idx / r, bb = idx % r;
-      if (bb <= aa) g(k + 1 + aa, k + 1 + bb) -= g(k + 1 + aa, k) * g(k + 1 + bb, k);
-    }
-    __syncthreads();
-  }
-  if (fail_s) {
-    if (tid == 0) st[i].fail = 1;
-    return;
-  }
-  for (int k = 0; k < n; ++k) {
-    if (tid == 0) yi[k] /= g(k, k);
-    __syncthreads();
-    const double yk = yi[k];
-    for (int a = k + 1 + tid; a < n; a += nt) yi[a] -= g(a, k) * yk;
-    __syncthreads();
-  }
-  for (int k = n - 1; k >= 0; --k) {
-    if (tid == 0) yi[k] /= g(k, k);
-    __syncthreads();
-    const double yk = yi[k];
-    for (int a = tid; a < k; a += nt) yi[a] -= g(k, a) * yk;
-    __syncthreads();
-  }
+  const size_t g0 = (size_t)i * kBRepRows * kBRepRows, r0 = (size_t)i * kBRepRows;
+  const bool ok = ws_solve<kBRepRows>(G + g0, t + r0, sgn + r0, st[i].m, L + g0, y + r0,
+                                      kBRepMargin, kBRepRidge, sh);
+  if (!ok && threadIdx.x == 0) st[i].fail = 1;
 }
 
 // p_u += w_u z_c (z_c = sum_r y_r A[r][c] + y_m), clipped to the box; one
@@ -1206,7 +1152,8 @@ struct HostNet {
   // primal repair buffers (allocated by the network's first repair)
   struct Repair {
     double *pin = nullptr, *p = nullptr, *p0c = nullptr, *W = nullptr, *t = nullptr,
-           *y = nullptr, *G = nullptr, *A = nullptr, *part = nullptr, *out = nullptr;
+           *y = nullptr, *G = nullptr, *L = nullptr, *A = nullptr, *part = nullptr,
+           *out = nullptr;
     int *pos = nullptr, *rows = nullptr, *sgn = nullptr;
     BRepState *st = nullptr;
     bool ready = false;
@@ -2069,6 +2016,7 @@ dcopf_status dcopf_batch_repair(dcopf_batch_t b, int32_t net, const double *p_in
     R.t = balloc<double>(own, (size_t)B * kBRepRows, &ok);
     R.y = balloc<double>(own, (size_t)B * kBRepRows, &ok);
     R.G = balloc<double>(own, (size_t)B * kBRepRows * kBRepRows, &ok);
+    R.L = balloc<double>(own, (size_t)B * kBRepRows * kBRepRows, &ok);
     R.A = balloc<double>(own, (size_t)B * kBRepRows * N.ldc, &ok);
     R.part = balloc<double>(own, (size_t)B * gc * 2, &ok);
     R.out = balloc<double>(own, (size_t)B * 4, &ok);
@@ -2124,7 +2072,7 @@ dcopf_status dcopf_batch_repair(dcopf_batch_t b, int32_t net, const double *p_in
           N, R.rows, R.st, ccb, R.A);
     brep_gram_kernel<<<dim3((unsigned)((pairs + 3) / 4), (unsigned)B), 256, 0, s>>>(N, R.A, R.W,
                                                                                    R.st, R.G);
-    brep_solve_kernel<<<B, 1024, 0, s>>>(R.G, R.t, R.y, R.st);
+    brep_solve_kernel<<<B, 1024, 0, s>>>(R.G, R.t, R.sgn, R.L, R.y, R.st);
     brep_step_kernel<<<dim3((unsigned)((N.n_c + 255) / 256), (unsigned)B), 256, 0, s>>>(
         N, R.A, R.y, R.st, R.p);
   }

@@ -155,4 +155,151 @@ inline hipError_t launch_k(void (*kernel)(KA...), dim3 grid, dim3 block, unsigne
   return hipLaunchKernel((const void *)kernel, grid, block, ptrs, lds, stream);
 }
 
+// ---------------------------------------------------------------------------
+// Working-set solve of one repair step, block-wide (every thread of the
+// workgroup calls it with the same arguments).  G: Gram matrix of the active
+// line rows 0..m-1 and the balance row m (lower triangle, row stride LD,
+// left intact); t: targets; sg: directions (+1 / -1) of rows 0..m-1; L:
+// factor workspace (LD x LD); y: the multipliers over rows 0..m, zero
+// outside the working set.  The active lines are inequalities: starting
+// from all of them, a working line whose multiplier pushes its flow out
+// (largest sg y > 0) leaves, else the line outside that the step would push
+// furthest past its target by more than margin / 2 ((G y)_r - t_r) joins
+// again, else the set is final; ties to the lowest row, at most
+// 4 (m + 1) + 8 solves, each a Cholesky factorisation (ridge of ridge times
+// the largest diagonal) and two triangular solves.  Returns false when a
+// pivot was not positive.
+// ---------------------------------------------------------------------------
+struct WsShared {
+  int wm[256];      // working mask of rows 0..m-1
+  int sidx[256];    // working rows in order, then the balance row
+  double v[256];    // right-hand side / solution, then the join test
+  double red[16];
+  int ns, pick, fail;
+};
+
+template <int LD>
+__device__ bool ws_solve(const double *G, const double *t, const int *sg, int m, double *L,
+                         double *y, double margin, double ridge, WsShared &sh) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  auto gl = [&](int a, int b) -> double {
+    return a >= b ? G[(size_t)a * LD + b] : G[(size_t)b * LD + a];
+  };
+  auto l = [&](int a, int b) -> double & { return L[(size_t)a * LD + b]; };
+  for (int r = tid; r < m; r += nt) sh.wm[r] = 1;
+  __syncthreads();
+  const int cap = 4 * (m + 1) + 8;
+  for (int pass = 0; pass < cap; ++pass) {
+    if (tid == 0) {
+      int ns = 0;
+      for (int r = 0; r < m; ++r)
+        if (sh.wm[r]) sh.sidx[ns++] = r;
+      sh.sidx[ns++] = m;
+      sh.ns = ns;
+      sh.fail = 0;
+    }
+    __syncthreads();
+    const int n = sh.ns;
+    double dm = 0.0;
+    for (int a = tid; a < n; a += nt) dm = fmax(dm, gl(sh.sidx[a], sh.sidx[a]));
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) dm = fmax(dm, __shfl_xor(dm, off, kWave));
+    if (tid % kWave == 0) sh.red[tid / kWave] = dm;
+    __syncthreads();
+    dm = 0.0;
+    for (int w = 0; w < nt / kWave; ++w) dm = fmax(dm, sh.red[w]);
+    if (!(dm > 0.0)) return false;
+    for (int e = tid; e < n * n; e += nt) {
+      const int a = e / n, b = e % n;
+      if (b <= a) l(a, b) = gl(sh.sidx[a], sh.sidx[b]) + (a == b ? ridge * dm : 0.0);
+    }
+    for (int a = tid; a < n; a += nt) sh.v[a] = t[sh.sidx[a]];
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+      if (tid == 0) {
+        const double d = l(k, k);
+        if (d > 0.0)
+          l(k, k) = sqrt(d);
+        else
+          sh.fail = 1;
+      }
+      __syncthreads();
+      if (sh.fail) return false;
+      const double dk = l(k, k);
+      for (int a = k + 1 + tid; a < n; a += nt) l(a, k) /= dk;
+      __syncthreads();
+      const int r = n - k - 1;
+      for (int idx = tid; idx < r * r; idx += nt) {
+        const int aa = idx / r, bb = idx % r;
+        if (bb <= aa) l(k + 1 + aa, k + 1 + bb) -= l(k + 1 + aa, k) * l(k + 1 + bb, k);
+      }
+      __syncthreads();
+    }
+    for (int k = 0; k < n; ++k) {  // L z = t
+      if (tid == 0) sh.v[k] /= l(k, k);
+      __syncthreads();
+      const double vk = sh.v[k];
+      for (int a = k + 1 + tid; a < n; a += nt) sh.v[a] -= l(a, k) * vk;
+      __syncthreads();
+    }
+    for (int k = n - 1; k >= 0; --k) {  // L^T y = z
+      if (tid == 0) sh.v[k] /= l(k, k);
+      __syncthreads();
+      const double vk = sh.v[k];
+      for (int a = tid; a < k; a += nt) sh.v[a] -= l(k, a) * vk;
+      __syncthreads();
+    }
+    for (int r = tid; r <= m; r += nt) y[r] = 0.0;
+    __syncthreads();
+    for (int a = tid; a < n; a += nt) y[sh.sidx[a]] = sh.v[a];
+    __syncthreads();
+    if (tid == 0) {  // a working line held against a slack inequality leaves
+      double worst = 0.0;
+      int pick = -1;
+      for (int a = 0; a + 1 < n; ++a) {
+        const double val = sg[sh.sidx[a]] * sh.v[a];
+        if (val > worst) {
+          worst = val;
+          pick = sh.sidx[a];
+        }
+      }
+      sh.pick = pick;
+    }
+    __syncthreads();
+    if (sh.pick >= 0) {
+      if (tid == 0) sh.wm[sh.pick] = 0;
+      __syncthreads();
+      continue;
+    }
+    for (int r = tid; r < m; r += nt) {  // lines outside: end past the target?
+      double val = -1.0;
+      if (!sh.wm[r]) {
+        double gy = 0.0;
+        for (int k = 0; k <= m; ++k) gy += gl(r, k) * y[k];
+        val = sg[r] * (gy - t[r]);
+      }
+      sh.v[r] = val;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double worst = 0.5 * margin;
+      int pick = -1;
+      for (int r = 0; r < m; ++r)
+        if (!sh.wm[r] && sh.v[r] > worst) {
+          worst = sh.v[r];
+          pick = r;
+        }
+      sh.pick = pick;
+    }
+    __syncthreads();
+    if (sh.pick >= 0) {
+      if (tid == 0) sh.wm[sh.pick] = 1;
+      __syncthreads();
+      continue;
+    }
+    break;
+  }
+  return true;
+}
+
 }  // namespace dcopf

@@ -1005,70 +1005,17 @@ __global__ __launch_bounds__(256) void repair_gram_kernel(const double *__restri
   if (lane == 0) G[(size_t)i * kRepRows + j] = s;
 }
 
-// One workgroup: ridge, Cholesky G = L L^T in place (lower triangle), then
-// L L^T y = t.  st->fail when a pivot is not positive.
-__global__ __launch_bounds__(1024) void repair_solve_kernel(double *__restrict__ G, int m,
+// One workgroup: the working-set solve of the step (ws_solve: active lines
+// as inequalities, Cholesky in FP64).  st->fail when a pivot is not positive.
+__global__ __launch_bounds__(1024) void repair_solve_kernel(const double *__restrict__ G, int m,
                                                             const double *__restrict__ t,
+                                                            const int *__restrict__ sgn,
+                                                            double *__restrict__ L,
                                                             double *__restrict__ y,
                                                             RepairState *st) {
-  __shared__ double red[16];
-  __shared__ int fail_s;
-  const int n = m + 1, tid = threadIdx.x, nt = blockDim.x;
-  auto g = [&](int i, int j) -> double & { return G[(size_t)i * kRepRows + j]; };
-  double dm = 0.0;
-  for (int i = tid; i < n; i += nt) dm = fmax(dm, g(i, i));
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) dm = fmax(dm, __shfl_xor(dm, off, kWave));
-  if (tid % kWave == 0) red[tid / kWave] = dm;
-  if (tid == 0) fail_s = 0;
-  __syncthreads();
-  dm = 0.0;
-  for (int w = 0; w < nt / kWave; ++w) dm = fmax(dm, red[w]);
-  if (!(dm > 0.0)) {
-    if (tid == 0) st->fail = 1;
-    return;
-  }
-  for (int i = tid; i < n; i += nt) g(i, i) += kRepRidge * dm;
-  for (int i = tid; i < n; i += nt) y[i] = t[i];
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (tid == 0) {
-      const double d = g(k, k);
-      if (d > 0.0)
-        g(k, k) = sqrt(d);
-      else
-        fail_s = 1;
-    }
-    __syncthreads();
-    if (fail_s) break;
-    const double dk = g(k, k);
-    for (int i = k + 1 + tid; i < n; i += nt) g(i, k) /= dk;
-    __syncthreads();
-    const int r = n - k - 1;
-    for (int idx = tid; idx < r * r; idx += nt) {
-      const int ii = idx / r, jj = idx % r;
-      if (jj <= ii) g(k + 1 + ii, k + 1 + jj) -= g(k + 1 + ii, k) * g(k + 1 + jj, k);
-    }
-    __syncthreads();
-  }
-  if (fail_s) {
-    if (tid == 0) st->fail = 1;
-    return;
-  }
-  for (int k = 0; k < n; ++k) {  // L z = t
-    if (tid == 0) y[k] /= g(k, k);
-    __syncthreads();
-    const double yk = y[k];
-    for (int i = k + 1 + tid; i < n; i += nt) y[i] -= g(i, k) * yk;
-    __syncthreads();
-  }
-  for (int k = n - 1; k >= 0; --k) {  // L^T y = z
-    if (tid == 0) y[k] /= g(k, k);
-    __syncthreads();
-    const double yk = y[k];
-    for (int i = tid; i < k; i += nt) y[i] -= g(k, i) * yk;
-    __syncthreads();
-  }
+  __shared__ WsShared sh;
+  const bool ok = ws_solve<kRepRows>(G, t, sgn, m, L, y, kRepMargin, kRepRidge, sh);
+  if (!ok && threadIdx.x == 0) st->fail = 1;
 }
 
 // p_u += w_u z_c (z_c = sum_i y_i A[i][c] + y_m), clipped to the box.
@@ -1284,8 +1231,8 @@ struct dcopf_dual_s {
   // primal repair (allocated by its first call)
   struct Repair {
     double *pin = nullptr, *p = nullptr, *p0c = nullptr, *x = nullptr, *W = nullptr,
-           *F = nullptr, *t = nullptr, *y = nullptr, *G = nullptr, *A = nullptr, *pc = nullptr,
-           *pl = nullptr;
+           *F = nullptr, *t = nullptr, *y = nullptr, *G = nullptr, *L = nullptr, *A = nullptr,
+           *pc = nullptr, *pl = nullptr;
     int *pos = nullptr, *rows = nullptr, *sgn = nullptr;
     RepairState *st = nullptr;
     DevRepair *out = nullptr;
@@ -1486,7 +1433,7 @@ void free_handle(dcopf_dual_s *h) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   auto &R = h->rep;
-  void *rptrs[] = {R.pin, R.p, R.p0c, R.x, R.W, R.F, R.t, R.y, R.G, R.A, R.pc, R.pl,
+  void *rptrs[] = {R.pin, R.p, R.p0c, R.x, R.W, R.F, R.t, R.y, R.G, R.L, R.A, R.pc, R.pl,
                    R.pos, R.rows, R.sgn, R.st, R.out};
   for (void *p : rptrs)
     if (p) (void)hipFree(p);
@@ -2054,6 +2001,7 @@ dcopf_status dcopf_dual_repair(dcopf_dual_t h, const double *p_in, int32_t max_r
     R.t = dalloc<double>(kRepRows, &st);
     R.y = dalloc<double>(kRepRows, &st);
     R.G = dalloc<double>((size_t)kRepRows * kRepRows, &st);
+    R.L = dalloc<double>((size_t)kRepRows * kRepRows, &st);
     R.A = dalloc<double>((size_t)kRepRows * h->ldc, &st);
     R.pc = dalloc<double>(2 * (size_t)kPrimalBlocks, &st);
     R.pl = dalloc<double>(3 * (size_t)kPrimalBlocks, &st);
@@ -2105,7 +2053,7 @@ dcopf_status dcopf_dual_repair(dcopf_dual_t h, const double *p_in, int32_t max_r
     }
     const long long pairs = (long long)(hs.m + 1) * (hs.m + 2) / 2;
     repair_gram_kernel<<<(unsigned)((pairs + 3) / 4), 256, 0, s>>>(R.A, ldc, R.W, nc, hs.m, R.G);
-    repair_solve_kernel<<<1, 1024, 0, s>>>(R.G, hs.m, R.t, R.y, R.st);
+    repair_solve_kernel<<<1, 1024, 0, s>>>(R.G, hs.m, R.t, R.sgn, R.L, R.y, R.st);
     repair_step_kernel<<<(nc + 255) / 256, 256, 0, s>>>(R.A, ldc, R.y, hs.m, h->seg, h->pmin,
                                                         h->pmax, nc, R.st, R.p);
     ++rounds;
