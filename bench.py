@@ -225,7 +225,7 @@ def batch_certified(stream, nets, shapes, tiles, n_iters=10000):
     best, _ = b.best()
     t_iter = time.perf_counter() - t0
     t0 = time.perf_counter()
-    reps = [b.repair(k) for k in range(len(nets))]
+    reps = [b.repair(k, max_rounds=64) for k in range(len(nets))]
     t_rep = time.perf_counter() - t0
     b.close()
     offs = np.cumsum([0] + [sh[4] for sh in shapes])
