@@ -366,8 +366,10 @@ def bench_warmstart(args, stream):
                       R.init_params(np.random.default_rng(0), dims)])
     ms_step = model.time_train(X[:256].data_ptr(), Y[:256].data_ptr(), 256, 20)
     losses, t_train = W.timed(W.train, model, X, Y, args.epochs, 256, 1e-3, 0, 0.9, log)
-    start, t_pred = W.timed(W.predict, model, Dev, sx, st, base.n_line)
-    model.close()
+    # inference for the held-out scenarios: the standardisations folded into
+    # the first and last layers, raw loads in, raw multipliers out, handed to
+    # the batch on the device
+    model.set_params(W.fold_standardizers(model.get_params(), sx, st))
     opt = []
     with mp.get_context("spawn").Pool(16) as pool:
         for o in pool.imap(_highs_opt, [(net, base.replace(d=Dev[i]))
@@ -378,7 +380,9 @@ def bench_warmstart(args, stream):
     opt = np.array(opt)
     keep = np.isfinite(opt)
     Dev, opt = Dev[keep], opt[keep]
-    start = tuple(a[keep] for a in start)
+    torch.cuda.synchronize()
+    start, t_pred = W.timed(W.predict_dev, model, Dev)
+    model.close()
     log(f"{int(keep.sum())} held-out scenarios with an optimum; cold solves")
     sc_, sw_ = {}, {}
     (hc, pc), t_cold = W.timed(W.run_to_gap, base, Dev, opt, r["alpha"], r["rho"], None,

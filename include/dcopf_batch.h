@@ -132,6 +132,16 @@ dcopf_status dcopf_batch_primal(dcopf_batch_t b, int32_t net, dcopf_primal *out,
 dcopf_status dcopf_batch_repair(dcopf_batch_t b, int32_t net, const double *p_in,
                                 int32_t max_rounds, dcopf_repair *out, double *p_out);
 
+/* Start multipliers of every instance of network `net` from a DEVICE array
+ * (FP32, row i = instance i, row stride ld >= 2 n_line + 1, laid out
+ * [mu+ (n_line), mu- (n_line), lambda], as the warm-start network's output
+ * of dcopf_mlp.h): mu is projected onto mu >= 0 on the device; the
+ * optimiser state and best bounds restart as in set_multipliers.  For a
+ * start computed on the GPU with no host round trip.  DCOPF_E_NONFINITE if
+ * a value is not finite (the state is then unspecified).  Synchronises.  */
+dcopf_status dcopf_batch_set_start_dev(dcopf_batch_t b, int32_t net, const float *Y,
+                                       int32_t ld);
+
 /* Tile shapes in use for network `net`: cfg[0], cfg[1] = instances x
  * columns of one W-product workgroup tile, cfg[2] = its K split (over
  * lines), cfg[3] = instances * 1000 + lines of one F-product tile.         */

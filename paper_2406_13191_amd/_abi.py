@@ -166,9 +166,11 @@ class DualSolver:
         self._arrays = None  # inputs were copied by create
 
     # -- lifecycle ---------------------------------------------------------
-    def close(self):
+    def close(self, _destroy=lib.dcopf_dual_destroy):
+        # the destroy function is bound at class creation, so that a handle
+        # closed while the interpreter shuts down still finds it
         if getattr(self, "_h", None):
-            lib.dcopf_dual_destroy(self._h)
+            _destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -311,6 +313,7 @@ def _bind_batch():
                                                   P(C.c_double), P(C.c_double)]),
         "dcopf_batch_info": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int32), P(C.c_int64)]),
         "dcopf_batch_set_tiles": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int32)]),
+        "dcopf_batch_set_start_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
         "dcopf_batch_average": (C.c_int, [C.c_void_p, C.c_int32]),
         "dcopf_batch_primal": (C.c_int, [C.c_void_p, C.c_int32, P(Primal_C), P(C.c_double)]),
         "dcopf_batch_repair": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double), C.c_int32,
@@ -370,9 +373,11 @@ class BatchSolver:
         self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(int)
         self.n_total = int(self.offsets[-1])
 
-    def close(self):
+    def close(self, _destroy=lib.dcopf_batch_destroy):
+        # the destroy function is bound at class creation, so that a handle
+        # closed while the interpreter shuts down still finds it
         if getattr(self, "_h", None):
-            lib.dcopf_batch_destroy(self._h)
+            _destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -424,6 +429,11 @@ class BatchSolver:
         lam, mu_p, mu_m = _f64(lam), _f64(mu_p), _f64(mu_m)
         check(lib.dcopf_batch_set_multipliers(self._h, int(net), _dptr(lam), _dptr(mu_p),
                                               _dptr(mu_m)))
+
+    def set_start_dev(self, net: int, y_ptr: int, ld: int):
+        """Start multipliers from a device FP32 array [n_inst, ld] laid out
+        [mu+, mu-, lambda] (e.g. a torch tensor's data_ptr())."""
+        check(lib.dcopf_batch_set_start_dev(self._h, int(net), C.c_void_p(y_ptr), int(ld)))
 
     def info(self, net: int):
         cfg = np.zeros(4, np.int32)
@@ -528,9 +538,11 @@ class MLP:
         self._h = h
         self.n_params = int(lib.dcopf_mlp_param_count(h))
 
-    def close(self):
+    def close(self, _destroy=lib.dcopf_mlp_destroy):
+        # the destroy function is bound at class creation, so that a handle
+        # closed while the interpreter shuts down still finds it
         if getattr(self, "_h", None):
-            lib.dcopf_mlp_destroy(self._h)
+            _destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -1076,6 +1076,32 @@ __global__ __launch_bounds__(256) void brep_final_kernel(BNet N, const double *_
   out[(size_t)i * 4 + 3] = sh;
 }
 
+// Start multipliers of every instance from rows of a device array (the warm
+// start network's output): mu+ = max(0, Y[i][l]), mu- = max(0, Y[i][n_l + l])
+// into the FP32 state (zero padding), lambda = Y[i][2 n_l] into slot 0;
+// bad = 1 on a value that is not finite.
+__global__ void bset_start_kernel(BNet N, const float *__restrict__ Y, int ld, int *bad) {
+  const int i = blockIdx.y;
+  const float *yi = Y + (size_t)i * ld;
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < N.ldl; l += gridDim.x * blockDim.x) {
+    float a = 0.f, c = 0.f;
+    if (l < N.n_l) {
+      a = yi[l];
+      c = yi[N.n_l + l];
+      if (!isfinite(a) || !isfinite(c)) *bad = 1;
+      a = fmaxf(a, 0.f);
+      c = fmaxf(c, 0.f);
+    }
+    N.mu_p[(size_t)i * N.ldl + l] = a;
+    N.mu_m[(size_t)i * N.ldl + l] = c;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const float lam = yi[2 * N.n_l];
+    if (!isfinite(lam)) *bad = 1;
+    N.lam[i] = (double)lam;
+  }
+}
+
 // ---- setup -----------------------------------------------------------------
 // tmp[l][j] = H[l][cols[j]] (zero padded to [nlp][ldc]) in FP64.
 __global__ void bgather_kernel(const double *__restrict__ H, int n_bus, int n_l,
@@ -1937,6 +1963,35 @@ dcopf_status dcopf_batch_set_multipliers(dcopf_batch_t b, int32_t net, const dou
   DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
   std::fill(b->best.begin(), b->best.end(), -INFINITY);
   std::fill(b->best_iter.begin(), b->best_iter.end(), -1);
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_set_start_dev(dcopf_batch_t b, int32_t net, const float *Y,
+                                       int32_t ld) {
+  if (!b || net < 0 || net >= (int)b->nets.size() || !Y)
+    return set_error("bad arguments"), DCOPF_E_INVALID;
+  const BNet &N = b->nets[net].d;
+  if (ld < 2 * N.n_l + 1) return set_error("ld must be >= 2 n_line + 1"), DCOPF_E_INVALID;
+  DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
+  DCOPF_HIP_TRY(reset_state(b, 0, net));
+  int *bad = nullptr;
+  DCOPF_HIP_TRY(hipMalloc(&bad, sizeof(int)));
+  hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), b->stream);
+  dim3 vg((unsigned)std::min(64, (N.ldl + 255) / 256), (unsigned)N.B);
+  if (e == hipSuccess) {
+    bset_start_kernel<<<vg, 256, 0, b->stream>>>(N, Y, ld, bad);
+    bmake_v_kernel<<<vg, 256, 0, b->stream>>>(N.mu_p, N.mu_m, N.B, N.n_l, N.ldl, N.V_hi, N.V_lo);
+    e = hipGetLastError();
+  }
+  int hbad = 0;
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e == hipSuccess) e = hipMemcpy(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost);
+  (void)hipFree(bad);
+  if (e != hipSuccess)
+    return set_error(std::string("set_start_dev: ") + hipGetErrorString(e)), DCOPF_E_HIP;
+  std::fill(b->best.begin(), b->best.end(), -INFINITY);
+  std::fill(b->best_iter.begin(), b->best_iter.end(), -1);
+  if (hbad) return set_error("non-finite start values"), DCOPF_E_NONFINITE;
   return DCOPF_OK;
 }
 

@@ -5,10 +5,12 @@
 //   1. B_r, one thread per row, from the lines incident to its bus;
 //   2. B_r = L L^T, right-looking by blocks of 64: the diagonal block is
 //      factored by one wavefront, which also forms its inverse; the
-//      panel below it is L_ik = A_ik L_kk^{-T}; the trailing lower triangle
-//      takes A_ij -= L_ik L_jk^T;
+//      panel below it is L_ik = A_ik L_kk^{-T}; block columns go in pairs,
+//      the second taking the first's update alone, then the trailing lower
+//      triangle takes A_ij -= L_i,[k,k+1] L_j,[k,k+1]^T (K = 128);
 //   3. W = L^{-1} on the identity, block row by block row: W_i = L_ii^{-1} W_i
-//      over the tiles left of the diagonal, then W_j -= L_ji W_i below;
+//      over the tiles left of the diagonal, then W_j -= L_ji W_i below, rows
+//      likewise in pairs (K = 128 for the rows below a pair);
 //   4. X = B_r^{-1} = W^T W (into the buffer that held L), lower block
 //      triangle, then mirrored;
 //   5. H[l][bus] = b_l (X[f][bus] - X[t][bus]) on the kept buses.
@@ -194,18 +196,30 @@ __global__ __launch_bounds__(256) void panel_kernel(double *__restrict__ A, int 
   store16x64(tile, N, acc, 0);
 }
 
-// Trailing update of the lower triangle: A_ij -= L_i,kb L_j,kb^T, i >= j > kb.
-__global__ __launch_bounds__(256) void update_kernel(double *__restrict__ A, int N, int kb) {
-  const long long p = blockIdx.x;
-  int ii = (int)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
-  while ((long long)(ii + 1) * (ii + 2) / 2 <= p) ++ii;
-  while ((long long)ii * (ii + 1) / 2 > p) --ii;
-  const int jj = (int)(p - (long long)ii * (ii + 1) / 2);
-  const int i = kb + 1 + ii, j = kb + 1 + jj, m0 = (threadIdx.x >> 6) * 16;
+// Trailing update by nk panels (block columns kb .. kb + nk - 1, K = 64 nk):
+// A_ij -= L_i,[kb..] L_j,[kb..]^T over the lower triangle i >= j >= kb + nk;
+// with col_only, the tiles (i, kb + 1) for i > kb instead (nk = 1).
+__global__ __launch_bounds__(256) void update_kernel(double *__restrict__ A, int N, int kb, int nk,
+                                                     int col_only) {
+  int i, j;
+  if (col_only) {
+    i = kb + 1 + (int)blockIdx.x;
+    j = kb + 1;
+  } else {
+    const long long p = blockIdx.x;
+    int ii = (int)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while ((long long)(ii + 1) * (ii + 2) / 2 <= p) ++ii;
+    while ((long long)ii * (ii + 1) / 2 > p) --ii;
+    const int jj = (int)(p - (long long)ii * (ii + 1) / 2);
+    i = kb + nk + ii;
+    j = kb + nk + jj;
+  }
+  const int m0 = (threadIdx.x >> 6) * 16;
   const double *Li = A + (size_t)i * kT * N + (size_t)kb * kT;
   const double *Lj = A + (size_t)j * kT * N + (size_t)kb * kT;
   f64x4 acc[4] = {};
-  mma16x64<kT>(Li + (size_t)m0 * N, N, 1, Lj, 1, N, 0, kT, acc);
+  for (int q = 0; q < nk; ++q)
+    mma16x64<kT>(Li + (size_t)m0 * N + q * kT, N, 1, Lj + q * kT, 1, N, 0, kT, acc);
   store16x64(A + (size_t)i * kT * N + (size_t)j * kT, N, acc, 1);
 }
 
@@ -227,16 +241,19 @@ __global__ __launch_bounds__(256) void trsm_scale_kernel(double *__restrict__ W,
   store16x64(tile, N, acc, 0);
 }
 
-// W_j,c -= L_j,i W_i,c for j > i, c <= i.
+// By nk block rows (i .. i + nk - 1, K = 64 nk): W_j,c -= L_j,[i..] W_[i..],c
+// for j >= i + nk, c < i + nk (the grid's first (i + nk) tiles are row i + nk).
 __global__ __launch_bounds__(256) void trsm_update_kernel(const double *__restrict__ L,
                                                           double *__restrict__ W, int N,
-                                                          int i) {
-  const int j = i + 1 + blockIdx.x / (i + 1), c = blockIdx.x % (i + 1);
+                                                          int i, int nk) {
+  const int j = i + nk + blockIdx.x / (i + nk), c = blockIdx.x % (i + nk);
   const int m0 = (threadIdx.x >> 6) * 16;
   const double *Lji = L + (size_t)j * kT * N + (size_t)i * kT;
   const double *Wic = W + (size_t)i * kT * N + (size_t)c * kT;
   f64x4 acc[4] = {};
-  mma16x64<kT>(Lji + (size_t)m0 * N, N, 1, Wic, N, 1, 0, kT, acc);
+  for (int q = 0; q < nk; ++q)
+    mma16x64<kT>(Lji + (size_t)m0 * N + q * kT, N, 1, Wic + (size_t)q * kT * N, N, 1, 0, kT,
+                 acc);
   store16x64(W + (size_t)j * kT * N + (size_t)c * kT, N, acc, 1);
 }
 
@@ -354,21 +371,33 @@ extern "C" dcopf_status dcopf_ptdf(int32_t n_bus, int32_t n_line, const int32_t 
     chk(hipMemsetAsync(A, 0, NN * 8, s));
     const int g = std::min(1024, (N + 255) / 256);
     assemble_kernel<<<g, 256, 0, s>>>(dstart, dadj, df, dt, db, slack, n, N, A);
-    for (int kb = 0; kb < T; ++kb) {
+    // block columns in pairs: the second column takes the first panel's
+    // update alone, then one K = 128 update of the trailing triangle
+    for (int kb = 0; kb < T; kb += 2) {
       potrf_kernel<<<1, 64, 0, s>>>(A, N, kb, Yd, flag);
       const int R = T - kb - 1;
-      if (R > 0) {
-        panel_kernel<<<R, 256, 0, s>>>(A, N, kb, Yd);
-        update_kernel<<<(unsigned)((long long)R * (R + 1) / 2), 256, 0, s>>>(A, N, kb);
+      if (R == 0) break;
+      panel_kernel<<<R, 256, 0, s>>>(A, N, kb, Yd);
+      update_kernel<<<R, 256, 0, s>>>(A, N, kb, 1, 1);
+      potrf_kernel<<<1, 64, 0, s>>>(A, N, kb + 1, Yd, flag);
+      const int R2 = R - 1;
+      if (R2 > 0) {
+        panel_kernel<<<R2, 256, 0, s>>>(A, N, kb + 1, Yd);
+        update_kernel<<<(unsigned)((long long)R2 * (R2 + 1) / 2), 256, 0, s>>>(A, N, kb, 2, 0);
       }
     }
     chk(hipMemsetAsync(W, 0, NN * 8, s));
     identity_kernel<<<g, 256, 0, s>>>(W, N);
-    for (int i = 0; i < T; ++i) {
+    // block rows in pairs: row i + 1 takes row i's update alone, then one
+    // K = 128 update of the rows below
+    for (int i = 0; i < T; i += 2) {
       trsm_scale_kernel<<<i + 1, 256, 0, s>>>(W, N, i, Yd);
-      if (i + 1 < T)
-        trsm_update_kernel<<<(unsigned)((long long)(T - i - 1) * (i + 1)), 256, 0, s>>>(A, W, N,
-                                                                                         i);
+      if (i + 1 == T) break;
+      trsm_update_kernel<<<i + 1, 256, 0, s>>>(A, W, N, i, 1);
+      trsm_scale_kernel<<<i + 2, 256, 0, s>>>(W, N, i + 1, Yd);
+      const int R = T - i - 2;
+      if (R > 0)
+        trsm_update_kernel<<<(unsigned)((long long)R * (i + 2)), 256, 0, s>>>(A, W, N, i, 2);
     }
     xprod_kernel<<<(unsigned)((long long)T * (T + 1) / 2), 256, 0, s>>>(W, N, A);
     mirror_kernel<<<dim3((unsigned)(N / 32), (unsigned)(N / 32)), 256, 0, s>>>(A, N);

@@ -119,21 +119,53 @@ def predict(model: "_abi.MLP", X, sx: Standardizer, st: Standardizer, n_line, ba
     return Yh[:, -1], mp, mm
 
 
+def fold_standardizers(params, sx: Standardizer, st: Standardizer):
+    """Parameters of the same network acting on raw loads and returning raw
+    multipliers: the input standardisation folded into the first layer
+    (W1 / std_x per input, b1 - W1 (mean_x / std_x)) and the output one into
+    the last (std_y W3 per output, std_y b3 + mean_y)."""
+    W1, b1, W2, b2, W3, b3 = [np.asarray(p, np.float64) for p in params]
+    W1f = W1 / sx.std[None, :]
+    b1f = b1 - W1 @ (sx.mean / sx.std)
+    W3f = st.std[:, None] * W3
+    b3f = st.std * b3 + st.mean
+    return [a.astype(np.float32) for a in (W1f, b1f, W2, b2, W3f, b3f)]
+
+
+def predict_dev(model: "_abi.MLP", X, batch=256):
+    """Raw warm-start rows [N, 2 n_line + 1] = [mu+, mu-, lambda] on the
+    device (a torch tensor) for raw load vectors X [N, n_bus] (host), from a
+    model whose parameters carry the folded standardisations."""
+    import torch
+    N = X.shape[0]
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    Y = torch.empty((N, model.dims[-1]), dtype=torch.float32, device="cuda")
+    for s in range(0, N, batch):
+        n = min(batch, N - s)
+        model.forward(Xd[s:s + n].data_ptr(), n, Y[s:s + n].data_ptr())
+    torch.cuda.synchronize()
+    return Y
+
+
 def run_to_gap(base, D, opt, alpha, rho, start=None, max_iters=5000, check_every=10,
                probe_at=100, stream=None, stats=None):
-    """Batched solve of the scenarios D (cold, or from start = (lam, mu+, mu-)).
+    """Batched solve of the scenarios D (cold; from start = (lam, mu+, mu-)
+    on the host; or from a device tensor start of rows [mu+, mu-, lambda]).
     Returns (iteration of the first exact bound within 0.1 % of opt per
     instance, -1 if none; exact bound at iteration probe_at).  If ``stats``
-    is a dict it receives the iterations run and their wall time."""
+    is a dict it receives the iterations run and their wall time, the start
+    hand-off included."""
     C = np.tile(base.c, (D.shape[0], 1))
     net = _abi.BatchNetwork(base, D, C, None, alpha=alpha, rho=rho)
     with _abi.BatchSolver([net], stream=stream, graph_iters=10, gamma_cap=1) as b:
-        if start is not None:
+        t0 = time.perf_counter()
+        if isinstance(start, tuple):
             b.set_multipliers(0, *start)
+        elif start is not None:
+            b.set_start_dev(0, start.data_ptr(), start.shape[1])
         hit = np.full(D.shape[0], -1, np.int64)
         probe = None
         it = 0
-        t0 = time.perf_counter()
         vals = b.bound()
         hit[(opt - vals) <= 1e-3 * np.abs(opt)] = 0
         while it < max_iters and np.any(hit < 0):

@@ -53,12 +53,22 @@ def test_warm_start_gains_over_cold_start():
         losses = W.train(model, X, Y, epochs=15, batch=256, lr=1e-3,
                          log=lambda s: print("[warm]", s, flush=True))
         assert losses[-1] < 0.5 * losses[0]
-        start = W.predict(model, Dev, sx, st, base.n_line)
-    print("[warm] optima", flush=True)
-    opt = highs_optima(net, base, Dev)
-    keep = np.isfinite(opt)
-    Dev, opt = Dev[keep], opt[keep]
-    start = tuple(a[keep] for a in start)
+        start_host = W.predict(model, Dev, sx, st, base.n_line)
+        # the standardisations folded into the weights: raw loads in, raw
+        # multipliers out, handed over on the device
+        model.set_params(W.fold_standardizers(model.get_params(), sx, st))
+        print("[warm] optima", flush=True)
+        opt = highs_optima(net, base, Dev)
+        keep = np.isfinite(opt)
+        Dev, opt = Dev[keep], opt[keep]
+        start = W.predict_dev(model, Dev)
+    lam_h, mp_h, mm_h = (a[keep] for a in start_host)
+    Yh = start.cpu().numpy().astype(np.float64)
+    nl = base.n_line
+    scale = np.abs(mp_h).max() + np.abs(mm_h).max() + 1.0
+    # same network up to the BF16 rounding of the folded weights
+    assert np.abs(np.maximum(Yh[:, :nl], 0) - mp_h).max() <= 3e-2 * scale
+    assert np.abs(Yh[:, -1] - lam_h).max() <= 3e-2 * (np.abs(lam_h).max() + 1.0)
     hc, pc = W.run_to_gap(base, Dev, opt, r["alpha"], r["rho"], None, 5000, 10, 100)
     hw, pw = W.run_to_gap(base, Dev, opt, r["alpha"], r["rho"], start, 5000, 10, 100)
     hf, used = W.combine_with_fallback(hc, pc, hw, pw, 100)
@@ -68,3 +78,38 @@ def test_warm_start_gains_over_cold_start():
     assert mf < mc
     # the fallback never does worse than cold at the probe
     assert np.all(np.maximum(pw, pc) >= pc)
+
+
+def test_device_start_equals_host_start():
+    """set_start_dev on a device array equals set_multipliers on the same
+    values (projected onto mu >= 0) bit for bit along the trajectory."""
+    import torch
+
+    from paper_2406_13191_amd import _abi
+    _, base = synth.make_network("geo300", 7)
+    r = synth.STEP_RULES["geo300"]
+    B, nl = 6, base.n_line
+    Dm, Cc, _ = synth.make_scenarios(base, 9900, B, 0.1, 0.1)
+    rng = np.random.default_rng(3)
+    Y = rng.normal(0.0, 3.0, (B, 2 * nl + 1)).astype(np.float32)
+    Y[:, -1] = rng.uniform(20, 60, B).astype(np.float32)
+    Yd = torch.tensor(Y, device="cuda")
+    out = []
+    for dev in (False, True):
+        net = _abi.BatchNetwork(base, Dm, Cc, None, alpha=r["alpha"], rho=r["rho"])
+        with _abi.BatchSolver([net]) as b:
+            if dev:
+                b.set_start_dev(0, Yd.data_ptr(), Yd.shape[1])
+            else:
+                Y64 = Y.astype(np.float64)
+                b.set_multipliers(0, Y64[:, -1], np.maximum(Y64[:, :nl], 0),
+                                  np.maximum(Y64[:, nl:2 * nl], 0))
+            b.step(50)
+            out.append(b.gammas(0, 50))
+    np.testing.assert_array_equal(out[0], out[1])
+    bad = Yd.clone()
+    bad[2, 5] = float("nan")
+    net = _abi.BatchNetwork(base, Dm, Cc, None, alpha=r["alpha"], rho=r["rho"])
+    with _abi.BatchSolver([net]) as b:
+        with pytest.raises(_abi.DcopfError):
+            b.set_start_dev(0, bad.data_ptr(), bad.shape[1])
