@@ -1,0 +1,132 @@
+"""Edge cases of the HIP paths against the FP64 oracle or a closed form:
+columns carrying more units than a wavefront has lanes (the strided unit
+loop), a batch of one instance (padded to a full tile) against the
+single-instance path, the congestion-free case where DCOPF is economic
+dispatch (lambda* by bisection, mu stays 0), and a two-bus batch with a
+single panel column."""
+import numpy as np
+import pytest
+
+from oracle import dual as D
+from paper_2406_13191_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _abi():
+    from paper_2406_13191_amd import _abi
+    return _abi
+
+
+def crowded_columns():
+    """The 300-bus network with 200 QP units on three buses (150, 30, 20)."""
+    _, p = synth.make_network("geo300", 7)
+    rng = np.random.default_rng(11)
+    gen_bus = np.array([17] * 150 + [40] * 30 + [123] * 20, np.int32)
+    pmax = rng.uniform(10.0, 60.0, gen_bus.size)
+    return p.replace(gen_bus=gen_bus, c=rng.uniform(10.0, 60.0, gen_bus.size),
+                     q=rng.uniform(0.005, 0.05, gen_bus.size), p_min=np.zeros(gen_bus.size),
+                     p_max=pmax)
+
+
+@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-9), ("fp32", 1e-5)])
+def test_units_beyond_a_wavefront_per_column(precision, rtol):
+    p = crowded_columns()
+    K = D.canonical(p)
+    n = 200
+    o = D.ascent(K, n, alpha=1e-4, rho=0.99)
+    with _abi().DualSolver(p, rule="gdm", alpha=1e-4, rho=0.99, precision=precision) as s:
+        assert s.info()["n_cols"] == 3
+        s.step(n)
+        g = s.gammas(0, n)
+        b = s.bound()
+    rel = np.abs(g - o.gammas) / np.maximum(np.abs(o.gammas), 1.0)
+    print(f"{precision}: worst relative gamma deviation {rel.max():.2e}", flush=True)
+    assert rel.max() <= rtol
+    assert b == pytest.approx(D.dual_value(K, o.state.lam, o.state.mu).g, rel=max(rtol, 1e-9))
+
+
+def test_units_beyond_a_wavefront_batched():
+    A = _abi()
+    p = crowded_columns()
+    B = 3
+    rng = np.random.default_rng(12)
+    Dm = np.tile(p.d, (B, 1)) * rng.uniform(0.9, 1.1, (B, 1))
+    Cc = np.tile(p.c, (B, 1)) * rng.uniform(0.95, 1.05, (B, p.n_gen))
+    Q = np.tile(p.q, (B, 1))
+    net = A.BatchNetwork(p, Dm, Cc, Q, alpha=1e-4, rho=0.99)
+    with A.BatchSolver([net]) as b:
+        b.step(150)
+        g = b.gammas(0, 150)
+    for i in range(B):
+        o = D.ascent(D.canonical(p.replace(d=Dm[i], c=Cc[i], q=Q[i])), 150, alpha=1e-4, rho=0.99)
+        rel = np.abs(g[:, i] - o.gammas) / np.maximum(np.abs(o.gammas), 1.0)
+        assert rel.max() <= 1e-4
+
+
+def test_batch_of_one_tracks_single_path():
+    A = _abi()
+    _, p = synth.make_network("geo300q", 7)
+    r = synth.STEP_RULES["geo300q"]
+    net = A.BatchNetwork(p, p.d[None, :], p.c[None, :], p.q[None, :], alpha=r["alpha"],
+                         rho=r["rho"])
+    with A.BatchSolver([net]) as b:
+        b.step(300)
+        gb = b.gammas(0, 300)[:, 0]
+    with A.DualSolver(p, rule="gdm", alpha=r["alpha"], rho=r["rho"], precision="fp64") as s:
+        s.step(300)
+        gs = s.gammas(0, 300)
+    rel = np.abs(gb - gs) / np.maximum(np.abs(gs), 1.0)
+    print(f"batch of one vs single path: worst relative deviation {rel.max():.2e}", flush=True)
+    assert rel.max() <= 1e-4
+
+
+def test_congestion_free_is_economic_dispatch():
+    # limits far above any flow: no line can bind, mu stays exactly 0, and the
+    # dual optimum is the economic dispatch price lambda*, found by bisection
+    # on sum_g clip((lambda - c_g) / (2 q_g), p_min, p_max) = 1^T d
+    _, p = synth.make_network("tiny30", 1)
+    rng = np.random.default_rng(13)
+    p = p.replace(q=rng.uniform(0.01, 0.05, p.n_gen), f_max=np.full(p.n_line, 1e5))
+    Dl = float(np.sum(p.d))
+
+    def supply(lam):
+        return float(np.sum(np.clip((lam - p.c) / (2 * p.q), p.p_min, p.p_max)))
+    lo, hi = 0.0, 1e4
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if supply(mid) < Dl else (lo, mid)
+    lam_star = 0.5 * (lo + hi)
+    x = np.clip((lam_star - p.c) / (2 * p.q), p.p_min, p.p_max)
+    opt = float(p.c @ x + p.q @ (x * x))
+    with _abi().DualSolver(p, rule="gdm", alpha=1e-3, rho=0.9, precision="fp64") as s:
+        s.step(3000)
+        b, lam, mp, mm = s.bound(want_multipliers=True)
+    assert np.all(mp == 0.0) and np.all(mm == 0.0)
+    assert lam == pytest.approx(lam_star, rel=1e-6)
+    assert b <= opt * (1 + 1e-12)
+    assert b == pytest.approx(opt, rel=1e-9)
+
+
+def test_two_bus_batch_single_column():
+    A = _abi()
+    net2 = synth.Network(2, np.array([0]), np.array([1]), np.array([10.0]), 0)
+    H = synth.ptdf(net2)
+    p = synth.Problem(H=H, gen_bus=np.array([0, 0], np.int32), c=np.array([30.0, 45.0]),
+                      q=np.zeros(2), p_min=np.zeros(2), p_max=np.array([40.0, 200.0]),
+                      d=np.array([0.0, 50.0]), f_max=np.array([80.0]), slack=0)
+    Dm = np.array([[0.0, 50.0], [0.0, 70.0]])
+    Cc = np.array([[30.0, 45.0], [31.0, 44.0]])
+    net = A.BatchNetwork(p, Dm, Cc, None, alpha=1e-3, rho=0.9)
+    with A.BatchSolver([net]) as b:
+        b.step(100)
+        g = b.gammas(0, 100)
+        vals = b.bound()
+    # merit order (the line, carrying the load behind it, never binds):
+    # 40 MW of the cheaper unit, the rest from the other one
+    opt = [40.0 * 30.0 + 10.0 * 45.0, 40.0 * 31.0 + 30.0 * 44.0]
+    for i in range(2):
+        K = D.canonical(p.replace(d=Dm[i], c=Cc[i]))
+        o = D.ascent(K, 100, alpha=1e-3, rho=0.9)
+        np.testing.assert_allclose(g[:, i], o.gammas, rtol=1e-6, atol=1e-6)
+        assert vals[i] <= opt[i] * (1 + 1e-12)        # weak duality
