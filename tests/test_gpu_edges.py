@@ -2,8 +2,9 @@
 columns carrying more units than a wavefront has lanes (the strided unit
 loop), a batch of one instance (padded to a full tile) against the
 single-instance path, the congestion-free case where DCOPF is economic
-dispatch (lambda* by bisection, mu stays 0), and a two-bus batch with a
-single panel column."""
+dispatch (lambda* by bisection, mu stays 0), a two-bus batch with a
+single panel column, and a panel too large for the last-level cache (the
+passes' nontemporal-load variants)."""
 import numpy as np
 import pytest
 
@@ -130,3 +131,25 @@ def test_two_bus_batch_single_column():
         o = D.ascent(K, 100, alpha=1e-3, rho=0.9)
         np.testing.assert_allclose(g[:, i], o.gammas, rtol=1e-6, atol=1e-6)
         assert vals[i] <= opt[i] * (1 + 1e-12)        # weak duality
+
+
+def test_panel_beyond_the_last_level_cache():
+    # the FP64 all-bus panel of the 4600-bus network: its two orientations
+    # (436 MB) exceed the 256 MiB last-level cache, so both passes stream it
+    # with nontemporal loads (smaller panels use plain loads)
+    _, p = synth.make_network("bus4600", 4600)
+    nl, nb = p.H.shape
+    assert 2 * nl * nb * 8 > 256 * 2 ** 20
+    r = synth.STEP_RULES["bus4600"]
+    K = D.canonical(p)
+    n = 30
+    o = D.ascent(K, n, alpha=r["alpha"], rho=r["rho"])
+    with _abi().DualSolver(p, rule="gdm", alpha=r["alpha"], rho=r["rho"], precision="fp64",
+                           panel="allbus") as s:
+        s.step(n)
+        g = s.gammas(0, n)
+        b = s.bound()
+    rel = np.abs(g - o.gammas) / np.maximum(np.abs(o.gammas), 1.0)
+    print(f"all-bus FP64 panel: worst relative gamma deviation {rel.max():.2e}", flush=True)
+    assert rel.max() <= 1e-9
+    assert b == pytest.approx(D.dual_value(K, o.state.lam, o.state.mu).g, rel=1e-9)
