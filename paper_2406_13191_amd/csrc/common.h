@@ -174,8 +174,9 @@ struct WsShared {
   int wm[256];      // working mask of rows 0..m-1
   int sidx[256];    // working rows in order, then the balance row
   double v[256];    // right-hand side / solution, then the join test
+  double col[256];  // the factor's current column (scaled)
   double red[16];
-  int ns, pick, fail;
+  int ns, pick;
 };
 
 template <int LD>
@@ -196,7 +197,6 @@ __device__ bool ws_solve(const double *G, const double *t, const int *sg, int m,
         if (sh.wm[r]) sh.sidx[ns++] = r;
       sh.sidx[ns++] = m;
       sh.ns = ns;
-      sh.fail = 0;
     }
     __syncthreads();
     const int n = sh.ns;
@@ -209,46 +209,71 @@ __device__ bool ws_solve(const double *G, const double *t, const int *sg, int m,
     dm = 0.0;
     for (int w = 0; w < nt / kWave; ++w) dm = fmax(dm, sh.red[w]);
     if (!(dm > 0.0)) return false;
-    for (int e = tid; e < n * n; e += nt) {
-      const int a = e / n, b = e % n;
-      if (b <= a) l(a, b) = gl(sh.sidx[a], sh.sidx[b]) + (a == b ? ridge * dm : 0.0);
-    }
+    // rows of the factor by thread row ty, columns by thread column tx
+    const int tx = tid & 31, ty = tid >> 5, ny = nt >> 5;
+    for (int a = ty; a < n; a += ny)
+      for (int b = tx; b <= a; b += 32)
+        l(a, b) = gl(sh.sidx[a], sh.sidx[b]) + (a == b ? ridge * dm : 0.0);
     for (int a = tid; a < n; a += nt) sh.v[a] = t[sh.sidx[a]];
     __syncthreads();
+    // right-looking Cholesky: every thread takes the pivot and its square
+    // root itself; the scaled column also goes to LDS for the update, and
+    // the pivot is stored once every thread has read it
     for (int k = 0; k < n; ++k) {
-      if (tid == 0) {
-        const double d = l(k, k);
-        if (d > 0.0)
-          l(k, k) = sqrt(d);
-        else
-          sh.fail = 1;
+      const double d = l(k, k);
+      if (!(d > 0.0)) return false;
+      const double dk = sqrt(d);
+      for (int a = k + 1 + tid; a < n; a += nt) {
+        const double q = l(a, k) / dk;
+        l(a, k) = q;
+        sh.col[a] = q;
       }
       __syncthreads();
-      if (sh.fail) return false;
-      const double dk = l(k, k);
-      for (int a = k + 1 + tid; a < n; a += nt) l(a, k) /= dk;
-      __syncthreads();
-      const int r = n - k - 1;
-      for (int idx = tid; idx < r * r; idx += nt) {
-        const int aa = idx / r, bb = idx % r;
-        if (bb <= aa) l(k + 1 + aa, k + 1 + bb) -= l(k + 1 + aa, k) * l(k + 1 + bb, k);
+      if (tid == 0) l(k, k) = dk;
+      for (int a = k + 1 + ty; a < n; a += ny) {
+        const double qa = sh.col[a];
+        for (int b = k + 1 + tx; b <= a; b += 32) l(a, b) -= qa * sh.col[b];
       }
       __syncthreads();
     }
-    for (int k = 0; k < n; ++k) {  // L z = t
-      if (tid == 0) sh.v[k] /= l(k, k);
-      __syncthreads();
-      const double vk = sh.v[k];
-      for (int a = k + 1 + tid; a < n; a += nt) sh.v[a] -= l(a, k) * vk;
-      __syncthreads();
+    // L z = t, then L^T y = z, by the first wavefront with the vector in
+    // registers (row a in slot a / 64 of lane a % 64; n <= 256)
+    if (tid < kWave) {
+      double z[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int a = q * kWave + tid;
+        z[q] = a < n ? sh.v[a] : 0.0;
+      }
+      auto pick_slot = [&](int k) {
+        const int q = k / kWave;
+        return q == 0 ? z[0] : (q == 1 ? z[1] : (q == 2 ? z[2] : z[3]));
+      };
+      for (int k = 0; k < n; ++k) {
+        const double zk = __shfl(pick_slot(k), k % kWave, kWave) / l(k, k);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int a = q * kWave + tid;
+          if (a == k) z[q] = zk;
+          else if (a > k && a < n) z[q] -= l(a, k) * zk;
+        }
+      }
+      for (int k = n - 1; k >= 0; --k) {
+        const double zk = __shfl(pick_slot(k), k % kWave, kWave) / l(k, k);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int a = q * kWave + tid;
+          if (a == k) z[q] = zk;
+          else if (a < k) z[q] -= l(k, a) * zk;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int a = q * kWave + tid;
+        if (a < n) sh.v[a] = z[q];
+      }
     }
-    for (int k = n - 1; k >= 0; --k) {  // L^T y = z
-      if (tid == 0) sh.v[k] /= l(k, k);
-      __syncthreads();
-      const double vk = sh.v[k];
-      for (int a = tid; a < k; a += nt) sh.v[a] -= l(k, a) * vk;
-      __syncthreads();
-    }
+    __syncthreads();
     for (int r = tid; r <= m; r += nt) y[r] = 0.0;
     __syncthreads();
     for (int a = tid; a < n; a += nt) y[sh.sidx[a]] = sh.v[a];
