@@ -44,6 +44,17 @@ class Standardizer:
         return a * self.std + self.mean
 
 
+def he_init(rng, dims):
+    """Initial parameters of the network with layer widths ``dims``: weights
+    [fan_out, fan_in] drawn N(0, 2 / fan_in) (He initialisation), layer by
+    layer from ``rng``, biases zero.  FP64; the caller casts."""
+    out = []
+    for fan_in, fan_out in zip(dims[:-1], dims[1:]):
+        out.append(rng.normal(0.0, np.sqrt(2.0 / fan_in), size=(fan_out, fan_in)))
+        out.append(np.zeros(fan_out))
+    return out
+
+
 def cold_solve(base, D, iters, alpha, rho, stream=None, chunk=8192, trend_window=1000):
     """Multipliers after ``iters`` cold-start GDM iterations for every load
     scenario D [B, n_bus] (batched GPU solves, chunks of ``chunk``).
