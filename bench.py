@@ -146,7 +146,9 @@ def bench_mixed(args, stream):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    ms_w, ms_u, ms_f = b.time_phases(20)
+    # per-phase durations: median of three samples of 20 iterations each
+    ms_w, ms_u, ms_f = (float(v) for v in
+                        np.median(np.array([b.time_phases(20) for _ in range(3)]), axis=0))
     tiles = [b.info(k) for k in range(len(nets))]
     b.close()
     splits = [t["w_split"] for t in tiles]
@@ -721,8 +723,10 @@ def main():
     print(f"[bench] {args.steps} iterations in {ms:.2f} ms (wall {wall*1e3:.2f} ms)",
           file=sys.stderr, flush=True)
     # per-kernel durations for the roofline: events attached to each dispatch of
-    # 200 real iterations (the iterate is restored afterwards)
-    ms_col, ms_line = s.time_phases(200)
+    # 200 real iterations (the iterate is restored afterwards), median of five
+    # such samples
+    ms_col, ms_line = (float(v) for v in
+                       np.median(np.array([s.time_phases(200) for _ in range(5)]), axis=0))
     s.close()
     b_col, b_line = panel_bytes(p.n_line, n_cols, p.n_gen)
     if ms_line >= ms_col:
