@@ -147,3 +147,34 @@ def test_weak_duality(name, seed):
         cost = float(K.c @ r.x + r.x @ (K.M * r.x))
         lam, mu = _rand_multipliers(rng, K)
         assert D.dual_value(K, lam, mu).g <= cost + 1e-9 * abs(cost)
+
+
+@pytest.mark.parametrize("qp", [False, True])
+def test_nu_form_complementary_split(qp):
+    """The dual depends on (mu+, mu-) through nu = mu+ - mu- and the limit
+    term -(mu+ + mu-)^T f_max only: moving to the complementary split
+    (max(nu, 0), max(-nu, 0)) of the same nu raises it by exactly
+    2 sum_l min(mu+_l, mu-_l) f_max_l, and leaves it unchanged when mu+ and
+    mu- are already complementary."""
+    _, p = synth.make_network("tiny30", 1)
+    if qp:
+        p = p.replace(q=np.random.default_rng(8).uniform(0.001, 0.05, p.n_gen))
+    K = D.canonical(p)
+    rng = np.random.default_rng(9)
+    nl = p.n_line
+    for _ in range(25):
+        lam = float(rng.uniform(0.0, 80.0))
+        mp = rng.exponential(3.0, nl) * (rng.random(nl) < 0.6)
+        mm = rng.exponential(3.0, nl) * (rng.random(nl) < 0.6)
+        nu = mp - mm
+        g = D.dual_value(K, lam, np.r_[mp, mm]).g
+        g_c = D.dual_value(K, lam, np.r_[np.maximum(nu, 0.0), np.maximum(-nu, 0.0)]).g
+        gain = 2.0 * float(np.sum(np.minimum(mp, mm) * p.f_max))
+        assert g <= g_c + 1e-9 * max(1.0, abs(g_c))
+        assert g_c - g == pytest.approx(gain, rel=1e-9, abs=1e-6 * max(1.0, abs(g)))
+        # already complementary: mu- zeroed wherever mu+ is positive
+        mm0 = np.where(mp > 0, 0.0, mm)
+        g0 = D.dual_value(K, lam, np.r_[mp, mm0]).g
+        nu0 = mp - mm0
+        g0_c = D.dual_value(K, lam, np.r_[np.maximum(nu0, 0.0), np.maximum(-nu0, 0.0)]).g
+        assert g0_c == pytest.approx(g0, rel=1e-12, abs=1e-9)
