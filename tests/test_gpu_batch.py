@@ -101,7 +101,7 @@ def one_step_parity(specs, rule="gdm", tol_rel=1e-5):
             b.set_multipliers(k, np.array(lams), np.array(mps), np.array(mms))
             states.append((Ks, lams, mps, mms))
         b.step(1)
-        worst = 0.0
+        worst = worst_lam = 0.0
         for k, (Ks, lams, mps, mms) in enumerate(states):
             lam_g, mp_g, mm_g = b.get_multipliers(k)
             alpha, rho = nets[k].alpha, nets[k].rho
@@ -118,6 +118,7 @@ def one_step_parity(specs, rule="gdm", tol_rel=1e-5):
                 scale = max(np.abs(st1.mu).max(), floor)
                 err = max(np.abs(mp_g[i] - st1.mu[:nl]).max(), np.abs(mm_g[i] - st1.mu[nl:]).max())
                 worst = max(worst, err / scale)
+                worst_lam = max(worst_lam, abs(lam_g[i] - st1.lam) / max(abs(st1.lam), floor))
                 assert err <= tol_rel * scale, (k, i, err, scale)
                 assert abs(lam_g[i] - st1.lam) <= tol_rel * max(abs(st1.lam), floor)
                 if rule == "gdm":
@@ -136,7 +137,8 @@ def one_step_parity(specs, rule="gdm", tol_rel=1e-5):
                              + 4 * U32 * (np.abs(st.mu[:nl]) + np.abs(st1.mu[:nl]) + alpha * g)
                              + 1e-12)
                     assert np.all(np.abs(mp_g[i] - st1.mu[:nl]) <= bound)
-        print(f"worst mu error / scale: {worst:.3e}", flush=True)
+        print(f"worst mu error / scale: {worst:.3e}, worst lambda error / scale: "
+              f"{worst_lam:.3e}", flush=True)
 
 
 def test_one_step_mixed_small():
@@ -158,6 +160,8 @@ def test_exact_bound_matches_oracle():
     for i in range(len(vals)):
         K = D.canonical(inst(base, Dm, Cc, Q, i))
         g = D.dual_value(K, lam[i], np.concatenate([mp[i], mm[i]])).g
+        print(f"batch exact bound, instance {i}: rel err {abs(vals[i] - g) / abs(g):.1e}",
+              flush=True)
         assert abs(vals[i] - g) <= 1e-7 * abs(g)
         assert abs(vals[i] - g) <= 1e-11 * abs(g), (i, vals[i], g)
 

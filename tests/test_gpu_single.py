@@ -128,7 +128,14 @@ def test_one_step_fp64(name, rule_key, panel):
         s.set_state(to_buf(st, rule, K.n_line))
         s.step(1)
         compare_state(s, st1, rule, K.n_line, rtol=1e-10, atol_mu=1e-11)
+        got = s.split_state(s.get_state())
         g = s.gammas(st.t, 1)[0]
+        nl = K.n_line
+        mu_err = max(np.abs(got["mu_p"] - st1.mu[:nl]).max(), np.abs(got["mu_m"] - st1.mu[nl:]).max())
+        print(f"fp64 {name} {rule_key} {panel}: mu err / max mu "
+              f"{mu_err / max(np.abs(st1.mu).max(), 1e-300):.1e}, lambda rel err "
+              f"{abs(got['lam'] - st1.lam) / max(abs(st1.lam), 1e-300):.1e}, gamma rel err "
+              f"{abs(g - ev.g) / abs(ev.g):.1e}", flush=True)
         assert g == pytest.approx(ev.g, rel=1e-12)
 
 
@@ -158,8 +165,11 @@ def test_one_step_fp32(name, rule_key):
     floor = 1e-3 * K.c.max()
     tol_a17 = 1e-5 * max(np.abs(st1.mu).max(), floor)
     err = max(np.abs(got["mu_p"] - st1.mu[:nl]).max(), np.abs(got["mu_m"] - st1.mu[nl:]).max())
+    lam_err = abs(got["lam"] - st1.lam)
+    print(f"fp32 {name} {rule_key}: mu err / scale {err / max(np.abs(st1.mu).max(), floor):.1e}, "
+          f"lambda err / scale {lam_err / max(abs(st1.lam), floor):.1e}", flush=True)
     assert err <= tol_a17, (err, tol_a17)
-    assert abs(got["lam"] - st1.lam) <= 1e-5 * max(abs(st1.lam), floor)
+    assert lam_err <= 1e-5 * max(abs(st1.lam), floor)
     if rule_key == "gdm":
         # line residual error: FP32 F = P x with ~n_cols/64 sequential terms
         x = ev.x
@@ -191,6 +201,8 @@ def test_exact_bound_matches_oracle(name):
         with solver_for(p, "gdm", prec, name=name) as s:
             s.set_state(to_buf(st, "gdm", K.n_line))
             v, lam, mp, mm = s.bound(want_multipliers=True)
+        print(f"exact bound {name} ({prec} loop): rel err {abs(v - g_ref) / abs(g_ref):.1e}",
+              flush=True)
         assert abs(v - g_ref) <= 1e-7 * abs(g_ref), (v, g_ref)
         assert abs(v - g_ref) <= 1e-11 * abs(g_ref)
         np.testing.assert_array_equal(mp, st.mu[:K.n_line])
