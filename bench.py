@@ -385,6 +385,9 @@ def bench_warmstart(args, stream):
                                   r["rho"], stream.cuda_stream)
     cost_ub = float(np.sum(np.maximum(base.c * base.p_min, base.c * base.p_max)))
     ok = W.settled(tb, te, cost_ub) & np.all(np.isfinite(T), axis=1)
+    if not ok.any():
+        sys.exit("no training scenario passed the settled test: --target-iters must exceed "
+                 "the 1000-iteration trend window by enough for the bounds to settle")
     log(f"targets: {ok.sum()} of {ok.size} scenarios kept, {t_data:.1f} s")
     Dtr, T = Dtr[ok], T[ok]
     sx, st = W.Standardizer.fit(Dtr), W.Standardizer.fit(T)
