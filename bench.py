@@ -588,8 +588,9 @@ def main():
                          "earlier run's config) to pin instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the single-instance path does not shard "
-              "across GPUs (see the sharding note in the design document).", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs on one device (batched "
+              "instances would split across GPUs with no per-iteration exchange; one large "
+              "instance would need an all-reduce of Pt v per iteration).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
