@@ -44,3 +44,24 @@ def test_he_init_matches_oracle_draws():
     # N(0, 2 / fan_in): the sample variance of a wide layer is close to it
     w = W.he_init(np.random.default_rng(1), (4000, 500))[0]
     assert w.var() == pytest.approx(2.0 / 4000, rel=0.02)
+
+
+def test_traffic_lookup_follows_source_hash():
+    """roofline.traffic comes from the counter table only while the kernel's
+    sources hash to the value recorded with the counters."""
+    import json
+    import re
+    with open(bench.TRAFFIC_FILE) as f:
+        table = json.loads(re.search(r"```json\n(.*?)\n```", f.read(), re.S).group(1))
+    key = "bus2000/genbus:colpass"
+    files = ("paper_2406_13191_amd/csrc/common.h", "paper_2406_13191_amd/csrc/single.hip")
+    e, cal = table["kernels"][key], table["copy_calibration"]
+    if e["source_sha256"] == bench.source_sha(files):
+        expected = round(e["fetch_kib"] * 1024 * cal["fetch_scale"]
+                         + e["write_kib"] * 1024 * cal["write_scale"])
+        assert bench.measured_traffic(key, files) == expected
+    else:
+        assert bench.measured_traffic(key, files) is None
+    # another source set or an unknown kernel never matches
+    assert bench.measured_traffic(key, ("paper_2406_13191_amd/csrc/batch.hip",)) is None
+    assert bench.measured_traffic("no-such-kernel", files) is None
