@@ -1,11 +1,16 @@
 """Benchmark of the projected dual ascent (instance-iterations/s and time to a
 bound within 0.1 % of the FP64 optimum) on one MI355X.
 
-Workload: the 2000-bus single instance (3200 lines, 540 generators on 478
-distinct buses, linear costs), FP32 PTDF products with FP64 state, gradient
-with momentum.  A step is one ascent iteration (reduced costs, inner
-minimiser, residuals, step + projection).  Inputs are resident in HBM before
-the timed region; the iteration loop is replayed as captured HIP graphs.
+Default workload: the mixed batch, 512 load/cost scenarios of a 4600-bus
+network, 128 of a 2000-bus network and 32 of a 10,000-bus network with
+quadratic costs, advanced together (split-BF16 MFMA products, FP32 line
+state, FP64 lambda and exact bound).  A step is one ascent iteration of
+every instance (reduced costs, inner minimiser, residuals, step +
+projection).  Inputs are resident in HBM before the timed region; the
+iteration loop is replayed as captured HIP graphs.  Other workloads
+(--workload): a single instance (bus2000, bus4600, bus10000), the learned
+warm start, the PTDF build, step rules, the iterated-s QP dual, and the
+device-copy calibration of the traffic counters.
 """
 import argparse
 import hashlib
@@ -107,9 +112,87 @@ def cpu_baseline(p, alpha, rho, budget_s=15.0):
 MIXED = [("bus4600", 4600, 512, 46_000_000), ("bus2000", 2000, 128, 20_000_000),
          ("bus10000", 10000, 32, 100_000_000)]
 BF16_PEAK_TFLOPS = 2500.0
+TTB_CHECK = 100
 
 
-def bench_mixed(args, stream):
+def _make_net(spec):
+    from paper_2406_13191_amd import synth
+    name, seed = spec
+    t = time.perf_counter()
+    net, prob = synth.make_network(name, seed)
+    return net, prob, time.perf_counter() - t
+
+
+def _pool(n):
+    import multiprocessing as mp
+    return mp.get_context("spawn").Pool(n)
+
+
+def _finish(pool):
+    """Let the workers exit by themselves (no SIGTERM from terminate())."""
+    pool.close()
+    pool.join()
+
+
+def prep_mixed(log):
+    """Host-side inputs of the mixed batch, before any GPU call: the three
+    networks (generated in parallel), every instance's load and cost
+    scenario, and the HiGHS optimum of every LP instance (reference leg of
+    the time to bound).  The QP network's instances get their target from a
+    certified upper bound later."""
+    import numpy as np
+
+    from paper_2406_13191_amd import synth
+    t0 = time.perf_counter()
+    with _pool(len(MIXED)) as pool:
+        made = pool.map(_make_net, [(n, s) for n, s, _, _ in MIXED])
+        _finish(pool)
+    for (name, *_), (_, _, dt) in zip(MIXED, made):
+        log(f"network {name}: {dt:.1f} s")
+    nets = []
+    jobs, owner = [], []
+    for k, ((name, seed, B, seed0), (topo, base, _)) in enumerate(zip(MIXED, made)):
+        Dm, Cc, Q = synth.make_scenarios(base, seed0, B, 0.1, 0.1)
+        nets.append(dict(name=name, topo=topo, base=base, D=Dm, C=Cc, Q=Q, B=B,
+                         n_cols=int(len(np.unique(base.gen_bus)))))
+        if not base.is_qp:
+            light = base.replace(H=None)
+            for i in range(B):
+                jobs.append((topo, light.replace(d=Dm[i], c=Cc[i])))
+                owner.append((k, i))
+    log(f"HiGHS optima for {len(jobs)} LP instances")
+    with _pool(16) as pool:
+        opts = pool.map(_highs_opt, jobs, chunksize=8)
+        _finish(pool)
+    for n in nets:
+        n["opt"] = np.full(n["B"], np.nan)
+    for (k, i), o in zip(owner, opts):
+        nets[k]["opt"][i] = o
+    log(f"host inputs ready in {time.perf_counter() - t0:.1f} s")
+    return nets
+
+
+def _batch_networks(nets):
+    from paper_2406_13191_amd import _abi, synth
+    out = []
+    for n in nets:
+        r = synth.STEP_RULES[n["name"]]
+        out.append(_abi.BatchNetwork(n["base"], n["D"], n["C"],
+                                     n["Q"] if n["base"].is_qp else None,
+                                     alpha=r["alpha"], rho=r["rho"]))
+    return out
+
+
+def _solver(stream, bnets, tiles):
+    from paper_2406_13191_amd import _abi
+    b = _abi.BatchSolver(bnets, stream=stream.cuda_stream, autotune=False, graph_iters=20,
+                         gamma_cap=64)
+    for k, t in enumerate(tiles):
+        b.set_tiles(k, t["w_tile"], t["w_split"], t["f_tile"])
+    return b
+
+
+def bench_mixed(args, stream, nets, log):
     """The mixed batch: 512 scenarios of the 4600-bus network, 128 of the
     2000-bus and 32 of the 10000-bus (QP) network in one batched launch per
     phase, split-BF16 products, autotuned tiles, HIP-graph replay."""
@@ -117,22 +200,13 @@ def bench_mixed(args, stream):
     import torch
 
     from paper_2406_13191_amd import _abi, synth
-    nets, shapes, bases, topos = [], [], [], []
-    for name, seed, B, seed0 in MIXED:
-        t = time.perf_counter()
-        topo, base = synth.make_network(name, seed)
-        bases.append(base)
-        topos.append(topo)
-        print(f"[bench] network {name}: {time.perf_counter() - t:.1f} s", file=sys.stderr,
-              flush=True)
-        Dm, Cc, Q = synth.make_scenarios(base, seed0, B, 0.1, 0.1)
-        r = synth.STEP_RULES[name]
-        nets.append(_abi.BatchNetwork(base, Dm, Cc, Q if base.is_qp else None,
-                                      alpha=r["alpha"], rho=r["rho"]))
-        shapes.append((name, base.n_line, len(np.unique(base.gen_bus)), base.n_gen, B))
+    bnets = _batch_networks(nets)
+    shapes = [(n["name"], n["base"].n_line, n["n_cols"], n["base"].n_gen, n["B"]) for n in nets]
     pinned = json.loads(args.tiles) if args.tiles else None
-    b = _abi.BatchSolver(nets, stream=stream.cuda_stream, autotune=pinned is None,
+    t0 = time.perf_counter()
+    b = _abi.BatchSolver(bnets, stream=stream.cuda_stream, autotune=pinned is None,
                          graph_iters=20, gamma_cap=64)
+    t_create = time.perf_counter() - t0
     if pinned:
         for k, t in enumerate(pinned):
             b.set_tiles(k, t["w_tile"], t["w_split"], t["f_tile"])
@@ -146,27 +220,29 @@ def bench_mixed(args, stream):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    # per-phase durations: median of three samples of 20 iterations each
+    log(f"{args.steps} iterations of {n_total} instances in {ms:.3f} ms")
+    # per-phase durations: median of three samples of 20 iterations each,
+    # events attached to each dispatch on the batch's stream
     ms_w, ms_u, ms_f = (float(v) for v in
                         np.median(np.array([b.time_phases(20) for _ in range(3)]), axis=0))
-    tiles = [b.info(k) for k in range(len(nets))]
+    tiles = [b.info(k) for k in range(len(bnets))]
     b.close()
-    splits = [t["w_split"] for t in tiles]
-    bw, bu, bf = batch_phase_bytes(shapes, splits)
+    bw, bu, bf = batch_phase_bytes(shapes, [t["w_split"] for t in tiles])
     # the same instances one at a time on the single-instance path (FP32
     # products): seconds for one iteration of all of them, against the batch
     single = {}
-    for (name, nl, nc, ng, B), base in zip(shapes, bases):
-        r = synth.STEP_RULES[name]
-        with _abi.DualSolver(base, stream=stream.cuda_stream, rule="gdm", alpha=r["alpha"],
-                             rho=r["rho"], precision="fp32", graph_iters=100) as s1:
+    for n in nets:
+        r = synth.STEP_RULES[n["name"]]
+        with _abi.DualSolver(n["base"], stream=stream.cuda_stream, rule="gdm",
+                             alpha=r["alpha"], rho=r["rho"], precision="fp32",
+                             graph_iters=100) as s1:
             s1.step(200)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             s1.step(2000)
             torch.cuda.synchronize()
-            single[name] = 2000 / (time.perf_counter() - t0)
-    t_single = sum(B / single[name] for name, nl, nc, ng, B in shapes)
+            single[n["name"]] = 2000 / (time.perf_counter() - t0)
+    t_single = sum(n["B"] / single[n["name"]] for n in nets)
     t_batch = ms / args.steps / 1e3
     phases = {"w": ("W product (W^T = V^T P, split-BF16 MFMA)", ms_w, bw),
               "units": ("unit pass (reduced costs, inner minimiser, lambda step)", ms_u, bu),
@@ -176,13 +252,15 @@ def bench_mixed(args, stream):
     achieved = kbytes / (kms * 1e-3) / 1e9
     useful = sum(2.0 * nl * nc * B for _, nl, nc, ng, B in shapes)  # one product
     issued = 3 * useful  # three split-BF16 terms
-    mfma_tflops = 2 * issued / ((ms_w + ms_f) * 1e-3) / 1e12
-    ttb = None if args.no_cpu else batch_time_to_bound(args, stream, nets, shapes, bases,
-                                                       topos, tiles)
-    cert = batch_certified(stream, nets, shapes, tiles)
+    mfma_issued = 2 * issued / ((ms_w + ms_f) * 1e-3) / 1e12
+    mfma_useful = 2 * useful / ((ms_w + ms_f) * 1e-3) / 1e12
+    iter_bytes = bw + bu + bf
+    cert = batch_certified(stream, bnets, nets, tiles, log)
+    ttb = batch_time_to_bound(args, stream, bnets, nets, tiles, cert["upper_bounds"], log)
     return dict(
         value=n_total * args.steps / (ms / 1e3), ms=ms, n_total=n_total, time_to_bound=ttb,
-        certified=cert,
+        certified={k: v for k, v in cert.items() if k != "upper_bounds"},
+        create_seconds=round(t_create, 3),
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                       unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
                       traffic=measured_traffic("mixed:" + key, BATCH_SRC), kernel=kname,
@@ -191,10 +269,17 @@ def bench_mixed(args, stream):
                       phase_bytes={k: int(v[2]) for k, v in phases.items()},
                       phase_gbs={k: round(v[2] / (v[1] * 1e-3) / 1e9, 1)
                                  for k, v in phases.items()},
-                      mfma=dict(issued_flops_per_product=issued,
-                                achieved_tflops=round(mfma_tflops, 2),
+                      phase_traffic={k: measured_traffic("mixed:" + k, BATCH_SRC)
+                                     for k in phases},
+                      iteration=dict(bytes=int(iter_bytes), us=round(t_batch * 1e6, 2),
+                                     gbs=round(iter_bytes / t_batch / 1e9, 1),
+                                     frac=round(iter_bytes / t_batch / 1e9 / HBM_PEAK_GBS, 4)),
+                      mfma=dict(issued_flops_per_product=issued, useful_flops_per_product=useful,
+                                issued_tflops=round(mfma_issued, 2),
+                                useful_tflops=round(mfma_useful, 2),
                                 peak_tflops=BF16_PEAK_TFLOPS,
-                                frac=round(mfma_tflops / BF16_PEAK_TFLOPS, 4))),
+                                issued_frac=round(mfma_issued / BF16_PEAK_TFLOPS, 4),
+                                useful_frac=round(mfma_useful / BF16_PEAK_TFLOPS, 4))),
         shapes=shapes, tiles=tiles,
         single_path=dict(rates={k: round(v, 1) for k, v in single.items()},
                          unit="instance-iterations/s",
@@ -203,20 +288,17 @@ def bench_mixed(args, stream):
                          speedup=round(t_single / t_batch, 1)))
 
 
-def batch_certified(stream, nets, shapes, tiles, n_iters=10000):
+def batch_certified(stream, bnets, nets, tiles, log, n_iters=10000):
     """Certified gaps of every instance with no external solver: n_iters
     iterations with each instance's exact bound checked every 100 and its
     inner minimisers averaged over the second half, then every network's
     averages repaired into feasible dispatches (a scenario with no feasible
-    dispatch stays unrepaired); gap = (repaired cost - best bound) / cost."""
+    dispatch stays unrepaired); gap = (repaired cost - best bound) / cost.
+    The repaired costs are upper bounds on each instance's optimum."""
     import numpy as np
     import torch
 
-    from paper_2406_13191_amd import _abi
-    b = _abi.BatchSolver(nets, stream=stream.cuda_stream, autotune=False, graph_iters=20,
-                         gamma_cap=64)
-    for k, t in enumerate(tiles):
-        b.set_tiles(k, t["w_tile"], t["w_split"], t["f_tile"])
+    b = _solver(stream, bnets, tiles)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(0, n_iters, 100):
@@ -227,88 +309,128 @@ def batch_certified(stream, nets, shapes, tiles, n_iters=10000):
     best, _ = b.best()
     t_iter = time.perf_counter() - t0
     t0 = time.perf_counter()
-    reps = [b.repair(k, max_rounds=64) for k in range(len(nets))]
+    reps = [b.repair(k, max_rounds=64) for k in range(len(bnets))]
     t_rep = time.perf_counter() - t0
     b.close()
-    offs = np.cumsum([0] + [sh[4] for sh in shapes])
-    per = {}
-    for k, (name, nl, nc, ng, B) in enumerate(shapes):
+    offs = np.cumsum([0] + [n["B"] for n in nets])
+    per, ub = {}, []
+    for k, n in enumerate(nets):
         r = reps[k]
         ok = r["feasible"]
+        ub.append(np.where(ok, r["cost"], np.nan))
         gap = (r["cost"] - best[offs[k]:offs[k + 1]]) / np.abs(r["cost"])
         g = gap[ok]
-        per[name] = dict(instances=int(B), repaired=int(ok.sum()),
-                         median_gap=float(np.median(g)) if g.size else None,
-                         max_gap=float(g.max()) if g.size else None,
-                         within_1e_3=int((g <= 1e-3).sum()), within_1e_4=int((g <= 1e-4).sum()),
-                         max_rounds=int(r["rounds"][ok].max()) if g.size else None,
-                         max_lines_held=int(r["n_active"][ok].max()) if g.size else None)
-        print(f"[bench] certified {name}: {int(ok.sum())}/{B} repaired, median gap "
-              f"{per[name]['median_gap']:.2e}, max {per[name]['max_gap']:.2e}",
-              file=sys.stderr, flush=True)
+        per[n["name"]] = dict(instances=int(n["B"]), repaired=int(ok.sum()),
+                              median_gap=float(np.median(g)) if g.size else None,
+                              max_gap=float(g.max()) if g.size else None,
+                              within_1e_3=int((g <= 1e-3).sum()),
+                              within_1e_4=int((g <= 1e-4).sum()),
+                              max_rounds=int(r["rounds"][ok].max()) if g.size else None,
+                              max_lines_held=int(r["n_active"][ok].max()) if g.size else None)
+        log(f"certified {n['name']}: {int(ok.sum())}/{n['B']} repaired, median gap "
+            f"{per[n['name']]['median_gap']:.2e}")
     return dict(iterations=n_iters, average_from=n_iters // 2, check_every=100,
                 seconds_iterations=round(t_iter, 3), seconds_repair=round(t_rep, 3),
-                per_network=per)
+                per_network=per, upper_bounds=ub)
 
 
-def batch_time_to_bound(args, stream, nets, shapes, bases, topos, tiles):
-    """Iterations and wall time until every LP instance of the batch has an
-    exact bound within 0.1 % of its HiGHS optimum (reference leg; the QP
-    network has no such optimum and only keeps the batch company).  Bounds
-    are checked every 100 iterations."""
-    import multiprocessing as mp
-
+def batch_time_to_bound(args, stream, bnets, nets, tiles, ub, log):
+    """Iterations and wall time until every instance's exact bound is within
+    0.1 % of its target, checked every TTB_CHECK iterations, with an
+    iteration cap of its own (--ttb-cap).  Targets: the HiGHS optimum of an
+    LP instance (the FP64 optimum); for a QP instance (no QP solver here)
+    the certified upper bound of its repaired average, which is at least the
+    optimum, so reaching it certifies a 0.1 % gap.  Instances with neither
+    (no feasible dispatch) have no target."""
     import numpy as np
     import torch
 
-    from paper_2406_13191_amd import _abi, synth
-    jobs, owner = [], []
-    for k, ((name, nl, nc, ng, B), base) in enumerate(zip(shapes, bases)):
-        if base.is_qp:
-            continue
-        net = topos[k]
-        seed0 = [s0 for n, _, _, s0 in MIXED if n == name][0]
-        Dm, Cc, Q = synth.make_scenarios(base, seed0, B, 0.1, 0.1)
-        for i in range(B):
-            jobs.append((net, base.replace(d=Dm[i], c=Cc[i])))
-            owner.append((k, i))
-    print(f"[bench] HiGHS optima for {len(jobs)} LP instances", file=sys.stderr, flush=True)
-    with mp.get_context("spawn").Pool(16) as pool:
-        opts = pool.map(_highs_opt, jobs, chunksize=8)
-    offs = np.cumsum([0] + [s[4] for s in shapes])
-    opt = np.full(int(offs[-1]), np.nan)
-    for (k, i), o in zip(owner, opts):
-        opt[offs[k] + i] = o
-    lp = np.isfinite(opt)
-    b = _abi.BatchSolver(nets, stream=stream.cuda_stream, autotune=False, graph_iters=20,
-                         gamma_cap=64)
-    for k, t in enumerate(tiles):
-        b.set_tiles(k, t["w_tile"], t["w_split"], t["f_tile"])
-    hit = np.full(opt.size, -1, np.int64)
+    offs = np.cumsum([0] + [n["B"] for n in nets])
+    target = np.full(int(offs[-1]), np.nan)
+    kind = []
+    for k, n in enumerate(nets):
+        target[offs[k]:offs[k + 1]] = ub[k] if n["base"].is_qp else n["opt"]
+        kind.append("certified upper bound" if n["base"].is_qp else "HiGHS optimum")
+    has = np.isfinite(target)
+    b = _solver(stream, bnets, tiles)
+    hit = np.full(target.size, -1, np.int64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     it, t_all = 0, None
-    while it < 20000:
-        b.step(100)
-        it += 100
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    dev_ms = 0.0
+    while it < args.ttb_cap:
+        e0.record(stream)
+        b.step(TTB_CHECK)
+        e1.record(stream)
+        it += TTB_CHECK
         vals = b.bound()
-        newly = lp & (hit < 0) & (opt - vals <= 1e-3 * np.abs(opt))
+        dev_ms += e0.elapsed_time(e1)
+        newly = has & (hit < 0) & (target - vals <= 1e-3 * np.abs(target))
         hit[newly] = it
-        if np.all(hit[lp] >= 0):
+        if np.all(hit[has] >= 0):
             t_all = time.perf_counter() - t0
             break
     b.close()
     per = {}
-    for k, (name, nl, nc, ng, B) in enumerate(shapes):
-        h = hit[offs[k]:offs[k + 1]][lp[offs[k]:offs[k + 1]]]
+    for k, n in enumerate(nets):
+        h = hit[offs[k]:offs[k + 1]][has[offs[k]:offs[k + 1]]]
         if h.size:
-            per[name] = dict(instances=int(h.size), median_iterations=float(np.median(
-                np.where(h >= 0, h, 20000))), max_iterations=int(h.max()) if np.all(h >= 0)
-                else None, reached=float((h >= 0).mean()))
-    return dict(lp_instances=int(lp.sum()), check_every=100, all_reached=t_all is not None,
-                iterations_all=it if t_all is not None else None,
-                seconds_all=None if t_all is None else round(t_all, 4), per_network=per,
-                note="wall time of the whole batch (672 instances) including bound checks")
+            per[n["name"]] = dict(target=kind[k], instances=int(h.size),
+                                  median_iterations=float(np.median(
+                                      np.where(h >= 0, h, args.ttb_cap))),
+                                  max_iterations=int(h.max()) if np.all(h >= 0) else None,
+                                  reached=float((h >= 0).mean()))
+    log(f"time to bound: {'all reached at %d iterations' % it if t_all else 'not all reached'}")
+    return dict(reached=t_all is not None, instances_with_target=int(has.sum()),
+                instances=int(target.size), check_every=TTB_CHECK, iteration_cap=args.ttb_cap,
+                iterations=it if t_all is not None else None,
+                seconds=None if t_all is None else round(t_all, 4),
+                device_seconds_iterations=round(dev_ms / 1e3, 4), per_network=per,
+                note="wall time of the whole batch (every instance advancing together) "
+                     "including the exact-bound checks and their read-back")
+
+
+def cpu_baseline_batch(nets, budget_s=15.0):
+    """The FP64 oracle run as batched GEMMs over the same instances (every
+    instance of every network, oracle.batch.ascent_batch), timed on a
+    bounded number of iterations that fills about budget_s seconds; then the
+    same with one BLAS thread on a shorter sample."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import batch as OB
+    from paper_2406_13191_amd import synth
+    KBs = []
+    for n in nets:
+        r = synth.STEP_RULES[n["name"]]
+        KBs.append((OB.canonical_batch(n["base"], n["D"], n["C"],
+                                       n["Q"] if n["base"].is_qp else None),
+                    r["alpha"], r["rho"]))
+    n_inst = sum(n["B"] for n in nets)
+
+    def run(iters):
+        t = time.perf_counter()
+        for KB, a, rho in KBs:
+            OB.ascent_batch(KB, iters, alpha=a, rho=rho)
+        return time.perf_counter() - t
+
+    per = run(2) / 2
+    n = int(max(3, min(2000, budget_s / per)))
+    dt = run(n)
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    with threadpool_limits(limits=1):
+        n1 = max(2, n // 8)
+        dt1 = run(n1)
+    return dict(value=n_inst * n / dt, unit="instance-iterations/s", cores=int(threads),
+                kind="oracle",
+                sample=f"{n} FP64 GDM iterations of all {n_inst} instances of the mixed batch "
+                       f"(oracle.batch: numpy FP64 GEMMs over each network's instances, "
+                       f"{threads} BLAS threads), {dt:.1f} s",
+                seconds_per_iteration=dt / n,
+                value_one_thread=n_inst * n1 / dt1,
+                sample_one_thread=f"{n1} iterations, {dt1:.1f} s")
 
 
 def batch_phase_bytes(shapes, splits):
@@ -363,23 +485,41 @@ def _highs_opt(args):
     return _lp_optimum(net, prob)
 
 
-def bench_warmstart(args, stream):
+def prep_warmstart(args, log):
+    """Host-side inputs of the warm-start workload, before any GPU call: the
+    2000-bus network, training and held-out load scenarios, and the HiGHS
+    optimum of every held-out scenario (reference leg)."""
+    import numpy as np
+
+    from paper_2406_13191_amd import synth
+    net, base = synth.make_network("bus2000", 2000)
+    Dtr, _, _ = synth.make_scenarios(base, 5_000_000, args.train, 0.15, 0.0)
+    Dev, _, _ = synth.make_scenarios(base, 6_000_000, args.eval, 0.15, 0.0)
+    light = base.replace(H=None)
+    opt = []
+    with _pool(16) as pool:
+        for o in pool.imap(_highs_opt, [(net, light.replace(d=Dev[i]))
+                                        for i in range(Dev.shape[0])], chunksize=16):
+            opt.append(o)
+            if len(opt) % 512 == 0:
+                log(f"HiGHS optima: {len(opt)} of {Dev.shape[0]}")
+        _finish(pool)
+    return net, base, Dtr, Dev, np.array(opt)
+
+
+def bench_warmstart(args, stream, prep):
     """Learned warm start on the 2000-bus network: training scenarios with
     per-bus load multipliers exp(N(0, 0.15^2)), targets from cold batched
     solves, training with the library's kernels, evaluation on held-out
     scenarios against HiGHS optima (reference leg) with the cold fallback."""
-    import multiprocessing as mp
-
     import numpy as np
     import torch
 
     from paper_2406_13191_amd import _abi, synth
     from paper_2406_13191_amd import warmstart as W
     log = lambda m: print("[warm]", m, file=sys.stderr, flush=True)  # noqa: E731
-    net, base = synth.make_network("bus2000", 2000)
+    net, base, Dtr, Dev, opt = prep
     r = synth.STEP_RULES["bus2000"]
-    Dtr, _, _ = synth.make_scenarios(base, 5_000_000, args.train, 0.15, 0.0)
-    Dev, _, _ = synth.make_scenarios(base, 6_000_000, args.eval, 0.15, 0.0)
     log(f"targets: {args.train} cold solves of {args.target_iters} iterations")
     (T, tb, te), t_data = W.timed(W.cold_solve, base, Dtr, args.target_iters, r["alpha"],
                                   r["rho"], stream.cuda_stream)
@@ -403,14 +543,6 @@ def bench_warmstart(args, stream):
     # the first and last layers, raw loads in, raw multipliers out, handed to
     # the batch on the device
     model.set_params(W.fold_standardizers(model.get_params(), sx, st))
-    opt = []
-    with mp.get_context("spawn").Pool(16) as pool:
-        for o in pool.imap(_highs_opt, [(net, base.replace(d=Dev[i]))
-                                        for i in range(Dev.shape[0])], chunksize=16):
-            opt.append(o)
-            if len(opt) % 512 == 0:
-                log(f"HiGHS optima: {len(opt)} of {Dev.shape[0]}")
-    opt = np.array(opt)
     keep = np.isfinite(opt)
     Dev, opt = Dev[keep], opt[keep]
     torch.cuda.synchronize()
@@ -570,14 +702,136 @@ def bench_qpdual(args, stream):
     return out
 
 
+def bench_single(args, stream, name, net, p, steps, warmup, log, with_cpu=True,
+                 with_primal=True):
+    """One instance on the single-instance path, FP32 products: iteration
+    rate over `steps` iterations replayed as HIP graphs, the dominant
+    kernel's roofline, time to a bound within 0.1 % (own iteration cap),
+    setup time, and optionally primal recovery and the FP64 oracle."""
+    import numpy as np
+    import torch
+
+    from paper_2406_13191_amd import _abi, synth
+    r = synth.STEP_RULES[name]
+    n_cols = len(np.unique(p.gen_bus))
+    kw = dict(rule="gdm", alpha=r["alpha"], rho=r["rho"], precision="fp32", panel=args.panel,
+              graph_iters=100)
+    if args.panel == "allbus":
+        n_cols = p.n_bus
+    # setup (reported apart from the iterations): copy of H to the device,
+    # panel gather in both orientations, f_d = H d.  The first create of a
+    # process also loads the library's kernels, so the second one is timed.
+    setup = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t_s = time.perf_counter()
+        s = _abi.DualSolver(p, stream=stream.cuda_stream, **kw)
+        torch.cuda.synchronize()
+        setup.append(time.perf_counter() - t_s)
+        if len(setup) == 1:
+            s.close()
+    s.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    log(f"{name}: {steps} iterations in {ms:.2f} ms (wall {wall*1e3:.2f} ms)")
+    # per-kernel durations for the roofline: events attached to each dispatch of
+    # 200 real iterations (the iterate is restored afterwards), median of five
+    # such samples
+    ms_col, ms_line = (float(v) for v in
+                       np.median(np.array([s.time_phases(200) for _ in range(5)]), axis=0))
+    s.close()
+    b_col, b_line = panel_bytes(p.n_line, n_cols, p.n_gen)
+    if ms_line >= ms_col:
+        kkey, kname, kms, kbytes = "linepass", "linepass (F = P x - f_d, mu step)", ms_line, b_line
+    else:
+        kkey, kname, kms, kbytes = "colpass", "colpass (w = P^T v, inner minimiser)", ms_col, b_col
+    achieved = kbytes / (kms * 1e-3) / 1e9
+    traffic = measured_traffic(f"{name}/{args.panel}:{kkey}", SINGLE_SRC)
+    it_bytes = b_col + b_line
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=kname,
+                    kernel_ms=round(kms, 5), bytes_per_launch=int(kbytes),
+                    other_kernel_ms=round(min(ms_col, ms_line), 5),
+                    iteration=dict(bytes=int(it_bytes), us=round(ms / steps * 1e3, 3),
+                                   gbs=round(it_bytes / (ms / steps * 1e-3) / 1e9, 1)))
+
+    # time to a bound within 0.1 % of the FP64 optimum (HiGHS reference for
+    # an LP), with an iteration cap of its own
+    ttb = primal = cpu = None
+    if not p.is_qp:
+        opt = _lp_optimum(net, p)
+        with _abi.DualSolver(p, stream=stream.cuda_stream, **kw) as s2:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = s2.solve(opt=opt, gap_tol=1e-3, max_iters=args.ttb_cap, check_every=100)
+            dt = time.perf_counter() - t0
+        ttb = dict(reached=res["status"] == 1, iterations=int(res["iter_of_bound"]),
+                   iteration_cap=args.ttb_cap, seconds=round(dt, 5), gap=res["gap"],
+                   check_every=100, target="HiGHS optimum",
+                   device_seconds=round(res["iter_of_bound"] * ms / steps / 1e3, 6))
+    if with_primal:
+        # primal recovery: the average of p* over iterations 2000..10000 (exact
+        # bound checked every 100), then its repair into a feasible dispatch,
+        # whose cost certifies the gap of the best bound without HiGHS
+        with _abi.DualSolver(p, stream=stream.cuda_stream, **kw) as s3:
+            s3.step(2000)
+            s3.average(True)
+            s3.solve(opt=float("nan"), gap_tol=0.0, max_iters=8000, check_every=100)
+            lb, _ = s3.best()
+            pr = s3.primal()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rp = s3.repair(None)
+            t_rep = time.perf_counter() - t0
+        opt = None if p.is_qp else _lp_optimum(net, p)
+        primal = dict(window=[2000, 10000], cost=pr["cost"], best_lower_bound=lb,
+                      gap_to_opt=None if p.is_qp else (pr["cost"] - opt) / abs(opt),
+                      balance_mw=pr["balance"], max_overload_mw=pr["max_overload"],
+                      overloaded_directions=pr["n_overloaded"],
+                      repair=dict(feasible=rp["feasible"], cost=rp["cost"], rounds=rp["rounds"],
+                                  lines_held=rp["n_active"], max_shift_mw=rp["max_shift"],
+                                  seconds=round(t_rep, 5),
+                                  certified_gap=(rp["cost"] - lb) / abs(rp["cost"])
+                                  if rp["feasible"] else None,
+                                  ub_minus_opt=None if p.is_qp else (rp["cost"] - opt) / abs(opt)))
+    if with_cpu:
+        cpu = cpu_baseline(p, r["alpha"], r["rho"])
+    desc = (f"{name} single instance: {p.n_bus} buses, {p.n_line} lines, {p.n_gen} generators "
+            f"on {n_cols} buses, {'quadratic' if p.is_qp else 'linear'} costs; "
+            f"{'full-PTDF' if args.panel == 'allbus' else 'generator-bus'} panel; FP32 PTDF "
+            f"products, FP64 multipliers and bound; gradient with momentum "
+            f"alpha={r['alpha']}, rho={r['rho']}")
+    return dict(value=steps / (ms / 1e3), ms=ms, steps=steps, warmup=warmup, workload=desc,
+                time_to_bound=ttb, setup_seconds=round(setup[1], 5),
+                setup_note="dcopf_dual_create on the host-resident problem: H "
+                           f"({p.n_line} x {p.n_bus} FP64) copied to the device, panel "
+                           "gathered in both orientations, f_d = H d; first create "
+                           f"(kernel loading included) {setup[0]:.4f} s",
+                primal_recovery=primal, roofline=roofline, cpu_baseline=cpu)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed iterations (default 2000 for the mixed batch, 20000 for a "
+                         "single instance)")
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="bus2000")
+    ap.add_argument("--workload", default="mixed",
+                    help="mixed (default) | bus2000 | bus4600 | bus10000 | warmstart | ptdf | "
+                         "rules | qpdual | copy")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--panel", default="genbus", choices=["genbus", "allbus"])
+    ap.add_argument("--ttb-cap", type=int, default=20000,
+                    help="iteration cap of the time-to-bound legs (independent of --steps)")
     ap.add_argument("--train", type=int, default=50000)
     ap.add_argument("--eval", type=int, default=4096)
     ap.add_argument("--epochs", type=int, default=20)
@@ -592,11 +846,19 @@ def main():
               "instances would split across GPUs with no per-iteration exchange; one large "
               "instance would need an all-reduce of Pt v per iteration).", file=sys.stderr)
         sys.exit(2)
+    if args.steps is None:
+        args.steps = 2000 if args.workload == "mixed" else 20000
+    log = lambda m: print("[bench]", m, file=sys.stderr, flush=True)  # noqa: E731
 
     import numpy as np
     import torch
 
-    from paper_2406_13191_amd import _abi, synth
+    # host-side inputs of the default workload first: nothing below this
+    # point forks or spawns processes once the GPU is in use
+    nets = prep_mixed(log) if args.workload == "mixed" else None
+    wprep = prep_warmstart(args, log) if args.workload == "warmstart" else None
+
+    from paper_2406_13191_amd import _abi, synth  # noqa: F401  (loads the library)
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
@@ -604,7 +866,7 @@ def main():
         copy_calibration()
         return
     if args.workload == "warmstart":
-        r = bench_warmstart(args, stream)
+        r = bench_warmstart(args, stream, wprep)
         out = {
             "metric": "median iterations to a bound within 0.1% of the FP64 optimum, "
                       "learned warm start vs cold start",
@@ -684,7 +946,20 @@ def main():
         print(json.dumps(out), flush=True)
         return
     if args.workload == "mixed":
-        r = bench_mixed(args, stream)
+        r = bench_mixed(args, stream, nets, log)
+        # the 2000-bus single instance (the batch's 2000-bus network, its
+        # base loads and costs) on the single-instance path, for reference
+        n2 = [n for n in nets if n["name"] == "bus2000"][0]
+        single = bench_single(args, stream, "bus2000", n2["topo"], n2["base"], 2000, 200, log,
+                              with_cpu=False, with_primal=False)
+        cpu = None
+        if not args.no_cpu:
+            cpu = cpu_baseline_batch(nets)
+            ttb = r["time_to_bound"]
+            if ttb["reached"]:
+                cpu["seconds_for_the_gpu_iterations_to_bound"] = round(
+                    ttb["iterations"] * cpu["seconds_per_iteration"], 2)
+            log(f"cpu baseline: {cpu['value']:.0f} instance-iterations/s ({cpu['cores']} threads)")
         out = {
             "metric": METRIC, "value": round(r["value"], 1), "unit": "instance-iterations/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -692,129 +967,34 @@ def main():
             "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
             "config": {"workload": "mixed batch: " + ", ".join(
                 f"{B} x {n} ({nl} lines, {nc} generator buses)" for n, nl, nc, ng, B in r["shapes"])
-                + "; split-BF16 MFMA products, FP32 line state, FP64 lambda and bound; GDM",
+                + "; split-BF16 MFMA products (hi*hi + hi*lo + lo*hi, FP32 accumulation), FP32 "
+                  "line state, FP64 lambda and exact bound; gradient with momentum",
                 "instances": r["n_total"], "tiles": r["tiles"],
+                "create_seconds": r["create_seconds"],
+                "time_to_bound": r["time_to_bound"],
                 "vs_single_instance_path": r["single_path"],
-                "time_to_bound": r["time_to_bound"], "certified": r["certified"]},
-            "roofline": r["roofline"], "cpu_baseline": None,
+                "single_instance_bus2000": single,
+                "certified": r["certified"]},
+            "roofline": r["roofline"], "cpu_baseline": cpu,
         }
         print(json.dumps(out), flush=True)
         return
     t = time.perf_counter()
     net, p = synth.make_network(args.workload, {"bus2000": 2000, "bus4600": 4600,
                                                 "bus10000": 10000}[args.workload])
-    print(f"[bench] network {args.workload}: {time.perf_counter() - t:.1f} s", file=sys.stderr,
-          flush=True)
-    r = synth.STEP_RULES[args.workload]
-    n_cols = len(np.unique(p.gen_bus))
-    kw = dict(rule="gdm", alpha=r["alpha"], rho=r["rho"], precision="fp32", panel=args.panel,
-              graph_iters=100)
-    if args.panel == "allbus":
-        n_cols = p.n_bus
-    # setup (reported apart from the iterations): copy of H to the device,
-    # panel gather in both orientations, f_d = H d.  The first create also
-    # loads the library's kernels, so the second one is timed.
-    setup = []
-    for _ in range(2):
-        torch.cuda.synchronize()
-        t_s = time.perf_counter()
-        s = _abi.DualSolver(p, stream=stream.cuda_stream, **kw)
-        torch.cuda.synchronize()
-        setup.append(time.perf_counter() - t_s)
-        if len(setup) == 1:
-            s.close()
-    s.step(args.warmup)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    s.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    value = args.steps / (ms / 1e3)
-    print(f"[bench] {args.steps} iterations in {ms:.2f} ms (wall {wall*1e3:.2f} ms)",
-          file=sys.stderr, flush=True)
-    # per-kernel durations for the roofline: events attached to each dispatch of
-    # 200 real iterations (the iterate is restored afterwards), median of five
-    # such samples
-    ms_col, ms_line = (float(v) for v in
-                       np.median(np.array([s.time_phases(200) for _ in range(5)]), axis=0))
-    s.close()
-    b_col, b_line = panel_bytes(p.n_line, n_cols, p.n_gen)
-    if ms_line >= ms_col:
-        kkey, kname, kms, kbytes = "linepass", "linepass (F = P x - f_d, mu step)", ms_line, b_line
-    else:
-        kkey, kname, kms, kbytes = "colpass", "colpass (w = P^T v, inner minimiser)", ms_col, b_col
-    achieved = kbytes / (kms * 1e-3) / 1e9
-    traffic = measured_traffic(f"{args.workload}/{args.panel}:{kkey}", SINGLE_SRC)
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=kname,
-                    kernel_ms=round(kms, 5), bytes_per_launch=int(kbytes),
-                    other_kernel_ms=round(min(ms_col, ms_line), 5))
-
-    # time to a bound within 0.1 % of the FP64 optimum (HiGHS reference)
-    ttb = None
-    cpu = None
-    primal = None
-    if not args.no_cpu:
-        opt = _lp_optimum(net, p) if not p.is_qp else float("nan")
-        with _abi.DualSolver(p, stream=stream.cuda_stream, **kw) as s2:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            res = s2.solve(opt=opt, gap_tol=1e-3, max_iters=args.steps, check_every=100)
-            dt = time.perf_counter() - t0
-        ttb = None if p.is_qp else dict(reached=res["status"] == 1, iterations=int(res["iter_of_bound"]),
-                   seconds=round(dt, 5), gap=res["gap"], check_every=100,
-                   device_seconds=round(res["iter_of_bound"] * ms / args.steps / 1e3, 6))
-        # primal recovery: the average of p* over iterations 2000..10000 (exact
-        # bound checked every 100), then its repair into a feasible dispatch,
-        # whose cost certifies the gap of the best bound without HiGHS
-        with _abi.DualSolver(p, stream=stream.cuda_stream, **kw) as s3:
-            s3.step(2000)
-            s3.average(True)
-            s3.solve(opt=float("nan"), gap_tol=0.0, max_iters=8000, check_every=100)
-            lb, _ = s3.best()
-            pr = s3.primal()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rp = s3.repair(None)
-            t_rep = time.perf_counter() - t0
-        primal = dict(window=[2000, 10000], cost=pr["cost"], best_lower_bound=lb,
-                      gap_to_opt=None if p.is_qp else (pr["cost"] - opt) / abs(opt),
-                      balance_mw=pr["balance"], max_overload_mw=pr["max_overload"],
-                      overloaded_directions=pr["n_overloaded"],
-                      repair=dict(feasible=rp["feasible"], cost=rp["cost"], rounds=rp["rounds"],
-                                  lines_held=rp["n_active"], max_shift_mw=rp["max_shift"],
-                                  seconds=round(t_rep, 5),
-                                  certified_gap=(rp["cost"] - lb) / abs(rp["cost"])
-                                  if rp["feasible"] else None,
-                                  ub_minus_opt=None if p.is_qp else (rp["cost"] - opt) / abs(opt)))
-        cpu = cpu_baseline(p, r["alpha"], r["rho"])
-
+    log(f"network {args.workload}: {time.perf_counter() - t:.1f} s")
+    r = bench_single(args, stream, args.workload, net, p, args.steps, args.warmup, log,
+                     with_cpu=not args.no_cpu, with_primal=not args.no_cpu)
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "instance-iterations/s",
+        "metric": METRIC, "value": round(r["value"], 1), "unit": "instance-iterations/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": r["ms"] / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{args.workload} single instance: {p.n_bus} buses, "
-                               f"{p.n_line} lines, {p.n_gen} generators on {n_cols} buses, "
-                               f"{'quadratic' if p.is_qp else 'linear'} costs; "
-                               f"{'full-PTDF' if args.panel == 'allbus' else 'generator-bus'} "
-                               f"panel; FP32 PTDF "
-                               f"products, FP64 multipliers and bound; gradient with "
-                               f"momentum alpha={r['alpha']}, rho={r['rho']}",
-                   "iterations": args.steps, "time_to_bound": ttb,
-                   "setup_seconds": round(setup[1], 5),
-                   "setup_note": "dcopf_dual_create on the host-resident problem: H "
-                                 f"({p.n_line} x {p.n_bus} FP64) copied to the device, panel "
-                                 "gathered in both orientations, f_d = H d; first create "
-                                 f"(kernel loading included) {setup[0]:.4f} s",
-                   "primal_recovery": primal},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
+        "config": {"workload": r["workload"], "iterations": args.steps,
+                   "time_to_bound": r["time_to_bound"], "setup_seconds": r["setup_seconds"],
+                   "setup_note": r["setup_note"], "primal_recovery": r["primal_recovery"]},
+        "roofline": r["roofline"],
+        "cpu_baseline": r["cpu_baseline"],
     }
     print(json.dumps(out), flush=True)
 

@@ -107,6 +107,29 @@ dcopf_status dcopf_batch_get_multipliers(dcopf_batch_t b, int32_t net, double *l
 dcopf_status dcopf_batch_set_multipliers(dcopf_batch_t b, int32_t net, const double *lambda,
                                          const double *mu_plus, const double *mu_minus);
 
+/* Whole ascent state of network `net` (checkpoint / resume, or a start that
+ * carries optimiser state; Section 3.3's rules keep a velocity or first
+ * moment and a second moment per multiplier).  Host doubles, length
+ * dcopf_batch_state_len(b, net) = 1 + 3 n_inst + 6 n_inst n_line:
+ *   [0]                      iteration counter k (shared by every network of
+ *                            the batch: it drives step decay and Adam's bias
+ *                            correction)
+ *   [1 .. 1+n_inst)          lambda per instance
+ *   then n_inst each         lambda's velocity (GDM) or first moment (Adam),
+ *                            lambda's second moment (Adam, AdaGrad)
+ *   then n_inst x n_line     each of mu+, mu-, their velocities / first
+ *                            moments, their second moments (instance-major)
+ * The line state is stored in FP32: set_state rounds it to nearest.
+ * set_state: mu and second moments >= 0, every value finite, k a
+ * nonnegative integer, else DCOPF_E_INVALID (nothing changed); a length
+ * other than state_len is DCOPF_E_STATE.  It sets the batch's counter to k
+ * (the other networks keep their iterates and optimiser state) and restarts
+ * this network's best bounds.  state_len returns 0 for a bad handle or
+ * network.  Synchronise.                                                  */
+size_t dcopf_batch_state_len(dcopf_batch_t b, int32_t net);
+dcopf_status dcopf_batch_get_state(dcopf_batch_t b, int32_t net, double *buf, size_t len);
+dcopf_status dcopf_batch_set_state(dcopf_batch_t b, int32_t net, const double *buf, size_t len);
+
 /* Primal recovery (an extension, as dcopf_dual_average / dcopf_dual_primal):
  * enable = 1 restarts the average of every instance's inner minimiser p*
  * over the following iterations (including those of time_phases, which

@@ -117,6 +117,19 @@ def dual_value(K: Canonical, lam: float, mu: np.ndarray) -> DualEval:
     return DualEval(g=g, x=x, a=a, grad_lam=grad_lam, grad_mu=grad_mu)
 
 
+def dual_value_at(K: Canonical, lam: float, mu: np.ndarray, x: np.ndarray) -> DualEval:
+    """The Lagrangian (eq. lagrangian) and the constraint residuals at a given
+    point x of the box, in the form of ``dual_value``.  At any minimiser x of
+    the Lagrangian over the box this is G(lambda, mu) with a supergradient:
+    where a linear unit's reduced cost is zero every point of its interval is
+    a minimiser, and each choice gives another valid supergradient."""
+    x = np.asarray(x, dtype=np.float64)
+    lam_v = np.array([lam], dtype=np.float64)
+    a = K.c + K.A.T @ lam_v + K.C.T @ mu
+    g = float(x @ (K.M * x) + a @ x - lam_v @ K.b - mu @ K.d)
+    return DualEval(g=g, x=x, a=a, grad_lam=float((K.A @ x - K.b)[0]), grad_mu=K.C @ x - K.d)
+
+
 def split_mu(mu):
     n = mu.shape[0] // 2
     return mu[:n], mu[n:]
@@ -264,18 +277,30 @@ class AscentResult:
     n_avg: int = 0                   # number of terms in x_sum
 
 
+def step_size(alpha: float, decay: float, t: int) -> float:
+    """Step size of the update that follows t earlier updates.  The paper
+    names step decay among the options of its ascent (Section 3.3) and uses
+    it in its experiments (Section 4) without giving the schedule; the
+    reading here is alpha_t = alpha / (1 + decay t), so decay = 0 is the
+    constant step of Algorithm 1."""
+    return alpha / (1.0 + decay * t)
+
+
 def ascent(K: Canonical, n_iters: int, rule: str = "gdm", alpha: float = 1e-3,
            rho: float = 0.9, beta1: float = 0.9, beta2: float = 0.999,
            eps: float = 1e-8, literal: bool = False, tol: float = 0.0,
            state: AscentState | None = None,
-           average_from: int | None = None) -> AscentResult:
+           average_from: int | None = None, decay: float = 0.0) -> AscentResult:
     """Projected dual ascent (Section 3.3, Algorithm 1) for ``n_iters`` updates.
 
     Iteration k evaluates the dual and its supergradient at the current
-    iterate (gamma_k), then updates.  With tol > 0 the loop stops when
-    |gamma_k - gamma_{k-1}| < tol (the stopping test of Algorithm 1).
-    With average_from = k0 the inner minimisers p*_k of the iterations
-    k0 <= k < n_iters are summed (primal recovery, ``primal_eval``).
+    iterate (gamma_k), then updates with the step size
+    ``step_size(alpha, decay, t)``, t being the number of updates the state
+    has taken (its counter, which a given ``state`` carries).  With tol > 0
+    the loop stops when |gamma_k - gamma_{k-1}| < tol (the stopping test of
+    Algorithm 1).  With average_from = k0 the inner minimisers p*_k of the
+    iterations k0 <= k < n_iters are summed (primal recovery,
+    ``primal_eval``).
     """
     st = AscentState.cold(K.n_line) if state is None else state.copy()
     gam = []
@@ -292,12 +317,13 @@ def ascent(K: Canonical, n_iters: int, rule: str = "gdm", alpha: float = 1e-3,
         if tol > 0 and k > 0 and abs(gam[-1] - gam[-2]) < tol:
             stopped = True
             break
+        a_t = step_size(alpha, decay, st.t)
         if rule == "gdm":
-            st = gdm_update(st, ev, alpha, rho, literal)
+            st = gdm_update(st, ev, a_t, rho, literal)
         elif rule == "adam":
-            st = adam_update(st, ev, alpha, beta1, beta2, eps)
+            st = adam_update(st, ev, a_t, beta1, beta2, eps)
         elif rule == "adagrad":
-            st = adagrad_update(st, ev, alpha, eps)
+            st = adagrad_update(st, ev, a_t, eps)
         else:
             raise ValueError(rule)
         it += 1

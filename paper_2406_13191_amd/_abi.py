@@ -302,6 +302,9 @@ def _bind_batch():
         "dcopf_batch_create": (C.c_int, [P(BatchNet_C), C.c_int32, P(BatchOpts_C), C.c_void_p,
                                          P(C.c_void_p)]),
         "dcopf_batch_step": (C.c_int, [C.c_void_p, C.c_int64]),
+        "dcopf_batch_state_len": (C.c_size_t, [C.c_void_p, C.c_int32]),
+        "dcopf_batch_get_state": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double), C.c_size_t]),
+        "dcopf_batch_set_state": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double), C.c_size_t]),
         "dcopf_batch_bound": (C.c_int, [C.c_void_p, P(C.c_double)]),
         "dcopf_batch_best": (C.c_int, [C.c_void_p, P(C.c_double), P(C.c_int64)]),
         "dcopf_batch_solve": (C.c_int, [C.c_void_p, P(C.c_double), C.c_double, C.c_int64,
@@ -429,6 +432,35 @@ class BatchSolver:
         lam, mu_p, mu_m = _f64(lam), _f64(mu_p), _f64(mu_m)
         check(lib.dcopf_batch_set_multipliers(self._h, int(net), _dptr(lam), _dptr(mu_p),
                                               _dptr(mu_m)))
+
+    def get_state(self, net: int) -> np.ndarray:
+        """Network `net`'s whole ascent state (dcopf_batch_get_state layout)."""
+        buf = np.empty(lib.dcopf_batch_state_len(self._h, int(net)))
+        check(lib.dcopf_batch_get_state(self._h, int(net), _dptr(buf), buf.size))
+        return buf
+
+    def set_state(self, net: int, buf):
+        buf = _f64(buf)
+        check(lib.dcopf_batch_set_state(self._h, int(net), _dptr(buf), buf.size))
+
+    def split_state(self, net: int, buf) -> dict:
+        """The fields of a state buffer: k, lam, v_lam, s_lam [B] and mu_p,
+        mu_m, v_p, v_m, s_p, s_m [B, n_line]."""
+        n = self.networks[net]
+        B, nl = n.B, np.asarray(n.base.f_max).size
+        out = dict(k=int(buf[0]), lam=buf[1:1 + B], v_lam=buf[1 + B:1 + 2 * B],
+                   s_lam=buf[1 + 2 * B:1 + 3 * B])
+        o = 1 + 3 * B
+        for name in ("mu_p", "mu_m", "v_p", "v_m", "s_p", "s_m"):
+            out[name] = buf[o:o + B * nl].reshape(B, nl)
+            o += B * nl
+        return out
+
+    @staticmethod
+    def pack_state(k, lam, v_lam, s_lam, mu_p, mu_m, v_p, v_m, s_p, s_m) -> np.ndarray:
+        """Inverse of split_state."""
+        parts = [[float(k)], lam, v_lam, s_lam, mu_p, mu_m, v_p, v_m, s_p, s_m]
+        return np.concatenate([np.ravel(np.asarray(x, dtype=np.float64)) for x in parts])
 
     def set_start_dev(self, net: int, y_ptr: int, ld: int):
         """Start multipliers from a device FP32 array [n_inst, ld] laid out

@@ -1966,6 +1966,81 @@ dcopf_status dcopf_batch_set_multipliers(dcopf_batch_t b, int32_t net, const dou
   return DCOPF_OK;
 }
 
+size_t dcopf_batch_state_len(dcopf_batch_t b, int32_t net) {
+  if (!b || net < 0 || net >= (int)b->nets.size()) return 0;
+  const BNet &N = b->nets[net].d;
+  return 1 + 3 * (size_t)N.B + 6 * (size_t)N.B * N.n_l;
+}
+
+dcopf_status dcopf_batch_get_state(dcopf_batch_t b, int32_t net, double *buf, size_t len) {
+  if (!b || net < 0 || net >= (int)b->nets.size() || !buf)
+    return set_error("bad arguments"), DCOPF_E_INVALID;
+  if (len != dcopf_batch_state_len(b, net)) return set_error("state length mismatch"), DCOPF_E_STATE;
+  DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
+  const BNet &N = b->nets[net].d;
+  const size_t B = N.B, nl = N.n_l;
+  buf[0] = (double)b->iters;
+  // after a step call the state of iteration `iters` sits in slot iters & 1
+  const size_t slot = (size_t)(b->iters & 1) * B;
+  const double *d8[] = {N.lam, N.vlam, N.slam};
+  for (int a = 0; a < 3; ++a)
+    DCOPF_HIP_TRY(hipMemcpy(buf + 1 + a * B, d8[a] + slot, B * 8, hipMemcpyDeviceToHost));
+  std::vector<float> tmp(B * N.ldl);
+  const float *f4[] = {N.mu_p, N.mu_m, N.v_p, N.v_m, N.s_p, N.s_m};
+  double *out = buf + 1 + 3 * B;
+  for (int a = 0; a < 6; ++a, out += B * nl) {
+    DCOPF_HIP_TRY(hipMemcpy(tmp.data(), f4[a], tmp.size() * 4, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < B; ++i)
+      for (size_t l = 0; l < nl; ++l) out[i * nl + l] = tmp[i * N.ldl + l];
+  }
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_set_state(dcopf_batch_t b, int32_t net, const double *buf, size_t len) {
+  if (!b || net < 0 || net >= (int)b->nets.size() || !buf)
+    return set_error("bad arguments"), DCOPF_E_INVALID;
+  if (len != dcopf_batch_state_len(b, net)) return set_error("state length mismatch"), DCOPF_E_STATE;
+  if (!finite_all_b(buf, len)) return set_error("non-finite state"), DCOPF_E_INVALID;
+  const BNet &N = b->nets[net].d;
+  const size_t B = N.B, nl = N.n_l;
+  const double *mu = buf + 1 + 3 * B;
+  for (size_t t = 0; t < 2 * B * nl; ++t)
+    if (mu[t] < 0) return set_error("mu must be >= 0"), DCOPF_E_INVALID;
+  const double *sq = buf + 1 + 3 * B + 4 * B * nl;
+  for (size_t t = 0; t < 2 * B * nl; ++t)
+    if (sq[t] < 0) return set_error("second moments must be >= 0"), DCOPF_E_INVALID;
+  for (size_t i = 0; i < B; ++i)
+    if (buf[1 + 2 * B + i] < 0) return set_error("second moments must be >= 0"), DCOPF_E_INVALID;
+  if (buf[0] < 0 || buf[0] != std::floor(buf[0]) || buf[0] > 1e15)
+    return set_error("iteration must be a nonnegative integer"), DCOPF_E_INVALID;
+  const long long k0 = (long long)buf[0];
+  DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
+  // zero this network's state; the batch's counter becomes k0 (the other
+  // networks keep their state, moved to the slot iteration k0 reads)
+  DCOPF_HIP_TRY(reset_state(b, k0, net));
+  const size_t slot = (size_t)(k0 & 1) * B;
+  double *d8[] = {N.lam, N.vlam, N.slam};
+  for (int a = 0; a < 3; ++a)
+    DCOPF_HIP_TRY(hipMemcpy(d8[a] + slot, buf + 1 + a * B, B * 8, hipMemcpyHostToDevice));
+  std::vector<float> tmp(B * N.ldl, 0.f);
+  float *f4[] = {N.mu_p, N.mu_m, N.v_p, N.v_m, N.s_p, N.s_m};
+  const double *in = buf + 1 + 3 * B;
+  for (int a = 0; a < 6; ++a, in += B * nl) {
+    for (size_t i = 0; i < B; ++i)
+      for (size_t l = 0; l < nl; ++l) tmp[i * N.ldl + l] = (float)in[i * nl + l];
+    DCOPF_HIP_TRY(hipMemcpy(f4[a], tmp.data(), tmp.size() * 4, hipMemcpyHostToDevice));
+  }
+  dim3 vg((unsigned)std::min(64, (N.n_l + 255) / 256), (unsigned)N.B);
+  bmake_v_kernel<<<vg, 256, 0, b->stream>>>(N.mu_p, N.mu_m, N.B, N.n_l, N.ldl, N.V_hi, N.V_lo);
+  DCOPF_HIP_TRY(hipGetLastError());
+  DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
+  for (size_t i = 0; i < B; ++i) {
+    b->best[N.inst0 + i] = -INFINITY;
+    b->best_iter[N.inst0 + i] = -1;
+  }
+  return DCOPF_OK;
+}
+
 dcopf_status dcopf_batch_set_start_dev(dcopf_batch_t b, int32_t net, const float *Y,
                                        int32_t ld) {
   if (!b || net < 0 || net >= (int)b->nets.size() || !Y)

@@ -358,3 +358,72 @@ def test_time_phases_leaves_iterate_unchanged():
         with solver_for(p, "gdm", "fp32", name="geo300") as s2:
             s2.step(12)
             np.testing.assert_array_equal(s.get_state(), s2.get_state())
+
+
+# ---------------------------------------------------------------------------
+# Step decay (alpha_t = alpha / (1 + decay t), t the state's counter)
+# ---------------------------------------------------------------------------
+DECAY = 0.02
+
+
+@pytest.mark.parametrize("rule_key", ["gdm", "gdm_literal", "adam", "adagrad"])
+def test_one_step_decay_fp64(rule_key):
+    """One step at a random counter t > 0 with step decay, FP64 products:
+    the device takes the oracle's step alpha / (1 + decay t)."""
+    name = "geo300"
+    p = prob(name, 7)
+    K = D.canonical(p)
+    rng = np.random.default_rng(29)
+    rule = "gdm" if rule_key.startswith("gdm") else rule_key
+    tau = np.full(K.c.size, 1e-9 * K.c.max())
+    for _ in range(20):
+        st = rand_state(K, rng, rule, 5.0)
+        if near_tie_free(K, st, tau) and st.t > 0:
+            break
+    ev = D.dual_value(K, st.lam, st.mu)
+    r = dict(synth.STEP_RULES[name])
+    base_alpha = {"adam": 0.05, "adagrad": 0.5}.get(rule, r["alpha"])
+    a_t = D.step_size(base_alpha, DECAY, st.t)
+    if rule_key == "gdm":
+        st1 = D.gdm_update(st, ev, a_t, r["rho"])
+    elif rule_key == "gdm_literal":
+        st1 = D.gdm_update(st, ev, a_t, r["rho"], literal=True)
+    elif rule == "adam":
+        st1 = D.adam_update(st, ev, a_t, 0.9, 0.99, 1e-8)
+    else:
+        st1 = D.adagrad_update(st, ev, a_t, 1e-8)
+    with solver_for(p, rule_key, "fp64", name=name, decay=DECAY) as s:
+        s.set_state(to_buf(st, rule, K.n_line))
+        s.step(1)
+        compare_state(s, st1, rule, K.n_line, rtol=1e-10, atol_mu=1e-11)
+        got = s.split_state(s.get_state())
+    # the decayed step differs measurably from the undecayed one
+    st_nodecay = UPDATES[rule_key](st, ev, r)
+    nl = K.n_line
+    moved = np.abs(st_nodecay.mu - st.mu).max()
+    assert np.abs(got["mu_p"] - st_nodecay.mu[:nl]).max() + \
+        np.abs(got["mu_m"] - st_nodecay.mu[nl:]).max() > 1e-3 * moved
+    print(f"decay {rule_key}: t = {st.t}, step {a_t:.3e} vs {base_alpha:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("rule", ["gdm", "adam", "adagrad"])
+def test_trajectory_fp64_decay(rule):
+    """Whole FP64 trajectories with step decay match the oracle (30-bus
+    network, 1000 iterations)."""
+    p = prob("tiny30")
+    K = D.canonical(p)
+    r = synth.STEP_RULES["tiny30"]
+    kw = {"gdm": dict(alpha=r["alpha"], rho=r["rho"]),
+          "adam": dict(alpha=0.05, beta1=0.9, beta2=0.99),
+          "adagrad": dict(alpha=0.5)}[rule]
+    ref_res = D.ascent(K, 1000, rule=rule, eps=1e-8, decay=1e-3, **kw)
+    with _abi().DualSolver(p, rule=rule, precision="fp64", eps=1e-8, decay=1e-3,
+                           graph_iters=50, **kw) as s:
+        s.step(1000)
+        gam = s.gammas(0, 1000)
+        got = s.split_state(s.get_state())
+    rel = np.abs(gam - ref_res.gammas) / np.maximum(np.abs(ref_res.gammas), 1.0)
+    print(f"decay trajectory {rule}: max rel gamma diff {rel.max():.2e}", flush=True)
+    assert rel.max() <= 1e-9
+    assert got["k"] == 1000
+    assert got["lam"] == pytest.approx(ref_res.state.lam, rel=1e-9)

@@ -23,7 +23,12 @@ def _opt(args):
 def highs_optima(net, base, D, procs=8):
     jobs = [(net, base.replace(d=D[i])) for i in range(D.shape[0])]
     with mp.get_context("spawn").Pool(procs) as pool:
-        return np.array(pool.map(_opt, jobs))
+        out = np.array(pool.map(_opt, jobs))
+        # let the workers exit by themselves (leaving the block would send
+        # them SIGTERM)
+        pool.close()
+        pool.join()
+    return out
 
 
 def test_warm_start_gains_over_cold_start():

@@ -178,3 +178,34 @@ def test_nu_form_complementary_split(qp):
         nu0 = mp - mm0
         g0_c = D.dual_value(K, lam, np.r_[np.maximum(nu0, 0.0), np.maximum(-nu0, 0.0)]).g
         assert g0_c == pytest.approx(g0, rel=1e-12, abs=1e-9)
+
+
+def test_dual_value_at_minimiser_and_at_a_tie():
+    """dual_value_at equals dual_value at the inner minimiser; at a linear
+    unit whose reduced cost is exactly zero, every point of its interval
+    gives the same value (the unit contributes 0 * p), while the residuals
+    move by the unit's column of the constraints."""
+    from oracle import dual as D
+    from paper_2406_13191_amd import synth
+    p = synth.make_problem("tiny30", 1)
+    K = D.canonical(p)
+    rng = np.random.default_rng(2)
+    mu = rng.exponential(1.0, 2 * K.n_line) * (rng.random(2 * K.n_line) < 0.3)
+    lam = 30.0
+    ev = D.dual_value(K, lam, mu)
+    at = D.dual_value_at(K, lam, mu, ev.x)
+    assert at.g == ev.g and at.grad_lam == ev.grad_lam
+    np.testing.assert_array_equal(at.grad_mu, ev.grad_mu)
+    # put unit 0 exactly at its switching price (mu = 0, lambda = c_0)
+    mu = np.zeros_like(mu)
+    lam0 = float(K.c[0])
+    ev0 = D.dual_value(K, lam0, mu)
+    assert ev0.a[0] == 0.0
+    for x0 in (K.lo[0], K.hi[0]):
+        x = ev0.x.copy()
+        x[0] = x0
+        e = D.dual_value_at(K, lam0, mu, x)
+        assert e.g == pytest.approx(ev0.g, rel=1e-14)
+        assert e.grad_lam == pytest.approx(ev0.grad_lam - (x0 - ev0.x[0]), abs=1e-9)
+        np.testing.assert_allclose(e.grad_mu, ev0.grad_mu + K.C[:, 0] * (x0 - ev0.x[0]),
+                                   atol=1e-9)
