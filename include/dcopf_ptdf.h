@@ -43,6 +43,25 @@ dcopf_status dcopf_ptdf(int32_t n_bus, int32_t n_line, const int32_t *fbus,
                         const int32_t *tbus, const double *b, int32_t slack,
                         void *hip_stream, double *H);
 
+/* The same build without any device allocation, for callers that cannot
+ * allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc / hipFree).  Arguments, result and errors as dcopf_ptdf; the
+ * kernels and their order are the same, so H is bitwise equal to what
+ * dcopf_ptdf writes.  The workspace is a fixed device array inside the
+ * library (about 65 MiB, allocated with the code object on each device the
+ * library runs on and held until the process ends), so the network must
+ * have at most DCOPF_PTDF_NOALLOC_MAX_BUS buses and
+ * DCOPF_PTDF_NOALLOC_MAX_LINE lines; larger ones get DCOPF_E_INVALID.
+ * Every call on one device shares that workspace: calls that overlap on
+ * one device (several host threads or streams) race and must be
+ * serialised by the caller.  The call runs on the current device and
+ * synchronises hip_stream before returning.                              */
+#define DCOPF_PTDF_NOALLOC_MAX_BUS 2049
+#define DCOPF_PTDF_NOALLOC_MAX_LINE 16384
+dcopf_status dcopf_ptdf_noalloc(int32_t n_bus, int32_t n_line, const int32_t *fbus,
+                                const int32_t *tbus, const double *b, int32_t slack,
+                                void *hip_stream, double *H);
+
 #ifdef __cplusplus
 }
 #endif

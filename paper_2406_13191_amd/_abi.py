@@ -649,3 +649,22 @@ def ptdf(n_bus: int, fbus, tbus, b, slack: int, H_ptr: int, stream=None):
     check(lib.dcopf_ptdf(int(n_bus), int(fb.size), fb.ctypes.data_as(C.POINTER(C.c_int32)),
                          tb.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(bb), int(slack),
                          C.c_void_p(stream or 0), C.c_void_p(H_ptr)))
+
+
+lib.dcopf_ptdf_noalloc.restype = C.c_int
+lib.dcopf_ptdf_noalloc.argtypes = lib.dcopf_ptdf.argtypes
+PTDF_NOALLOC_MAX_BUS = 2049
+PTDF_NOALLOC_MAX_LINE = 16384
+
+
+def ptdf_noalloc(n_bus: int, fbus, tbus, b, slack: int, H_ptr: int, stream=None):
+    """As ptdf(), through the entry point that allocates no device memory
+    (fixed workspace inside the library; at most PTDF_NOALLOC_MAX_BUS buses
+    and PTDF_NOALLOC_MAX_LINE lines)."""
+    fb = np.ascontiguousarray(np.asarray(fbus, np.int32))
+    tb = np.ascontiguousarray(np.asarray(tbus, np.int32))
+    bb = _f64(b)
+    check(lib.dcopf_ptdf_noalloc(int(n_bus), int(fb.size),
+                                 fb.ctypes.data_as(C.POINTER(C.c_int32)),
+                                 tb.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(bb), int(slack),
+                                 C.c_void_p(stream or 0), C.c_void_p(H_ptr)))

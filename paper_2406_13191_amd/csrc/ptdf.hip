@@ -26,6 +26,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 namespace dcopf {
@@ -34,6 +36,8 @@ namespace {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 64;  // block size
+
+constexpr size_t round_up_c(size_t v, size_t m) { return (v + m - 1) / m * m; }
 
 __device__ __forceinline__ int reduced(int bus, int slack) {
   return bus == slack ? -1 : (bus < slack ? bus : bus - 1);
@@ -306,15 +310,24 @@ __global__ void gather_kernel(const double *__restrict__ X, int N, const int *__
   }
 }
 
-}  // namespace
-}  // namespace dcopf
 
-using namespace dcopf;
+__global__ void zero_kernel(double *__restrict__ p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
 
-extern "C" dcopf_status dcopf_ptdf(int32_t n_bus, int32_t n_line, const int32_t *fbus,
-                                   const int32_t *tbus, const double *b, int32_t slack,
-                                   void *hip_stream, double *H) {
-  set_error("");
+__global__ void zero_flag_kernel(int *flag) { *flag = 0; }
+
+// Device buffers of one build: the two N x N matrices, the inverses of the
+// diagonal blocks, the line data, the incidence lists and the failure flag.
+struct Workspace {
+  double *A = nullptr, *W = nullptr, *Yd = nullptr, *b = nullptr;
+  int *start = nullptr, *adj = nullptr, *fbus = nullptr, *tbus = nullptr, *flag = nullptr;
+};
+
+dcopf_status validate(int32_t n_bus, int32_t n_line, const int32_t *fbus, const int32_t *tbus,
+                      const double *b, int32_t slack, const double *H) {
   if (!fbus || !tbus || !b || !H) return set_error("ptdf: null pointer"), DCOPF_E_INVALID;
   if (n_bus < 2 || n_line < 1) return set_error("ptdf: need n_bus >= 2, n_line >= 1"), DCOPF_E_INVALID;
   if (slack < 0 || slack >= n_bus) return set_error("ptdf: slack out of range"), DCOPF_E_INVALID;
@@ -325,6 +338,14 @@ extern "C" dcopf_status dcopf_ptdf(int32_t n_bus, int32_t n_line, const int32_t 
     if (!(std::isfinite(b[l]) && b[l] > 0.0))
       return set_error("ptdf: susceptances must be finite and positive"), DCOPF_E_INVALID;
   }
+  return DCOPF_OK;
+}
+
+// The build itself, on buffers the caller of this function provides (every
+// buffer is cleared or written here before it is read).
+dcopf_status build(int32_t n_bus, int32_t n_line, const int32_t *fbus, const int32_t *tbus,
+                   const double *b, int32_t slack, hipStream_t s, double *H,
+                   const Workspace &ws) {
   const int n = n_bus - 1, T = (n + kT - 1) / kT, N = T * kT;
   // incidence lists per bus, in line order
   std::vector<int> start(n_bus + 1, 0), adj(2 * (size_t)n_line);
@@ -340,79 +361,169 @@ extern "C" dcopf_status dcopf_ptdf(int32_t n_bus, int32_t n_line, const int32_t 
       adj[fill[tbus[l]]++] = l;
     }
   }
-  hipStream_t s = (hipStream_t)hip_stream;
   const size_t NN = (size_t)N * N;
-  double *A = nullptr, *W = nullptr, *Yd = nullptr, *db = nullptr;
-  int *dstart = nullptr, *dadj = nullptr, *df = nullptr, *dt = nullptr, *flag = nullptr;
-  dcopf_status st = DCOPF_OK;
-  auto alloc = [&](void **p, size_t bytes) {
-    if (st == DCOPF_OK && hipMalloc(p, bytes) != hipSuccess) st = DCOPF_E_NOMEM;
-  };
-  alloc((void **)&A, NN * 8);
-  alloc((void **)&W, NN * 8);
-  alloc((void **)&Yd, (size_t)T * kT * kT * 8);
-  alloc((void **)&db, (size_t)n_line * 8);
-  alloc((void **)&dstart, (size_t)(n_bus + 1) * 4);
-  alloc((void **)&dadj, 2 * (size_t)n_line * 4);
-  alloc((void **)&df, (size_t)n_line * 4);
-  alloc((void **)&dt, (size_t)n_line * 4);
-  alloc((void **)&flag, 4);
+  double *A = ws.A, *W = ws.W, *Yd = ws.Yd;
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t r) {
     if (e == hipSuccess && r != hipSuccess) e = r;
   };
-  if (st == DCOPF_OK) {
-    chk(hipMemcpyAsync(db, b, (size_t)n_line * 8, hipMemcpyHostToDevice, s));
-    chk(hipMemcpyAsync(dstart, start.data(), (size_t)(n_bus + 1) * 4, hipMemcpyHostToDevice, s));
-    chk(hipMemcpyAsync(dadj, adj.data(), 2 * (size_t)n_line * 4, hipMemcpyHostToDevice, s));
-    chk(hipMemcpyAsync(df, fbus, (size_t)n_line * 4, hipMemcpyHostToDevice, s));
-    chk(hipMemcpyAsync(dt, tbus, (size_t)n_line * 4, hipMemcpyHostToDevice, s));
-    chk(hipMemsetAsync(flag, 0, 4, s));
-    chk(hipMemsetAsync(A, 0, NN * 8, s));
-    const int g = std::min(1024, (N + 255) / 256);
-    assemble_kernel<<<g, 256, 0, s>>>(dstart, dadj, df, dt, db, slack, n, N, A);
-    // block columns in pairs: the second column takes the first panel's
-    // update alone, then one K = 128 update of the trailing triangle
-    for (int kb = 0; kb < T; kb += 2) {
-      potrf_kernel<<<1, 64, 0, s>>>(A, N, kb, Yd, flag);
-      const int R = T - kb - 1;
-      if (R == 0) break;
-      panel_kernel<<<R, 256, 0, s>>>(A, N, kb, Yd);
-      update_kernel<<<R, 256, 0, s>>>(A, N, kb, 1, 1);
-      potrf_kernel<<<1, 64, 0, s>>>(A, N, kb + 1, Yd, flag);
-      const int R2 = R - 1;
-      if (R2 > 0) {
-        panel_kernel<<<R2, 256, 0, s>>>(A, N, kb + 1, Yd);
-        update_kernel<<<(unsigned)((long long)R2 * (R2 + 1) / 2), 256, 0, s>>>(A, N, kb, 2, 0);
-      }
+  chk(hipMemcpyAsync(ws.b, b, (size_t)n_line * 8, hipMemcpyHostToDevice, s));
+  chk(hipMemcpyAsync(ws.start, start.data(), (size_t)(n_bus + 1) * 4, hipMemcpyHostToDevice, s));
+  chk(hipMemcpyAsync(ws.adj, adj.data(), 2 * (size_t)n_line * 4, hipMemcpyHostToDevice, s));
+  chk(hipMemcpyAsync(ws.fbus, fbus, (size_t)n_line * 4, hipMemcpyHostToDevice, s));
+  chk(hipMemcpyAsync(ws.tbus, tbus, (size_t)n_line * 4, hipMemcpyHostToDevice, s));
+  const int gz = (int)std::min<size_t>(4096, (NN + 255) / 256);
+  zero_flag_kernel<<<1, 1, 0, s>>>(ws.flag);
+  zero_kernel<<<gz, 256, 0, s>>>(A, NN);
+  const int g = std::min(1024, (N + 255) / 256);
+  assemble_kernel<<<g, 256, 0, s>>>(ws.start, ws.adj, ws.fbus, ws.tbus, ws.b, slack, n, N, A);
+  // block columns in pairs: the second column takes the first panel's
+  // update alone, then one K = 128 update of the trailing triangle
+  for (int kb = 0; kb < T; kb += 2) {
+    potrf_kernel<<<1, 64, 0, s>>>(A, N, kb, Yd, ws.flag);
+    const int R = T - kb - 1;
+    if (R == 0) break;
+    panel_kernel<<<R, 256, 0, s>>>(A, N, kb, Yd);
+    update_kernel<<<R, 256, 0, s>>>(A, N, kb, 1, 1);
+    potrf_kernel<<<1, 64, 0, s>>>(A, N, kb + 1, Yd, ws.flag);
+    const int R2 = R - 1;
+    if (R2 > 0) {
+      panel_kernel<<<R2, 256, 0, s>>>(A, N, kb + 1, Yd);
+      update_kernel<<<(unsigned)((long long)R2 * (R2 + 1) / 2), 256, 0, s>>>(A, N, kb, 2, 0);
     }
-    chk(hipMemsetAsync(W, 0, NN * 8, s));
-    identity_kernel<<<g, 256, 0, s>>>(W, N);
-    // block rows in pairs: row i + 1 takes row i's update alone, then one
-    // K = 128 update of the rows below
-    for (int i = 0; i < T; i += 2) {
-      trsm_scale_kernel<<<i + 1, 256, 0, s>>>(W, N, i, Yd);
-      if (i + 1 == T) break;
-      trsm_update_kernel<<<i + 1, 256, 0, s>>>(A, W, N, i, 1);
-      trsm_scale_kernel<<<i + 2, 256, 0, s>>>(W, N, i + 1, Yd);
-      const int R = T - i - 2;
-      if (R > 0)
-        trsm_update_kernel<<<(unsigned)((long long)R * (i + 2)), 256, 0, s>>>(A, W, N, i, 2);
-    }
-    xprod_kernel<<<(unsigned)((long long)T * (T + 1) / 2), 256, 0, s>>>(W, N, A);
-    mirror_kernel<<<dim3((unsigned)(N / 32), (unsigned)(N / 32)), 256, 0, s>>>(A, N);
-    dim3 gg((unsigned)std::min(64, (n_bus + 255) / 256), (unsigned)std::min(n_line, 32768));
-    gather_kernel<<<gg, 256, 0, s>>>(A, N, df, dt, db, n_bus, n_line, slack, H);
-    chk(hipGetLastError());
-    chk(hipStreamSynchronize(s));
   }
+  zero_kernel<<<gz, 256, 0, s>>>(W, NN);
+  identity_kernel<<<g, 256, 0, s>>>(W, N);
+  // block rows in pairs: row i + 1 takes row i's update alone, then one
+  // K = 128 update of the rows below
+  for (int i = 0; i < T; i += 2) {
+    trsm_scale_kernel<<<i + 1, 256, 0, s>>>(W, N, i, Yd);
+    if (i + 1 == T) break;
+    trsm_update_kernel<<<i + 1, 256, 0, s>>>(A, W, N, i, 1);
+    trsm_scale_kernel<<<i + 2, 256, 0, s>>>(W, N, i + 1, Yd);
+    const int R = T - i - 2;
+    if (R > 0)
+      trsm_update_kernel<<<(unsigned)((long long)R * (i + 2)), 256, 0, s>>>(A, W, N, i, 2);
+  }
+  xprod_kernel<<<(unsigned)((long long)T * (T + 1) / 2), 256, 0, s>>>(W, N, A);
+  mirror_kernel<<<dim3((unsigned)(N / 32), (unsigned)(N / 32)), 256, 0, s>>>(A, N);
+  dim3 gg((unsigned)std::min(64, (n_bus + 255) / 256), (unsigned)std::min(n_line, 32768));
+  gather_kernel<<<gg, 256, 0, s>>>(A, N, ws.fbus, ws.tbus, ws.b, n_bus, n_line, slack, H);
+  chk(hipGetLastError());
+  chk(hipStreamSynchronize(s));
   int hflag = 0;
-  if (st == DCOPF_OK && e == hipSuccess) chk(hipMemcpy(&hflag, flag, 4, hipMemcpyDeviceToHost));
-  void *ptrs[] = {A, W, Yd, db, dstart, dadj, df, dt, flag};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
-  if (st != DCOPF_OK) return set_error("ptdf: device allocation failed"), st;
+  if (e == hipSuccess) chk(hipMemcpy(&hflag, ws.flag, 4, hipMemcpyDeviceToHost));
   if (e != hipSuccess) return set_error(std::string("ptdf: ") + hipGetErrorString(e)), DCOPF_E_HIP;
   if (hflag) return set_error("ptdf: the network is not connected"), DCOPF_E_INVALID;
   return DCOPF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed workspace of dcopf_ptdf_noalloc: networks of at most
+// DCOPF_PTDF_NOALLOC_MAX_BUS buses (N = 2048 reduced rows) and
+// DCOPF_PTDF_NOALLOC_MAX_LINE lines.  Each device holds its own copy for the
+// life of the process; host code addresses it only through the pointer that
+// hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocN = 2048;
+constexpr size_t kOffA = 0;
+constexpr size_t kOffW = kOffA + kNoAllocN * kNoAllocN * 8;
+constexpr size_t kOffY = kOffW + kNoAllocN * kNoAllocN * 8;
+constexpr size_t kOffB = kOffY + kNoAllocN * kT * 8;
+constexpr size_t kOffStart = kOffB + (size_t)DCOPF_PTDF_NOALLOC_MAX_LINE * 8;
+constexpr size_t kOffAdj = kOffStart + round_up_c((size_t)DCOPF_PTDF_NOALLOC_MAX_BUS + 1, 64) * 4;
+constexpr size_t kOffF = kOffAdj + 2 * (size_t)DCOPF_PTDF_NOALLOC_MAX_LINE * 4;
+constexpr size_t kOffT = kOffF + (size_t)DCOPF_PTDF_NOALLOC_MAX_LINE * 4;
+constexpr size_t kOffFlag = kOffT + (size_t)DCOPF_PTDF_NOALLOC_MAX_LINE * 4;
+constexpr size_t kScratchBytes = kOffFlag + 256;
+static_assert(kOffStart % 256 == 0 && kOffAdj % 256 == 0 && kOffF % 256 == 0 &&
+                  kOffT % 256 == 0 && kOffFlag % 256 == 0,
+              "workspace regions stay 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+dcopf_status scratch_on_current_device(unsigned char **out) {
+  int dev = -1;
+  DCOPF_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_error("ptdf_noalloc: device index out of range"), DCOPF_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(std::string("ptdf_noalloc: hipGetSymbolAddress failed: ") +
+                       hipGetErrorString(e)),
+             DCOPF_E_HIP;
+    g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return DCOPF_OK;
+}
+
+}  // namespace
+}  // namespace dcopf
+
+using namespace dcopf;
+
+extern "C" dcopf_status dcopf_ptdf(int32_t n_bus, int32_t n_line, const int32_t *fbus,
+                                   const int32_t *tbus, const double *b, int32_t slack,
+                                   void *hip_stream, double *H) {
+  set_error("");
+  dcopf_status st = validate(n_bus, n_line, fbus, tbus, b, slack, H);
+  if (st != DCOPF_OK) return st;
+  const int n = n_bus - 1, T = (n + kT - 1) / kT, N = T * kT;
+  const size_t NN = (size_t)N * N;
+  Workspace ws;
+  auto alloc = [&](void **p, size_t bytes) {
+    if (st == DCOPF_OK && hipMalloc(p, bytes) != hipSuccess) st = DCOPF_E_NOMEM;
+  };
+  alloc((void **)&ws.A, NN * 8);
+  alloc((void **)&ws.W, NN * 8);
+  alloc((void **)&ws.Yd, (size_t)T * kT * kT * 8);
+  alloc((void **)&ws.b, (size_t)n_line * 8);
+  alloc((void **)&ws.start, (size_t)(n_bus + 1) * 4);
+  alloc((void **)&ws.adj, 2 * (size_t)n_line * 4);
+  alloc((void **)&ws.fbus, (size_t)n_line * 4);
+  alloc((void **)&ws.tbus, (size_t)n_line * 4);
+  alloc((void **)&ws.flag, 4);
+  if (st == DCOPF_OK) st = build(n_bus, n_line, fbus, tbus, b, slack, (hipStream_t)hip_stream, H, ws);
+  else set_error("ptdf: device allocation failed");
+  void *ptrs[] = {ws.A, ws.W, ws.Yd, ws.b, ws.start, ws.adj, ws.fbus, ws.tbus, ws.flag};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  return st;
+}
+
+extern "C" dcopf_status dcopf_ptdf_noalloc(int32_t n_bus, int32_t n_line, const int32_t *fbus,
+                                           const int32_t *tbus, const double *b, int32_t slack,
+                                           void *hip_stream, double *H) {
+  set_error("");
+  dcopf_status st = validate(n_bus, n_line, fbus, tbus, b, slack, H);
+  if (st != DCOPF_OK) return st;
+  if (n_bus > DCOPF_PTDF_NOALLOC_MAX_BUS || n_line > DCOPF_PTDF_NOALLOC_MAX_LINE)
+    return set_error("ptdf_noalloc: at most " + std::to_string(DCOPF_PTDF_NOALLOC_MAX_BUS) +
+                     " buses and " + std::to_string(DCOPF_PTDF_NOALLOC_MAX_LINE) +
+                     " lines (fixed workspace); use dcopf_ptdf for larger networks"),
+           DCOPF_E_INVALID;
+  unsigned char *base = nullptr;
+  st = scratch_on_current_device(&base);
+  if (st != DCOPF_OK) return st;
+  Workspace ws;
+  ws.A = reinterpret_cast<double *>(base + kOffA);
+  ws.W = reinterpret_cast<double *>(base + kOffW);
+  ws.Yd = reinterpret_cast<double *>(base + kOffY);
+  ws.b = reinterpret_cast<double *>(base + kOffB);
+  ws.start = reinterpret_cast<int *>(base + kOffStart);
+  ws.adj = reinterpret_cast<int *>(base + kOffAdj);
+  ws.fbus = reinterpret_cast<int *>(base + kOffF);
+  ws.tbus = reinterpret_cast<int *>(base + kOffT);
+  ws.flag = reinterpret_cast<int *>(base + kOffFlag);
+  return build(n_bus, n_line, fbus, tbus, b, slack, (hipStream_t)hip_stream, H, ws);
 }
