@@ -120,9 +120,29 @@ typedef struct {
                           DCOPF_E_INVALID; the monitor gamma is the value of
                           that dual, dcopf_dual_bound the exact (closed-form)
                           dual at the same lambda and mu.                  */
+  int32_t scheme;      /* how an iteration reads the panel (same arithmetic
+                          up to FP32 summation order; results bitwise
+                          reproducible either way):
+                          DCOPF_SCHEME_TWO_PASS: a column pass over P^T
+                          (w = P^T v, units, x) then a line pass over P
+                          (F = P x, step and projection): the panel is read
+                          twice, with two launches and little beyond it.
+                          DCOPF_SCHEME_READ_ONCE: the line pass also forms,
+                          from the same rows of P, the per-workgroup
+                          partials of the next w = P^T v (Algorithm 1's two
+                          products from one read), and a unit pass sums them
+                          per column: the panel is read once, plus the
+                          partials (workgroups x columns).  Rows wider than
+                          16 chunks per lane of a workgroup (FP32 panels of
+                          more than 16,384 columns, FP64 of 8,192) only have
+                          the two-pass scheme (DCOPF_E_INVALID if asked).
+                          DCOPF_SCHEME_AUTO (0): read-once for panels of at
+                          least 10 MiB in the loop precision, two-pass below
+                          (launch latency, not bytes, bounds those).       */
 } dcopf_opts;
 
 enum { DCOPF_QP_CLOSED = 0, DCOPF_QP_ITERATED = 1 };
+enum { DCOPF_SCHEME_AUTO = 0, DCOPF_SCHEME_TWO_PASS = 1, DCOPF_SCHEME_READ_ONCE = 2 };
 
 typedef struct dcopf_dual_s *dcopf_dual_t;
 

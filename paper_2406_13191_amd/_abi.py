@@ -42,7 +42,8 @@ class Opts_C(C.Structure):
     _fields_ = [("rule", C.c_int32), ("literal", C.c_int32), ("alpha", C.c_double),
                 ("rho", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
                 ("eps", C.c_double), ("decay", C.c_double), ("precision", C.c_int32),
-                ("panel", C.c_int32), ("graph_iters", C.c_int32), ("qp_dual", C.c_int32)]
+                ("panel", C.c_int32), ("graph_iters", C.c_int32), ("qp_dual", C.c_int32),
+                ("scheme", C.c_int32)]
 
 
 class Primal_C(C.Structure):
@@ -126,14 +127,15 @@ def _f64(a) -> np.ndarray:
 
 
 QP_DUALS = {"closed": 0, "iterated": 1}
+SCHEMES = {"auto": 0, "two_pass": 1, "read_once": 2}
 
 
 def make_opts(rule="gdm", alpha=1e-3, rho=0.9, beta1=0.9, beta2=0.999, eps=1e-8,
               decay=0.0, literal=False, precision="fp32", panel="genbus",
-              graph_iters=0, qp_dual="closed") -> Opts_C:
+              graph_iters=0, qp_dual="closed", scheme="auto") -> Opts_C:
     return Opts_C(RULES[rule], int(bool(literal)), float(alpha), float(rho), float(beta1),
                   float(beta2), float(eps), float(decay), PRECISIONS[precision],
-                  PANELS[panel], int(graph_iters), QP_DUALS[qp_dual])
+                  PANELS[panel], int(graph_iters), QP_DUALS[qp_dual], SCHEMES[scheme])
 
 
 class DualSolver:

@@ -727,6 +727,391 @@ __global__ __launch_bounds__(256) void finalize_kernel(DevScalars *sc, int par,
 }
 
 // ---------------------------------------------------------------------------
+// Read-once iteration (panels whose rows fit the registers of a workgroup).
+// The two products of an iteration share one read of P (row-major):
+//
+//   line pass of iteration k:  per line l, F_l = P_l x - f_d,l, the residuals
+//       and the step and projection of mu_l, then with the same row of P
+//       still in registers the line's contribution P_l^T v_l of the new
+//       v_l = mu+_l - mu-_l to the next iteration's reduced costs;
+//       workgroup g writes its sum over its lines as the partial W_g of
+//       w = P^T v (columns in its lanes, fixed order);
+//   unit pass of iteration k+1: w = sum_g W_g (index order, FP64), then the
+//       units (reduced cost, inner minimiser, x) as in the column pass.
+//
+// So each iteration reads the panel once instead of once per orientation;
+// the partials (workgroups x columns) are the price.  A workgroup owns a
+// contiguous range of lines; its waves form 4 / QW row groups of QW waves,
+// each wave covering a slice of every row's 16-byte chunks (CPL per lane),
+// and a row group takes RW rows at a time.  With QW > 1 the slices' dot
+// products meet in LDS (one barrier per RW rows).  x stays in registers;
+// the w partials are accumulated in registers and the row groups' sums meet
+// in LDS at the end.
+//
+// With prime = 1 the pass only forms the partials of the current v (after
+// the state was set); the arithmetic is that of a step, so a resumed run is
+// bitwise equal to an uninterrupted one.
+// ---------------------------------------------------------------------------
+template <typename V, typename T> __device__ __forceinline__ V axpy_vec(const V &p, T v, V acc);
+template <> __device__ __forceinline__ f32x4 axpy_vec(const f32x4 &p, float v, f32x4 acc) {
+  acc.x = fmaf(p.x, v, acc.x);
+  acc.y = fmaf(p.y, v, acc.y);
+  acc.z = fmaf(p.z, v, acc.z);
+  acc.w = fmaf(p.w, v, acc.w);
+  return acc;
+}
+template <> __device__ __forceinline__ f64x2 axpy_vec(const f64x2 &p, double v, f64x2 acc) {
+  acc.x = fma(p.x, v, acc.x);
+  acc.y = fma(p.y, v, acc.y);
+  return acc;
+}
+
+// Rows of one block: the panel chunks and the state of line (first row +
+// lane) for lanes < RW.
+template <typename V, int RW, int CPL> struct RowBlock {
+  V pr[RW][CPL];
+  double mp, mm, fdl, fl, vp, vm, sp, sm;
+};
+
+template <typename T, int QW, int RW, int CPL, bool NT, bool PIPE>
+__global__ __launch_bounds__(256) void rlines_kernel(
+    const T *__restrict__ P, int n_lines, int ldc, const T *__restrict__ x_in,
+    const double *__restrict__ fd, const double *__restrict__ flim,
+    double *__restrict__ mu_p, double *__restrict__ mu_m, double *__restrict__ v_p,
+    double *__restrict__ v_m, double *__restrict__ s_p, double *__restrict__ s_m,
+    const DevScalars *sc, int par, double *__restrict__ part_b, int gb,
+    T *__restrict__ part_w, StepParams prm, int prime) {
+  using V = typename Vec16<T>::type;
+  using Blk = RowBlock<V, RW, CPL>;
+  constexpr int VN = Vec16<T>::n;
+  constexpr int NRG = 4 / QW;
+  extern __shared__ __align__(16) unsigned char smem_raw[];  // [NRG - 1][ldc] of T
+  __shared__ T dots[2][NRG][RW][QW];
+  // the wavefront index is uniform: in a scalar register, so row addresses
+  // are scalar bases with per-lane offsets
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int rg = wave / QW, qi = wave % QW;
+  const int nv = ldc / VN;
+  const int qc = (nv + QW - 1) / QW;
+  const int c0 = qi * qc, c1 = min(nv, c0 + qc);
+  // contiguous, balanced line ranges (every workgroup has at least one line)
+  const int l_begin = (int)((long long)blockIdx.x * n_lines / gridDim.x);
+  const int l_end = (int)((long long)(blockIdx.x + 1) * n_lines / gridDim.x);
+  const int nblk = (l_end - l_begin + RW - 1) / RW;
+  // chunk indices of this lane (clamped to a valid chunk; masked by xr = 0
+  // in the dot products and never stored)
+  unsigned cidx[CPL];  // unsigned: a scalar row base plus a 32-bit lane offset
+  bool cval[CPL];
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) {
+    const int i = c0 + lane + u * kWave;
+    cval[u] = i < c1;
+    cidx[u] = cval[u] ? (unsigned)i : 0u;
+  }
+  // Block bb of this row group: its rows (rows past the range read a valid
+  // row and get weight 0) and the state of its line lane < RW.
+  auto load_blk = [&](int bb, Blk &B) {
+    const int b = bb + rg;
+    const int lrow0 = l_begin + b * RW;
+    const int lm = lrow0 + lane;
+    const int lc = (lane < RW && b < nblk && lm < l_end) ? lm : l_begin;
+    B.mp = ldg(mu_p + lc);
+    B.mm = ldg(mu_m + lc);
+    B.fdl = B.fl = B.vp = B.vm = B.sp = B.sm = 0.0;
+    if (!prime) {
+      B.fdl = ldg(fd + lc);
+      B.fl = ldg(flim + lc);
+      B.vp = ldg(v_p + lc);
+      B.vm = ldg(v_m + lc);
+      if (prm.rule != DCOPF_RULE_GDM) {
+        B.sp = ldg(s_p + lc);
+        B.sm = ldg(s_m + lc);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int lr = (b < nblk && lrow0 + r < l_end) ? lrow0 + r : l_begin;
+      const char *row = reinterpret_cast<const char *>(P + (size_t)lr * ldc);
+#pragma unroll
+      for (int u = 0; u < CPL; ++u)
+        B.pr[r][u] = panel_ld<NT>(reinterpret_cast<const V *>(row + cidx[u] * 16u));
+    }
+  };
+  const V *xv = reinterpret_cast<const V *>(x_in);
+  V xr[CPL], wacc[CPL];
+  const V zero = {};
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) {
+    xr[u] = (!prime && cval[u]) ? xv[cidx[u]] : zero;
+    wacc[u] = zero;
+  }
+  const IterSlot cur = sc->slot[par];
+  double term = 0.0;
+  int it = 0;
+  Blk B;
+  if (PIPE) load_blk(0, B);
+  for (int bb = 0; bb < nblk; bb += NRG, ++it) {
+    if (!PIPE) load_blk(bb, B);
+    // with PIPE the next block's loads are in flight during this block's work
+    Blk Nx;
+    const bool more = PIPE && bb + NRG < nblk;
+    if (more) load_blk(bb + NRG, Nx);
+    const int b = bb + rg;
+    const int lm = l_begin + b * RW + lane;
+    const bool mine = lane < RW && b < nblk && lm < l_end;
+    double dot = 0.0;
+    if (!prime) {
+      T acc[RW];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        T a = (T)0;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) a = fma_vec(B.pr[r][u], xr[u], a);
+        acc[r] = wave_sum(a);
+      }
+      if constexpr (QW > 1) {
+        if (lane == 0)
+#pragma unroll
+          for (int r = 0; r < RW; ++r) dots[it & 1][rg][r][qi] = acc[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+          T s = (T)0;
+#pragma unroll
+          for (int q2 = 0; q2 < QW; ++q2) s += dots[it & 1][rg][r][q2];
+          acc[r] = s;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RW; ++r)
+        if (lane == r) dot = (double)acc[r];
+    }
+    double vnew = 0.0;
+    if (mine) {
+      const double mp = B.mp, mm = B.mm;
+      if (prime) {
+        vnew = mp - mm;
+      } else {
+        double vp = B.vp, vm = B.vm, sp = B.sp, sm = B.sm;
+        const double F = dot - B.fdl;
+        const double gp = F - B.fl, gm = -F - B.fl;
+        const double a = cur.alpha;
+        double np_, nm_;
+        if (prm.rule == DCOPF_RULE_GDM) {
+          vp = prm.rho * vp + a * gp;
+          vm = prm.rho * vm + a * gm;
+          np_ = mp + vp;
+          nm_ = mm + vm;
+          if (prm.literal) {
+            np_ += a * gp;
+            nm_ += a * gm;
+          }
+        } else if (prm.rule == DCOPF_RULE_ADAM) {
+          vp = prm.beta1 * vp + (1.0 - prm.beta1) * gp;
+          vm = prm.beta1 * vm + (1.0 - prm.beta1) * gm;
+          sp = prm.beta2 * sp + (1.0 - prm.beta2) * gp * gp;
+          sm = prm.beta2 * sm + (1.0 - prm.beta2) * gm * gm;
+          np_ = mp + a * (vp / cur.c1) / (sqrt(sp / cur.c2) + prm.eps);
+          nm_ = mm + a * (vm / cur.c1) / (sqrt(sm / cur.c2) + prm.eps);
+        } else {
+          sp += gp * gp;
+          sm += gm * gm;
+          np_ = mp + a * gp / (sqrt(sp) + prm.eps);
+          nm_ = mm + a * gm / (sqrt(sm) + prm.eps);
+        }
+        np_ = fmax(np_, 0.0);
+        nm_ = fmax(nm_, 0.0);
+        if (qi == 0) {
+          term += (mp - mm) * B.fdl + (mp + mm) * B.fl;
+          if (prm.rule != DCOPF_RULE_ADAGRAD) {
+            v_p[lm] = vp;
+            v_m[lm] = vm;
+          }
+          if (prm.rule != DCOPF_RULE_GDM) {
+            s_p[lm] = sp;
+            s_m[lm] = sm;
+          }
+          mu_p[lm] = np_;
+          mu_m[lm] = nm_;
+        }
+        vnew = np_ - nm_;
+      }
+    }
+    // P_l^T v_l of the block's rows, in row order
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const T vr = (T)__shfl(vnew, r, kWave);
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) wacc[u] = axpy_vec(B.pr[r][u], vr, wacc[u]);
+    }
+    if (more) B = Nx;
+  }
+  // one partial of the line terms per workgroup (its wavefronts in order),
+  // and the row groups' partials of w meet in LDS: ((W_0 + W_1) + W_2) + W_3
+  __shared__ double tw[4];
+  if (!prime) {
+    const double wl_ = wave_sum(term);
+    if (lane == 0) tw[wave] = wl_;
+  }
+  V *wp = reinterpret_cast<V *>(part_w + (size_t)blockIdx.x * ldc);
+  if constexpr (NRG > 1) {
+    V *wl = reinterpret_cast<V *>(smem_raw);
+    if (rg > 0)
+#pragma unroll
+      for (int u = 0; u < CPL; ++u)
+        if (cval[u]) wl[(size_t)(rg - 1) * nv + cidx[u]] = wacc[u];
+    __syncthreads();
+    if (rg == 0)
+#pragma unroll
+      for (int u = 0; u < CPL; ++u)
+        if (cval[u]) {
+          V t = wacc[u];
+#pragma unroll
+          for (int g = 1; g < NRG; ++g) t += wl[(size_t)(g - 1) * nv + cidx[u]];
+          wp[cidx[u]] = t;
+        }
+  } else {
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+      if (cval[u]) wp[cidx[u]] = wacc[u];
+    if (!prime) __syncthreads();
+  }
+  if (!prime && threadIdx.x == 0)
+    part_b[(size_t)par * gb + blockIdx.x] = ((tw[0] + tw[1]) + tw[2]) + tw[3];
+}
+
+// Units of one column handled by one lane, in unit order (the serial form
+// of column_units); the data of the first unit (cf, qf, lof, hif) were
+// loaded earlier.
+__device__ __forceinline__ void lane_units(double w, double lam, int g0, int g1, double cf,
+                                           double qf, double lof, double hif,
+                                           const double *__restrict__ c,
+                                           const double *__restrict__ q,
+                                           const double *__restrict__ pmin,
+                                           const double *__restrict__ pmax, double *xj,
+                                           double *phij, double *__restrict__ psum, SDual sd,
+                                           double alpha, double rho) {
+  double xs = 0.0, ph = 0.0;
+  for (int t = g0; t < g1; ++t) {
+    const bool first = t == g0;
+    const double ct = first ? cf : c[t], qt = first ? qf : q[t];
+    const double lo = first ? lof : pmin[t], hi = first ? hif : pmax[t];
+    const double r = ct - lam + w;
+    double p;
+    if (sd.s) {
+      // Section 3.2, eq. QP_finalgamma with s fixed: q (p - m)^2 is bounded
+      // below by -sqrt(q) s (p - m) - s^2 / 4
+      const double m = 0.5 * (lo + hi), sq = sqrt(qt), st = sd.s[t];
+      const double a = r + 2.0 * qt * m - sq * st;
+      p = inner_min(a, 0.0, lo, hi);
+      ph += a * p - qt * m * m + sq * st * m - 0.25 * st * st;
+      const double v = rho * sd.v[t] + alpha * (-sq * (p - m) - 0.5 * st);
+      sd.v[t] = v;
+      sd.s[t] = st + v;
+    } else {
+      p = inner_min(r, qt, lo, hi);
+      ph += r * p + qt * p * p;
+    }
+    xs += p;
+    if (psum) psum[t] += p;
+  }
+  *xj = xs;
+  *phij = ph;
+}
+
+// Unit pass of the read-once iteration k.  Workgroup j owns the 16 columns
+// 16 j .. 16 j + 15; thread (r, c) = (t / 16, t % 16) loads the partials
+// g = r, r + 16, ... (< 16 MP of them) of column 16 j + c, all before its
+// first wait, and sums them in FP64 in that order; the 16 row sums of a
+// column meet in LDS in row order.  Wavefront 0 folds iteration k-1 (as the
+// column pass does), then its lanes c < 16 run the units of column 16 j + c
+// and write x; lane 0 writes the workgroup's sums of p* and phi.
+#ifndef DCOPF_UNIT_COLS
+#define DCOPF_UNIT_COLS 16
+#endif
+constexpr int kUnitCols = DCOPF_UNIT_COLS;
+template <typename T, int MP>
+__global__ __launch_bounds__(256) void runits_kernel(
+    const T *__restrict__ part_w, int gw, int ldc, int n_cols, const int *__restrict__ seg,
+    const double *__restrict__ c, const double *__restrict__ q,
+    const double *__restrict__ pmin, const double *__restrict__ pmax, DevScalars *sc, int par,
+    T *__restrict__ x_out, double *__restrict__ part_a, int ga,
+    const double *__restrict__ part_b, int gb, StepParams prm, double *__restrict__ gam_buf,
+    long long gam_mask, double *__restrict__ psum, SDual sd) {
+  constexpr int NR = 256 / kUnitCols;
+  __shared__ double wr[NR][kUnitCols];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int tc = threadIdx.x % kUnitCols, tr = threadIdx.x / kUnitCols;
+  const int col = blockIdx.x * kUnitCols + tc;
+  const int cc = col < n_cols ? col : 0;
+  const IterSlot prev = sc->slot[par ^ 1];
+  const double *pa = part_a + (size_t)(par ^ 1) * 2 * ga;
+  const double *pb = part_b + (size_t)(par ^ 1) * gb;
+  // wavefront 0: unit boundaries of its column and the previous partials
+  const bool ulane = wave == 0 && lane < kUnitCols && col < n_cols;
+  int g0 = 0, g1 = 0;
+  WaveSums ws;
+  if (wave == 0) {
+    g0 = ldg(seg + cc);
+    g1 = ulane ? ldg(seg + cc + 1) : g0;
+    ws.load(pa, ga, pb, gb, lane);
+  }
+  T pv[MP];
+#pragma unroll
+  for (int m = 0; m < MP; ++m) {
+    const int g = tr + m * NR;
+    pv[m] = ldg(part_w + (size_t)(g < gw ? g : 0) * ldc + cc);
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int m = 0; m < MP; ++m)
+    if (tr + m * NR < gw) s += (double)pv[m];
+  // the data of the column's first unit (waits for the boundaries only)
+  double cf = 0.0, qf = 0.0, lof = 0.0, hif = 0.0;
+  if (wave == 0) {
+    const int tf = g0 < g1 ? g0 : 0;
+    cf = ldg(c + tf);
+    qf = ldg(q + tf);
+    lof = ldg(pmin + tf);
+    hif = ldg(pmax + tf);
+  }
+  wr[tr][tc] = s;
+  __syncthreads();
+  if (wave != 0) return;
+  double w = 0.0;
+  if (lane < kUnitCols)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) w += wr[r][lane];
+  IterSlot cur = prev;
+  if (prev.pending) {
+    double ps, phis, lines, gam;
+    ws.sum(pa, ga, pb, gb, lane, &ps, &phis, &lines);
+    cur = fold(prev, ps, phis, lines, sc->D, prm, &gam);
+    if (blockIdx.x == 0 && lane == 0) {
+      gam_buf[prev.k & gam_mask] = gam;
+      sc->gamma_last = gam;
+    }
+  }
+  set_step(cur, prev.k + 1, prm);
+  cur.pending = 1;
+  const bool avg = sc->avg_on;
+  if (blockIdx.x == 0 && lane == 0) {
+    sc->slot[par] = cur;
+    if (avg) sc->avg_count += 1;
+  }
+  double xj = 0.0, phj = 0.0;
+  lane_units(w, cur.lam, g0, g1, cf, qf, lof, hif, c, q, pmin, pmax, &xj, &phj,
+             avg ? psum : nullptr, sd, cur.alpha, prm.rho);
+  if (ulane) x_out[col] = (T)xj;
+  const double xs = wave_sum(xj), phs = wave_sum(phj);
+  if (lane == 0) {
+    part_a[(size_t)par * 2 * ga + 2 * blockIdx.x] = xs;
+    part_a[(size_t)par * 2 * ga + 2 * blockIdx.x + 1] = phs;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Primal recovery (not in the paper): the average pbar of the inner
 // minimisers summed by the column passes, its cost and its residuals, in
 // FP64.  Columns: pbar per unit, xbar per column (the averaged injection),
@@ -1258,6 +1643,11 @@ struct dcopf_dual_s {
   bool col_one = false;  // one-column, one-barrier column pass (small panels)
   bool panel_nt = false;  // panels too large for the last-level cache: nontemporal loads
   int line_xr = 0;  // x chunks per lane held in registers (0: LDS / global)
+  // read-once iteration (line pass forms the next w's partials; unit pass)
+  bool fused = false;
+  int rl_qw = 1, rl_rw = 4, rl_cpl = 1, grid_rl = 0, grid_units = 0;
+  size_t lds_rl = 0;
+  void *part_w = nullptr;  // [grid_rl][ldc] in the loop precision
   // graph of graph_iters iterations (even), starting at an even iteration
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -1272,6 +1662,36 @@ struct dcopf_dual_s {
 namespace {
 
 constexpr int kLineRows = 4;  // lines per wavefront in the line pass
+
+// Workgroups per compute unit the read-once line pass aims at (the
+// partials of w it writes grow with the count)
+#ifndef DCOPF_READ_ONCE_GROUPS_PER_CU
+#define DCOPF_READ_ONCE_GROUPS_PER_CU 2
+#endif
+constexpr int kReadOnceGroupsPerCU = DCOPF_READ_ONCE_GROUPS_PER_CU;
+// The next block's panel loads issued before the current block's work
+#ifndef DCOPF_READ_ONCE_PIPE
+#define DCOPF_READ_ONCE_PIPE 0
+#endif
+constexpr bool kReadOncePipe = DCOPF_READ_ONCE_PIPE != 0;
+// Rows per wavefront and block when a row has at most 2 chunks per lane
+#ifndef DCOPF_ROWS_NARROW
+#define DCOPF_ROWS_NARROW 4
+#endif
+constexpr int kRowsNarrow = DCOPF_ROWS_NARROW;
+// Rows of up to this many chunks per lane are covered by one wavefront
+#ifndef DCOPF_QW1_MAX_CPL
+#define DCOPF_QW1_MAX_CPL 12
+#endif
+constexpr int kQw1MaxCpl = DCOPF_QW1_MAX_CPL;
+// Automatic scheme: panels below this size (loop precision) keep the
+// two-pass iteration (measured: a 6 MB panel iterates faster two-pass, a
+// 21 MB one read-once)
+#ifndef DCOPF_READ_ONCE_MIN_BYTES
+#define DCOPF_READ_ONCE_MIN_BYTES (10 << 20)
+#endif
+constexpr double kReadOnceMinBytes = DCOPF_READ_ONCE_MIN_BYTES;
+static_assert(kQw1MaxCpl == 4 || kQw1MaxCpl == 12, "one-wavefront rows: 4 or 12 chunks");
 
 template <typename T, int CB, int UNR>
 void launch_colpass_cb(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hipEvent_t e1) {
@@ -1328,9 +1748,93 @@ void launch_linepass(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hip
 #undef DCOPF_LINEPASS
 }
 
+template <typename T, int QW, int RW, int CPL>
+void launch_rlines_cfg(dcopf_dual_s *h, hipStream_t s, int par, int prime, hipEvent_t e0,
+                       hipEvent_t e1) {
+  T *P = std::is_same<T, float>::value ? (T *)h->P32 : (T *)h->P64;
+  constexpr bool PIPE = kReadOncePipe && QW > 1;
+  (void)launch_k(h->panel_nt ? rlines_kernel<T, QW, RW, CPL, true, PIPE>
+                             : rlines_kernel<T, QW, RW, CPL, false, PIPE>,
+                 dim3(h->grid_rl), dim3(256), (unsigned)h->lds_rl, s, e0, e1, P, h->n_lines,
+                 h->ldc, (T *)h->xbuf, h->fd, h->fmax, h->mu_p, h->mu_m, h->v_p, h->v_m,
+                 h->s_p, h->s_m, h->sc, par, h->part_b, h->n_line_part, (T *)h->part_w, h->prm,
+                 prime);
+}
+
+template <typename T>
+void launch_rlines(dcopf_dual_s *h, hipStream_t s, int par, int prime, hipEvent_t e0 = nullptr,
+                   hipEvent_t e1 = nullptr) {
+  if (h->rl_qw == 1) {
+    switch (h->rl_cpl) {
+      case 1: launch_rlines_cfg<T, 1, kRowsNarrow, 1>(h, s, par, prime, e0, e1); break;
+      case 2: launch_rlines_cfg<T, 1, kRowsNarrow, 2>(h, s, par, prime, e0, e1); break;
+      case 4: launch_rlines_cfg<T, 1, 4, 4>(h, s, par, prime, e0, e1); break;
+#if DCOPF_QW1_MAX_CPL > 4
+      case 6: launch_rlines_cfg<T, 1, 2, 6>(h, s, par, prime, e0, e1); break;
+      case 9: launch_rlines_cfg<T, 1, 2, 9>(h, s, par, prime, e0, e1); break;
+      default: launch_rlines_cfg<T, 1, 2, 12>(h, s, par, prime, e0, e1); break;
+#else
+      default: break;
+#endif
+    }
+    return;
+  }
+  // rows per block: about 24 chunks per lane in flight (twice that, in two
+  // blocks, when the next block's loads go out before this block's work)
+  constexpr int D = kReadOncePipe ? 2 : 1;
+  switch (h->rl_cpl) {
+    case 2: launch_rlines_cfg<T, 4, 8 / D, 2>(h, s, par, prime, e0, e1); break;
+    case 3: launch_rlines_cfg<T, 4, 8 / D, 3>(h, s, par, prime, e0, e1); break;
+    case 4: launch_rlines_cfg<T, 4, 8 / D, 4>(h, s, par, prime, e0, e1); break;
+    case 6: launch_rlines_cfg<T, 4, 4 / D, 6>(h, s, par, prime, e0, e1); break;
+    case 8: launch_rlines_cfg<T, 4, 4 / D, 8>(h, s, par, prime, e0, e1); break;
+    case 10: launch_rlines_cfg<T, 4, 2 / D, 10>(h, s, par, prime, e0, e1); break;
+    case 12: launch_rlines_cfg<T, 4, 2 / D, 12>(h, s, par, prime, e0, e1); break;
+    default: launch_rlines_cfg<T, 4, 2 / D, 16>(h, s, par, prime, e0, e1); break;
+  }
+}
+
+template <typename T, int MP>
+void launch_runits_mp(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hipEvent_t e1) {
+  (void)launch_k(runits_kernel<T, MP>, dim3(h->grid_units), dim3(256), 0, s, e0, e1,
+                 (T *)h->part_w, h->grid_rl, h->ldc, h->n_cols, h->seg, h->c, h->q, h->pmin,
+                 h->pmax, h->sc, par, (T *)h->xbuf, h->part_a, h->grid_units, h->part_b,
+                 h->n_line_part, h->prm, h->gam, kGamCap - 1, h->psum,
+                 SDual{h->s_unit, h->v_unit});
+}
+
+// partials per thread: at most 16 MP line-pass workgroups
+template <typename T>
+void launch_runits(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hipEvent_t e1) {
+  constexpr int NR = 256 / kUnitCols;
+  if (h->grid_rl <= NR * 4) launch_runits_mp<T, 4>(h, s, par, e0, e1);
+  else if (h->grid_rl <= NR * 8) launch_runits_mp<T, 8>(h, s, par, e0, e1);
+  else if (h->grid_rl <= NR * 16) launch_runits_mp<T, 16>(h, s, par, e0, e1);
+  else if (h->grid_rl <= NR * 32) launch_runits_mp<T, 32>(h, s, par, e0, e1);
+  else launch_runits_mp<T, 64>(h, s, par, e0, e1);
+}
+
+// Partials of w = P^T v for the current multipliers (after create or a set
+// state), so the next unit pass starts from them.
+void prime_w(dcopf_dual_s *h) {
+  if (!h->fused) return;
+  if (h->opts.precision == DCOPF_PREC_FP32) launch_rlines<float>(h, h->stream, 0, 1);
+  else launch_rlines<double>(h, h->stream, 0, 1);
+}
+
 void launch_phase(dcopf_dual_s *h, hipStream_t s, int phase, int par, hipEvent_t e0 = nullptr,
                   hipEvent_t e1 = nullptr) {
   const bool fp32 = h->opts.precision == DCOPF_PREC_FP32;
+  if (h->fused) {
+    if (phase == 0) {
+      if (fp32) launch_runits<float>(h, s, par, e0, e1);
+      else launch_runits<double>(h, s, par, e0, e1);
+    } else {
+      if (fp32) launch_rlines<float>(h, s, par, 0, e0, e1);
+      else launch_rlines<double>(h, s, par, 0, e0, e1);
+    }
+    return;
+  }
   if (phase == 0) {
     if (fp32) launch_colpass<float>(h, s, par, e0, e1);
     else launch_colpass<double>(h, s, par, e0, e1);
@@ -1352,9 +1856,10 @@ void launch_iters(dcopf_dual_s *h, hipStream_t s, long long first, int64_t n) {
 // Fold the partials of the last launched iteration (no-op when none pending).
 void launch_finalize(dcopf_dual_s *h, hipStream_t s) {
   const int par = (int)((h->iters - 1) & 1);
-  finalize_kernel<<<1, 256, 0, s>>>(h->sc, par, h->part_a, h->grid_col, h->part_b,
+  finalize_kernel<<<1, 256, 0, s>>>(h->sc, par, h->part_a,
+                                    h->fused ? h->grid_units : h->grid_col, h->part_b,
                                     h->n_line_part, h->prm, h->gam, kGamCap - 1,
-                                    h->col_one ? 1 : 0);
+                                    (h->fused || h->col_one) ? 1 : 0);
 }
 
 void refresh_v(dcopf_dual_s *h) {
@@ -1425,6 +1930,8 @@ dcopf_status validate(const dcopf_problem *p, const dcopf_opts *o) {
     return set_error("graph_iters must be in [0, 4096]"), DCOPF_E_INVALID;
   if (o->qp_dual != DCOPF_QP_CLOSED && o->qp_dual != DCOPF_QP_ITERATED)
     return set_error("unknown qp_dual"), DCOPF_E_INVALID;
+  if (o->scheme < DCOPF_SCHEME_AUTO || o->scheme > DCOPF_SCHEME_READ_ONCE)
+    return set_error("unknown scheme"), DCOPF_E_INVALID;
   if (o->qp_dual == DCOPF_QP_ITERATED &&
       (o->rule != DCOPF_RULE_GDM || o->literal != 0 || o->decay != 0.0))
     return set_error("the iterated-s QP dual needs rule GDM, literal 0, decay 0"),
@@ -1446,7 +1953,7 @@ void free_handle(dcopf_dual_s *h) {
                   h->pmin, h->pmax, h->seg, h->gperm, h->mu_p, h->mu_m, h->v_p, h->v_m,
                   h->s_p, h->s_m, h->vbuf, h->xbuf, h->v64b, h->part_a, h->part_b,
                   h->part_c, h->part_d, h->counters, h->sc, h->gam, h->psum, h->pbar,
-                  h->xbar, h->ppart, h->primal, h->s_unit, h->v_unit};
+                  h->xbar, h->ppart, h->primal, h->s_unit, h->v_unit, h->part_w};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   auto &R = h->rep;
@@ -1528,6 +2035,59 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   }
   h->grid_line = grid_for(nl, 4 * kLineRows, 65536);
   h->n_line_part = 4 * h->grid_line;
+  {
+    // read-once iteration: rows of up to 4 chunks per lane are covered by
+    // one wavefront (four row groups per workgroup), wider rows by the four
+    // wavefronts together (up to 16 chunks per lane); wider panels keep the
+    // two-pass iteration
+    const int nvc = h->ldc / (fp32 ? 4 : 2);
+    int qw = 1, cpl = (nvc + kWave - 1) / kWave;
+    if (cpl > kQw1MaxCpl) {
+      qw = 4;
+      cpl = (nvc + 4 * kWave - 1) / (4 * kWave);
+    }
+    static const int kCpl1[] = {1, 2, 4, 4, 6, 6, 9, 9, 9, 12, 12, 12},
+                     kCpl4[] = {2, 3, 4, 6, 8, 10, 12, 16};
+    if (qw == 1) cpl = kCpl1[cpl - 1];
+    else
+      for (int v : kCpl4)
+        if (v >= cpl) {
+          cpl = v;
+          break;
+        }
+    const bool can = qw == 1 || cpl <= 16;
+    if (o->scheme == DCOPF_SCHEME_READ_ONCE && !can) {
+      free_handle(h);
+      return set_error("read-once scheme: panel rows too wide (use two-pass)"), DCOPF_E_INVALID;
+    }
+    h->fused = o->scheme == DCOPF_SCHEME_READ_ONCE ||
+               (o->scheme == DCOPF_SCHEME_AUTO && can &&
+                (double)nl * h->ldc * (fp32 ? 4 : 8) >= (double)kReadOnceMinBytes);
+    if (h->fused) {
+      h->rl_qw = qw;
+      h->rl_cpl = cpl;
+      h->rl_rw = qw == 1 ? (cpl <= 2 ? kRowsNarrow : (cpl <= 4 ? 4 : 2))
+                         : (cpl <= 4 ? 8 : (cpl <= 8 ? 4 : 2)) / (kReadOncePipe ? 2 : 1);
+      // workgroups: one block round each while that keeps the count below
+      // the target (a few per compute unit), else the target
+      const int rows_m = h->rl_rw * (4 / qw);
+      int n_cu = 256;
+      {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            v > 0)
+          n_cu = v;
+      }
+      const int target = std::max(1, kReadOnceGroupsPerCU * n_cu);
+      h->grid_rl = std::min(target, (nl + rows_m - 1) / rows_m);
+      h->grid_rl = std::max(1, std::min(h->grid_rl, nl));
+      h->lds_rl = (size_t)(4 / qw - 1) * h->ldc * (fp32 ? 4 : 8);
+      h->n_line_part = h->grid_rl;
+      h->grid_units = (nc + kUnitCols - 1) / kUnitCols;
+      h->panel_nt = (size_t)nl * h->ldc * (fp32 ? 4 : 8) > kMallBytes;
+    }
+  }
   h->grid_bnd_col = grid_for(nc, 4, 4096);
   h->grid_bnd_line = grid_for(nl, 256, 1024);
   h->lds_col = (size_t)h->ldl * esz;
@@ -1541,7 +2101,7 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   const size_t panel = (size_t)nl * h->ldc, panelT = (size_t)nc * h->ldl;
   if (fp32) {
     h->P32 = dalloc<float>(panel, &st);
-    h->P32T = dalloc<float>(panelT, &st);
+    if (!h->fused) h->P32T = dalloc<float>(panelT, &st);
   } else {
     h->P64 = dalloc<double>(panel, &st);
   }
@@ -1559,7 +2119,8 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   h->vbuf = dalloc<unsigned char>((size_t)h->ldl * esz, &st);
   h->xbuf = dalloc<unsigned char>((size_t)h->ldc * esz, &st);
   h->v64b = dalloc<double>(h->ldl, &st);
-  h->part_a = dalloc<double>(4 * (size_t)h->grid_col, &st);
+  h->part_a = dalloc<double>(4 * (size_t)std::max(h->grid_col, h->grid_units), &st);
+  if (h->fused) h->part_w = dalloc<unsigned char>((size_t)h->grid_rl * h->ldc * esz, &st);
   h->part_b = dalloc<double>(2 * (size_t)h->n_line_part, &st);
   h->part_c = dalloc<double>((size_t)h->grid_bnd_line, &st);
   h->part_d = dalloc<double>((size_t)h->grid_bnd_col, &st);
@@ -1640,7 +2201,8 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
     dim3 tg((unsigned)(h->ldc / 32), (unsigned)(h->ldl / 32));
     if (fp32) {
       gather_kernel<float><<<gg, 256, 0, s>>>(Hd, nb, nl, dcols, nc, h->ldc, h->P32);
-      transpose_kernel<float><<<tg, dim3(32, 8), 0, s>>>(h->P32, nl, h->ldc, nc, h->ldl, h->P32T);
+      if (h->P32T)
+        transpose_kernel<float><<<tg, dim3(32, 8), 0, s>>>(h->P32, nl, h->ldc, nc, h->ldl, h->P32T);
       // FP64 panel for the bound, transposed: gather into the (free) T slot first
       double *tmp = nullptr;
       chk(hipMalloc(&tmp, panel * 8));
@@ -1658,6 +2220,7 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   }
   chk(hipGetLastError());
   refresh_v(h);
+  prime_w(h);
   chk(hipGetLastError());
   chk(hipStreamSynchronize(s));
   cleanup_tmp();
@@ -1896,6 +2459,7 @@ dcopf_status dcopf_dual_set_state(dcopf_dual_t h, const double *buf, size_t len)
     DCOPF_HIP_TRY(hipMemcpy(arrs[i], buf + 5 + i * nl, nl * 8, hipMemcpyHostToDevice));
   h->iters = k0;
   refresh_v(h);
+  prime_w(h);
   DCOPF_HIP_TRY(hipGetLastError());
   DCOPF_HIP_TRY(hipStreamSynchronize(h->stream));
   return DCOPF_OK;
@@ -1912,14 +2476,18 @@ dcopf_status dcopf_dual_time_phases(dcopf_dual_t h, int64_t n, double *ms_out) {
   double *save = nullptr;
   void *vsave = nullptr;
   DevScalars *ssave = nullptr;
+  // the loop-precision vector the first timed launch reads: v (two-pass
+  // iteration) or the partials of w = P^T v (read-once iteration)
+  void *vbuf = h->fused ? h->part_w : h->vbuf;
+  const size_t vbytes = h->fused ? (size_t)h->grid_rl * h->ldc * esz : (size_t)h->ldl * esz;
   DCOPF_HIP_TRY(hipMalloc(&save, 6 * nl * 8));
-  DCOPF_HIP_TRY(hipMalloc(&vsave, (size_t)h->ldl * esz));
+  DCOPF_HIP_TRY(hipMalloc(&vsave, vbytes));
   DCOPF_HIP_TRY(hipMalloc(&ssave, sizeof(DevScalars)));
   double *arrs[] = {h->mu_p, h->mu_m, h->v_p, h->v_m, h->s_p, h->s_m};
   hipStream_t s = h->stream;
   for (int i = 0; i < 6; ++i)
     DCOPF_HIP_TRY(hipMemcpyAsync(save + i * nl, arrs[i], nl * 8, hipMemcpyDeviceToDevice, s));
-  DCOPF_HIP_TRY(hipMemcpyAsync(vsave, h->vbuf, (size_t)h->ldl * esz, hipMemcpyDeviceToDevice, s));
+  DCOPF_HIP_TRY(hipMemcpyAsync(vsave, vbuf, vbytes, hipMemcpyDeviceToDevice, s));
   DCOPF_HIP_TRY(hipMemcpyAsync(ssave, h->sc, sizeof(DevScalars), hipMemcpyDeviceToDevice, s));
   // the timed iterations add nothing to a primal average in progress
   static const int zero = 0;
@@ -1933,7 +2501,7 @@ dcopf_status dcopf_dual_time_phases(dcopf_dual_t h, int64_t n, double *ms_out) {
   }
   for (int i = 0; i < 6; ++i)
     DCOPF_HIP_TRY(hipMemcpyAsync(arrs[i], save + i * nl, nl * 8, hipMemcpyDeviceToDevice, s));
-  DCOPF_HIP_TRY(hipMemcpyAsync(h->vbuf, vsave, (size_t)h->ldl * esz, hipMemcpyDeviceToDevice, s));
+  DCOPF_HIP_TRY(hipMemcpyAsync(vbuf, vsave, vbytes, hipMemcpyDeviceToDevice, s));
   DCOPF_HIP_TRY(hipMemcpyAsync(h->sc, ssave, sizeof(DevScalars), hipMemcpyDeviceToDevice, s));
   DCOPF_HIP_TRY(hipGetLastError());
   DCOPF_HIP_TRY(hipStreamSynchronize(s));

@@ -31,6 +31,7 @@ def crowded_columns():
 
 
 @pytest.mark.parametrize("precision,rtol", [("fp64", 1e-9), ("fp32", 1e-5)])
+@pytest.mark.usefixtures("both_schemes")
 def test_units_beyond_a_wavefront_per_column(precision, rtol):
     p = crowded_columns()
     K = D.canonical(p)
@@ -65,6 +66,7 @@ def test_units_beyond_a_wavefront_batched():
         assert rel.max() <= 1e-4
 
 
+@pytest.mark.usefixtures("both_schemes")
 def test_batch_of_one_tracks_single_path():
     A = _abi()
     _, p = synth.make_network("geo300q", 7)
@@ -82,6 +84,7 @@ def test_batch_of_one_tracks_single_path():
     assert rel.max() <= 1e-4
 
 
+@pytest.mark.usefixtures("both_schemes")
 def test_congestion_free_is_economic_dispatch():
     # limits far above any flow: no line can bind, mu stays exactly 0, and the
     # dual optimum is the economic dispatch price lambda*, found by bisection
@@ -133,10 +136,12 @@ def test_two_bus_batch_single_column():
         assert vals[i] <= opt[i] * (1 + 1e-12)        # weak duality
 
 
+@pytest.mark.usefixtures("both_schemes")
 def test_panel_beyond_the_last_level_cache():
     # the FP64 all-bus panel of the 4600-bus network: its two orientations
-    # (436 MB) exceed the 256 MiB last-level cache, so both passes stream it
-    # with nontemporal loads (smaller panels use plain loads)
+    # (436 MB) exceed the 256 MiB last-level cache, so the two-pass scheme
+    # streams both with nontemporal loads; the read-once scheme reads one
+    # orientation (217 MB, plain loads) and 9 chunks per lane per row
     _, p = synth.make_network("bus4600", 4600)
     nl, nb = p.H.shape
     assert 2 * nl * nb * 8 > 256 * 2 ** 20
@@ -153,3 +158,67 @@ def test_panel_beyond_the_last_level_cache():
     print(f"all-bus FP64 panel: worst relative gamma deviation {rel.max():.2e}", flush=True)
     assert rel.max() <= 1e-9
     assert b == pytest.approx(D.dual_value(K, o.state.lam, o.state.mu).g, rel=1e-9)
+
+
+@pytest.mark.parametrize("name,precision,rtol", [("geo300q", "fp32", 1e-6),
+                                                  ("geo300", "fp64", 1e-10),
+                                                  ("bus2000", "fp64", 1e-10)])
+def test_schemes_agree(name, precision, rtol):
+    """Two-pass and read-once iterations: the same trajectory (FP64: to
+    rounding; FP32 compared on a QP, whose inner minimiser is continuous, as
+    the two schemes sum P^T v in different orders), and each scheme is
+    bitwise reproducible."""
+    A = _abi()
+    p = synth.make_problem(name, 7) if name.startswith("geo") else synth.config_problem(name)
+    r = synth.STEP_RULES[name]
+    kw = dict(rule="gdm", alpha=r["alpha"], rho=r["rho"], precision=precision)
+    g = {}
+    for scheme in ("two_pass", "read_once", "read_once"):
+        with A.DualSolver(p, scheme=scheme, graph_iters=20, **kw) as s:
+            s.step(60)
+            g.setdefault(scheme, []).append(s.gammas(0, 60))
+    np.testing.assert_array_equal(g["read_once"][0], g["read_once"][1])
+    np.testing.assert_allclose(g["read_once"][0], g["two_pass"][0], rtol=rtol, atol=rtol)
+
+
+def test_read_once_nontemporal_panel_and_width_limit():
+    """The FP32 all-bus panel of the 10,000-bus network (508 MB, beyond the
+    last-level cache: nontemporal loads, 10 chunks per lane and wavefront)
+    on the read-once scheme: one step from a random state matches the FP64
+    oracle's step (every unit is quadratic, so the inner minimiser is
+    continuous) to 1e-5 (floor 1e-3 max c).  The FP64 all-bus panel (10,000
+    columns) is wider than read-once rows allow, which create rejects when
+    that scheme is asked for."""
+    A = _abi()
+    _, p = synth.make_network("bus10000", 10000)
+    r = synth.STEP_RULES["bus10000"]
+    K = D.canonical(p)
+    assert np.all(K.M > 0)
+    nl = K.n_line
+    rng = np.random.default_rng(5)
+    st = D.AscentState.cold(nl)
+    st.t = 9
+    st.lam = float(rng.uniform(10, 60))
+    st.mu = rng.exponential(2.0, 2 * nl) * (rng.random(2 * nl) < 0.2)
+    st.v_mu = rng.normal(0, 0.2, 2 * nl)
+    st.v_lam = float(rng.normal(0, 1))
+    st1 = D.gdm_update(st, D.dual_value(K, st.lam, st.mu), r["alpha"], r["rho"])
+    buf = np.concatenate([[st.t, st.lam, st.v_lam, 0.0, 0.0], st.mu[:nl], st.mu[nl:],
+                          st.v_mu[:nl], st.v_mu[nl:], np.zeros(2 * nl)])
+    with A.DualSolver(p, rule="gdm", alpha=r["alpha"], rho=r["rho"], precision="fp32",
+                      panel="allbus", scheme="read_once") as s:
+        assert s.info()["n_cols"] == p.n_bus
+        s.set_state(buf)
+        s.step(1)
+        got = s.split_state(s.get_state())
+    floor = 1e-3 * K.c.max()
+    scale = max(np.abs(st1.mu).max(), floor)
+    err = max(np.abs(got["mu_p"] - st1.mu[:nl]).max(), np.abs(got["mu_m"] - st1.mu[nl:]).max())
+    print(f"read-once FP32 all-bus 10,000-bus panel: one-step mu error / scale "
+          f"{err / scale:.2e}", flush=True)
+    assert err <= 1e-5 * scale
+    assert abs(got["lam"] - st1.lam) <= 1e-5 * max(abs(st1.lam), floor)
+    with pytest.raises(A.DcopfError) as e:
+        A.DualSolver(p, rule="gdm", alpha=r["alpha"], rho=r["rho"], precision="fp64",
+                     panel="allbus", scheme="read_once")
+    assert e.value.status == -1 and "too wide" in str(e.value)

@@ -10,7 +10,7 @@ import pytest
 
 from paper_2406_13191_amd import synth
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("both_schemes")]
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "c1_tiny30.json")
 

@@ -8,7 +8,7 @@ import pytest
 from oracle import dual as D
 from paper_2406_13191_amd import synth
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("both_schemes")]
 
 
 def _abi():

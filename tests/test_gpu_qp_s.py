@@ -10,7 +10,7 @@ from oracle import dual as D
 from oracle.qp_s import ascent_s
 from paper_2406_13191_amd import synth
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("both_schemes")]
 
 
 def _abi():

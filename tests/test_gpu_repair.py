@@ -13,7 +13,7 @@ from oracle import ref
 from oracle.repair import repair as oracle_repair
 from paper_2406_13191_amd import synth
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("both_schemes")]
 
 
 def _abi():

@@ -15,7 +15,7 @@ from oracle import dual as D
 from oracle import ref
 from paper_2406_13191_amd import synth
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("both_schemes")]
 
 U32 = 2.0 ** -24
 
