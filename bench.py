@@ -71,11 +71,21 @@ def copy_calibration():
                       "bytes_written": 2 ** 30, "repeats": 3}), flush=True)
 
 
-def panel_bytes(n_line, n_cols, n_gen):
-    """Algorithmic HBM bytes of one launch of each pass (FP32 panel read once,
-    every vector read or written once)."""
+def panel_bytes(n_line, n_cols, n_gen, scheme="two_pass"):
+    """Algorithmic HBM bytes of one launch of each pass (FP32 panel, every
+    vector read or written once).  Two-pass: both passes read the panel.
+    Read-once: only the line pass reads it; the per-workgroup partials of
+    P^T v it writes and the unit pass reads are workspace, reported apart
+    (partial_bytes)."""
     panel = 4.0 * n_line * n_cols
-    col = panel + 4 * n_line + 4 * n_cols + n_gen * (4 * 8 + 4) + 4 * (n_cols + 1)
+    units = n_gen * (4 * 8 + 4) + 4 * (n_cols + 1)
+    if scheme == "read_once":
+        # unit pass: unit data and boundaries read, x written
+        col = units + 4 * n_cols
+        # line pass: x, f_d, f_max, mu+-, velocity+- read; mu+-, velocity+- written
+        line = panel + 4 * n_cols + n_line * (6 * 8 + 4 * 8)
+        return col, line
+    col = panel + 4 * n_line + 4 * n_cols + units
     # line pass: x, f_d, f_max, mu+-, velocity+- read; mu+-, velocity+-, v written
     line = panel + 4 * n_cols + n_line * (6 * 8 + 4 * 8 + 4)
     return col, line
@@ -555,27 +565,42 @@ def bench_warmstart(args, stream, prep):
     log(f"cold: {t_cold:.1f} s; warm solves")
     (hw, pw), t_warm = W.timed(W.run_to_gap, base, Dev, opt, r["alpha"], r["rho"], start,
                                args.max_iters, 10, 100, stream.cuda_stream, sw_)
-    log(f"warm: {t_warm:.1f} s")
-    hf, used = W.combine_with_fallback(hc, pc, hw, pw, 100)
+    log(f"warm: {t_warm:.1f} s; warm start with its cold shadow in one pipeline")
+    # the deployed form: warm and cold shadow side by side for 100
+    # iterations, the better trajectory kept per instance on the device
+    pipe, t_pipe = W.timed(W.run_with_fallback, base, Dev, opt, r["alpha"], r["rho"], start,
+                           100, args.max_iters, 10, stream.cuda_stream)
+    hf, used_cold = pipe["hit"], pipe["kept_cold"]
+    log(f"warm + fallback: {t_pipe:.1f} s")
     # wall time per iteration of the batched solve (bound checks every 10
     # iterations included), and the time at which the median instance is
-    # certified; the warm start adds one inference pass
+    # certified (the shadow's iterations included); the warm start adds one
+    # inference pass
     spi_c = sc_["seconds"] / max(sc_["iterations"], 1)
     spi_w = sw_["seconds"] / max(sw_["iterations"], 1)
+    cap_c = sc_["seconds_at"][max(sc_["seconds_at"])]
+    cap_f = pipe["seconds_at"][max(pipe["seconds_at"])]
     flops = 6.0 * 256 * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
     return dict(
-        n_train=int(ok.sum()), n_eval=int(keep.sum()), data_seconds=t_data,
+        n_train=int(ok.sum()), n_eval=int(keep.sum()), n_eval_drawn=int(keep.size),
+        n_eval_infeasible=int(keep.size - keep.sum()), data_seconds=t_data,
         train_seconds=t_train, epochs=args.epochs, final_loss=losses[-1], first_loss=losses[0],
         train_step_ms=ms_step, train_tflops=flops / (ms_step * 1e-3) / 1e12,
         median_iters_cold=W.median_iters(hc, args.max_iters),
         median_iters_warm=W.median_iters(hw, args.max_iters),
         median_iters_warm_fallback=W.median_iters(hf, args.max_iters),
         reached_cold=float((hc >= 0).mean()), reached_warm_fallback=float((hf >= 0).mean()),
-        warm_kept=float(used.mean()), solve_seconds_cold=t_cold, solve_seconds_warm=t_warm,
+        warm_kept=float(1.0 - used_cold.mean()), solve_seconds_cold=t_cold,
+        solve_seconds_warm=t_warm, solve_seconds_warm_fallback=t_pipe,
+        instance_iterations_warm_fallback=pipe["instance_iterations"],
         batch_ms_per_iteration_cold=spi_c * 1e3, batch_ms_per_iteration_warm=spi_w * 1e3,
-        median_seconds_to_gap_cold=W.median_iters(hc, args.max_iters) * spi_c,
-        median_seconds_to_gap_warm_fallback=W.median_iters(hf, args.max_iters) * spi_w
-        + t_pred, inference_seconds=t_pred)
+        median_seconds_to_gap_cold=W.median_seconds(hc, sc_["seconds_at"], cap_c),
+        median_seconds_to_gap_warm_fallback=W.median_seconds(hf, pipe["seconds_at"], cap_f)
+        + t_pred, inference_seconds=t_pred,
+        timing_note="median wall time from the hand-off of the start to the check at which "
+                    "the median instance is certified; warm + fallback includes the cold "
+                    "shadow's 100 iterations, the per-instance choice on the device and one "
+                    "inference pass")
 
 
 def ptdf_tiles(n):
@@ -747,27 +772,54 @@ def bench_single(args, stream, name, net, p, steps, warmup, log, with_cpu=True,
     # such samples
     ms_col, ms_line = (float(v) for v in
                        np.median(np.array([s.time_phases(200) for _ in range(5)]), axis=0))
+    sch = s.scheme()
     s.close()
-    b_col, b_line = panel_bytes(p.n_line, n_cols, p.n_gen)
+    scheme = sch["scheme"]
+    b_col, b_line = panel_bytes(p.n_line, n_cols, p.n_gen, scheme)
+    names = {"two_pass": ("colpass (w = P^T v, inner minimiser)",
+                          "linepass (F = P x - f_d, mu step)"),
+             "read_once": ("unit pass (w from the line pass's partials, inner minimiser)",
+                           "line pass (F = P x - f_d, mu step, partials of the next P^T v)")}
     if ms_line >= ms_col:
-        kkey, kname, kms, kbytes = "linepass", "linepass (F = P x - f_d, mu step)", ms_line, b_line
+        kkey, kname, kms, kbytes = "linepass", names[scheme][1], ms_line, b_line
     else:
-        kkey, kname, kms, kbytes = "colpass", "colpass (w = P^T v, inner minimiser)", ms_col, b_col
+        kkey, kname, kms, kbytes = "colpass", names[scheme][0], ms_col, b_col
     achieved = kbytes / (kms * 1e-3) / 1e9
-    traffic = measured_traffic(f"{name}/{args.panel}:{kkey}", SINGLE_SRC)
+    traffic = measured_traffic(f"{name}/{args.panel}/{scheme}:{kkey}", SINGLE_SRC)
     it_bytes = b_col + b_line
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=kname,
                     kernel_ms=round(kms, 5), bytes_per_launch=int(kbytes),
-                    other_kernel_ms=round(min(ms_col, ms_line), 5),
+                    other_kernel_ms=round(min(ms_col, ms_line), 5), scheme=scheme,
                     iteration=dict(bytes=int(it_bytes), us=round(ms / steps * 1e3, 3),
-                                   gbs=round(it_bytes / (ms / steps * 1e-3) / 1e9, 1)))
+                                   gbs=round(it_bytes / (ms / steps * 1e-3) / 1e9, 1),
+                                   frac=round(it_bytes / (ms / steps * 1e-3) / 1e9
+                                              / HBM_PEAK_GBS, 4)))
+    if scheme == "read_once":
+        # partials of P^T v: written by the line pass, read by the unit pass
+        roofline["partial_bytes"] = int(2 * 4 * sch["line_groups"] * n_cols)
 
     # time to a bound within 0.1 % of the FP64 optimum (HiGHS reference for
     # an LP), with an iteration cap of its own
     ttb = primal = cpu = None
     if not p.is_qp:
         opt = _lp_optimum(net, p)
+        target = "HiGHS optimum"
+    else:
+        # no QP solver here: the target is a certified upper bound, the cost
+        # of the repaired primal average of a long run (every feasible cost
+        # is >= OPT, so a bound within 0.1 % of it is within 0.1 % of OPT)
+        with _abi.DualSolver(p, stream=stream.cuda_stream, **kw) as s3:
+            s3.step(args.ttb_cap // 2)
+            s3.average(True)
+            s3.step(args.ttb_cap - args.ttb_cap // 2)
+            lb_long = s3.bound()
+            rp = s3.repair(None)
+        opt = rp["cost"] if rp["feasible"] else None
+        target = (f"certified upper bound: repaired primal average of {args.ttb_cap} "
+                  f"iterations (cost {opt}, {(opt - lb_long) / abs(opt):.2e} above that run's "
+                  f"last exact bound)" if opt is not None else None)
+    if opt is not None:
         with _abi.DualSolver(p, stream=stream.cuda_stream, **kw) as s2:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -775,7 +827,7 @@ def bench_single(args, stream, name, net, p, steps, warmup, log, with_cpu=True,
             dt = time.perf_counter() - t0
         ttb = dict(reached=res["status"] == 1, iterations=int(res["iter_of_bound"]),
                    iteration_cap=args.ttb_cap, seconds=round(dt, 5), gap=res["gap"],
-                   check_every=100, target="HiGHS optimum",
+                   check_every=100, target=target,
                    device_seconds=round(res["iter_of_bound"] * ms / steps / 1e3, 6))
     if with_primal:
         # primal recovery: the average of p* over iterations 2000..10000 (exact
@@ -813,7 +865,8 @@ def bench_single(args, stream, name, net, p, steps, warmup, log, with_cpu=True,
                 time_to_bound=ttb, setup_seconds=round(setup[1], 5),
                 setup_note="dcopf_dual_create on the host-resident problem: H "
                            f"({p.n_line} x {p.n_bus} FP64) copied to the device, panel "
-                           "gathered in both orientations, f_d = H d; first create "
+                           f"gathered ({scheme.replace('_', '-')} scheme), f_d = H d; first "
+                           "create "
                            f"(kernel loading included) {setup[0]:.4f} s",
                 primal_recovery=primal, roofline=roofline, cpu_baseline=cpu)
 

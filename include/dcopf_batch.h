@@ -130,6 +130,21 @@ size_t dcopf_batch_state_len(dcopf_batch_t b, int32_t net);
 dcopf_status dcopf_batch_get_state(dcopf_batch_t b, int32_t net, double *buf, size_t len);
 dcopf_status dcopf_batch_set_state(dcopf_batch_t b, int32_t net, const double *buf, size_t len);
 
+/* The fallback of a learned warm start: `dst` runs its instances from a
+ * predicted start, `src` the same instances (equal loads, instance by
+ * instance, on a network of the same shape) from the cold start of
+ * Algorithm 1, both for the same number of iterations.  Evaluates the exact
+ * bound of every instance of both, and wherever the cold instance's bound
+ * is larger, copies its whole state (multipliers, optimiser state, best
+ * bound, primal sums) over the warm one on the device; `kept` (host, [n
+ * instances], may be NULL) receives 1 there and 0 elsewhere.  `src` may
+ * then be destroyed: `dst` continues with the better trajectory of every
+ * instance.  DCOPF_E_STATE if the two are at different iterations,
+ * DCOPF_E_INVALID for different shapes, loads or step rules.
+ * Synchronises both streams.                                               */
+dcopf_status dcopf_batch_adopt_better(dcopf_batch_t dst, int32_t dnet, dcopf_batch_t src,
+                                      int32_t snet, int32_t *kept);
+
 /* Primal recovery (an extension, as dcopf_dual_average / dcopf_dual_primal):
  * enable = 1 restarts the average of every instance's inner minimiser p*
  * over the following iterations (including those of time_phases, which

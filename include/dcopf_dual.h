@@ -57,6 +57,30 @@ typedef enum {
   DCOPF_E_STATE = -7        /* state buffer of the wrong length */
 } dcopf_status;
 
+/* Device memory of the handles.  Every buffer a handle owns (panels, state,
+ * workspaces, the temporaries of its calls) comes from the allocator that
+ * was installed on the creating thread when the handle was created, and
+ * goes back to it when the handle is destroyed (or, for a temporary, when
+ * its call returns).  Without one, hipMalloc and hipFree serve.  A caller
+ * that manages device memory itself (PyTorch's caching allocator, a pool)
+ * installs its pair here, so the library allocates nothing on its own:
+ *
+ *   alloc(bytes, stream, ctx): device memory of at least `bytes` bytes,
+ *     256-byte aligned, usable on the current device by work on `stream`
+ *     (the handle's stream); NULL when it cannot (the call then returns
+ *     DCOPF_E_NOMEM);
+ *   free(ptr, bytes, stream, ctx): returns a block alloc gave, after the
+ *     work enqueued on `stream` that uses it (the release is stream
+ *     ordered: the library does not wait before it).
+ *
+ * dcopf_set_allocator(NULL, NULL, NULL) restores hipMalloc / hipFree; one
+ * of the two functions alone is DCOPF_E_INVALID.  The setting is per host
+ * thread and applies to handles (and dcopf_ptdf calls) made after it; each
+ * handle keeps the pair it was created with.                              */
+typedef void *(*dcopf_alloc_fn)(size_t bytes, void *hip_stream, void *ctx);
+typedef void (*dcopf_free_fn)(void *ptr, size_t bytes, void *hip_stream, void *ctx);
+dcopf_status dcopf_set_allocator(dcopf_alloc_fn alloc, dcopf_free_fn free, void *ctx);
+
 /* One DCOPF instance in the paper's statement (Section 2, eq. DCOPF).
  * All pointers are HOST memory; they are read during dcopf_dual_create and
  * may be freed by the caller when it returns.                              */
@@ -278,6 +302,13 @@ dcopf_status dcopf_dual_repair(dcopf_dual_t h, const double *p_in, int32_t max_r
 
 /* Panel width (number of H columns the products use) and iterations done. */
 dcopf_status dcopf_dual_info(dcopf_dual_t h, int32_t *n_cols, int64_t *iters);
+
+/* The iteration scheme the handle runs (DCOPF_SCHEME_TWO_PASS or
+ * DCOPF_SCHEME_READ_ONCE, resolved from DCOPF_SCHEME_AUTO at create) and,
+ * for read-once, the number of line-pass workgroups, each of which writes
+ * one partial of P^T v per iteration (0 for two-pass).  Either output may
+ * be NULL.                                                                 */
+dcopf_status dcopf_dual_scheme(dcopf_dual_t h, int32_t *scheme, int32_t *line_groups);
 
 /* Free all device and host memory of the handle.  NULL is a no-op.        */
 void dcopf_dual_destroy(dcopf_dual_t h);

@@ -91,6 +91,7 @@ def _load():
         "dcopf_dual_get_state": (C.c_int, [C.c_void_p, P(C.c_double), C.c_size_t]),
         "dcopf_dual_set_state": (C.c_int, [C.c_void_p, P(C.c_double), C.c_size_t]),
         "dcopf_dual_info": (C.c_int, [C.c_void_p, P(C.c_int32), P(C.c_int64)]),
+        "dcopf_dual_scheme": (C.c_int, [C.c_void_p, P(C.c_int32), P(C.c_int32)]),
         "dcopf_dual_average": (C.c_int, [C.c_void_p, C.c_int32]),
         "dcopf_dual_primal": (C.c_int, [C.c_void_p, P(Primal_C), P(C.c_double)]),
         "dcopf_dual_repair": (C.c_int, [C.c_void_p, P(C.c_double), C.c_int32, P(Repair_C),
@@ -107,6 +108,54 @@ def _load():
 
 
 lib = _load()
+
+
+# ---------------------------------------------------------------------------
+# Device memory from PyTorch's caching allocator (dcopf_set_allocator): the
+# handles' buffers then come from, and go back to, torch's pool on the
+# handle's stream.  Installed for the importing thread when a GPU is
+# present; other threads call use_torch_allocator() themselves.
+# ---------------------------------------------------------------------------
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+lib.dcopf_set_allocator.restype = C.c_int
+lib.dcopf_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, C.c_void_p]
+_exiting = False
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:  # noqa: BLE001  (out of memory: the library reports E_NOMEM)
+        return None
+
+
+def _torch_free(ptr, nbytes, stream, ctx):
+    if _exiting or not ptr:
+        return  # at interpreter exit torch may be gone; the process frees all
+    import torch
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+_TORCH_ALLOC = _ALLOC_FN(_torch_alloc)
+_TORCH_FREE = _FREE_FN(_torch_free)
+
+
+def use_torch_allocator():
+    """Handles created from now on by this thread take their device memory
+    from torch's caching allocator."""
+    check(lib.dcopf_set_allocator(_TORCH_ALLOC, _TORCH_FREE, None))
+
+
+def use_hip_allocator():
+    """Handles created from now on by this thread use hipMalloc / hipFree."""
+    check(lib.dcopf_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
+
+
+def _mark_exit():
+    global _exiting
+    _exiting = True
 
 
 def last_error() -> str:
@@ -269,6 +318,12 @@ class DualSolver:
         check(lib.dcopf_dual_info(self._h, C.byref(nc), C.byref(it)))
         return dict(n_cols=nc.value, iters=it.value)
 
+    def scheme(self):
+        sc = C.c_int32()
+        g = C.c_int32()
+        check(lib.dcopf_dual_scheme(self._h, C.byref(sc), C.byref(g)))
+        return dict(scheme={v: k for k, v in SCHEMES.items()}[sc.value], line_groups=g.value)
+
     # -- state helpers -------------------------------------------------------
     def split_state(self, buf):
         nl = self.n_line
@@ -319,6 +374,8 @@ def _bind_batch():
         "dcopf_batch_info": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int32), P(C.c_int64)]),
         "dcopf_batch_set_tiles": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_int32)]),
         "dcopf_batch_set_start_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32]),
+        "dcopf_batch_adopt_better": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
+                                               C.POINTER(C.c_int32)]),
         "dcopf_batch_average": (C.c_int, [C.c_void_p, C.c_int32]),
         "dcopf_batch_primal": (C.c_int, [C.c_void_p, C.c_int32, P(Primal_C), P(C.c_double)]),
         "dcopf_batch_repair": (C.c_int, [C.c_void_p, C.c_int32, P(C.c_double), C.c_int32,
@@ -468,6 +525,16 @@ class BatchSolver:
         """Start multipliers from a device FP32 array [n_inst, ld] laid out
         [mu+, mu-, lambda] (e.g. a torch tensor's data_ptr())."""
         check(lib.dcopf_batch_set_start_dev(self._h, int(net), C.c_void_p(y_ptr), int(ld)))
+
+    def adopt_better(self, net: int, other: "BatchSolver", other_net: int):
+        """Where an instance of `other` (the same instances from another
+        start, at the same iteration) has the larger exact bound, its state
+        replaces this batch's (dcopf_batch_adopt_better).  Returns the
+        per-instance flags (1: taken from `other`)."""
+        kept = np.zeros(self.sizes[net], np.int32)
+        check(lib.dcopf_batch_adopt_better(self._h, int(net), other._h, int(other_net),
+                                           kept.ctypes.data_as(C.POINTER(C.c_int32))))
+        return kept
 
     def info(self, net: int):
         cfg = np.zeros(4, np.int32)
@@ -670,3 +737,17 @@ def ptdf_noalloc(n_bus: int, fbus, tbus, b, slack: int, H_ptr: int, stream=None)
                                  fb.ctypes.data_as(C.POINTER(C.c_int32)),
                                  tb.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(bb), int(slack),
                                  C.c_void_p(stream or 0), C.c_void_p(H_ptr)))
+
+
+def _install_default_allocator():
+    import atexit
+    atexit.register(_mark_exit)
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        use_torch_allocator()
+
+
+_install_default_allocator()

@@ -1102,6 +1102,37 @@ __global__ void bset_start_kernel(BNet N, const float *__restrict__ Y, int ld, i
   }
 }
 
+// Instance i of `dst` takes the whole state of instance i of `src` when the
+// exact bound of `src`'s is larger (both evaluated at the same iteration):
+// multipliers, optimiser state, the split of v, the bound and the primal
+// sums; kept[i] says which.  Grid: (column blocks, instances).
+__global__ void badopt_kernel(BNet dst, BNet src, int slot, int *__restrict__ kept) {
+  const int i = blockIdx.y;
+  const bool take = src.bound[i] > dst.bound[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) kept[i] = take ? 1 : 0;
+  if (!take) return;
+  const size_t row = (size_t)i * dst.ldl;
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < dst.ldl; l += gridDim.x * blockDim.x) {
+    dst.mu_p[row + l] = src.mu_p[row + l];
+    dst.mu_m[row + l] = src.mu_m[row + l];
+    dst.v_p[row + l] = src.v_p[row + l];
+    dst.v_m[row + l] = src.v_m[row + l];
+    dst.s_p[row + l] = src.s_p[row + l];
+    dst.s_m[row + l] = src.s_m[row + l];
+    dst.V_hi[row + l] = src.V_hi[row + l];
+    dst.V_lo[row + l] = src.V_lo[row + l];
+  }
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < dst.n_g; g += gridDim.x * blockDim.x)
+    dst.psum[(size_t)i * dst.n_g + g] = src.psum[(size_t)i * dst.n_g + g];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const size_t a = (size_t)slot * dst.B + i;
+    dst.lam[a] = src.lam[a];
+    dst.vlam[a] = src.vlam[a];
+    dst.slam[a] = src.slam[a];
+    dst.bound[i] = src.bound[i];
+  }
+}
+
 // ---- setup -----------------------------------------------------------------
 // tmp[l][j] = H[l][cols[j]] (zero padded to [nlp][ldc]) in FP64.
 __global__ void bgather_kernel(const double *__restrict__ H, int n_bus, int n_l,
@@ -1174,7 +1205,6 @@ struct HostNet {
   BNet d{};  // device pointers (owned) and shapes
   std::vector<int> gperm;  // unit t of the column order is generator gperm[t]
   int n_bus = 0;
-  std::vector<void *> owned;
   // primal repair buffers (allocated by the network's first repair)
   struct Repair {
     double *pin = nullptr, *p = nullptr, *p0c = nullptr, *W = nullptr, *t = nullptr,
@@ -1187,15 +1217,10 @@ struct HostNet {
   double best_dummy = 0;
 };
 
-template <typename T> T *balloc(std::vector<void *> &owned, size_t n, bool *ok) {
-  void *p = nullptr;
-  if (n == 0) n = 1;
-  if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
-    *ok = false;
-    return nullptr;
-  }
-  owned.push_back(p);
-  return static_cast<T *>(p);
+template <typename T> T *balloc(DevPool &pool, size_t n, bool *ok) {
+  T *p = pool.get_n<T>(n == 0 ? 1 : n);
+  if (!p) *ok = false;
+  return p;
 }
 
 bool finite_all_b(const double *p, size_t n) {
@@ -1207,6 +1232,7 @@ bool finite_all_b(const double *p, size_t n) {
 }  // namespace
 
 struct dcopf_batch_s {
+  DevPool pool;  // every device buffer of the batch (the caller's allocator)
   std::vector<HostNet> nets;
   dcopf_batch_opts opts{};
   BParams prm{};
@@ -1233,11 +1259,7 @@ void free_batch(dcopf_batch_s *b) {
   if (!b) return;
   if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  for (auto &n : b->nets)
-    for (void *p : n.owned) (void)hipFree(p);
-  void *ptrs[] = {b->d_nets, b->d_wtiles, b->d_ftiles, b->d_inst, b->d_units, b->sc, b->gam};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
+  b->pool.release_all();
   delete b;
 }
 
@@ -1395,11 +1417,13 @@ hipError_t upload_tables(dcopf_batch_s *b) {
   std::iota(all.begin(), all.end(), 0);
   std::vector<int4> wt, ft;
   build_tables(b->nets, all, &wt, &ft);
-  if (b->d_wtiles) (void)hipFree(b->d_wtiles);
-  if (b->d_ftiles) (void)hipFree(b->d_ftiles);
+  b->pool.put(b->d_wtiles);
+  b->pool.put(b->d_ftiles);
   b->d_wtiles = b->d_ftiles = nullptr;
-  hipError_t e = hipMalloc(&b->d_wtiles, std::max<size_t>(1, wt.size()) * sizeof(int4));
-  if (e == hipSuccess) e = hipMalloc(&b->d_ftiles, std::max<size_t>(1, ft.size()) * sizeof(int4));
+  b->d_wtiles = b->d_ftiles = nullptr;
+  b->d_wtiles = b->pool.get_n<int4>(std::max<size_t>(1, wt.size()));
+  b->d_ftiles = b->pool.get_n<int4>(std::max<size_t>(1, ft.size()));
+  hipError_t e = (b->d_wtiles && b->d_ftiles) ? hipSuccess : hipErrorOutOfMemory;
   if (e == hipSuccess)
     e = hipMemcpy(b->d_wtiles, wt.data(), wt.size() * sizeof(int4), hipMemcpyHostToDevice);
   if (e == hipSuccess)
@@ -1553,7 +1577,7 @@ dcopf_status validate_net(const dcopf_batch_network &n, int idx, size_t inst0) {
 
 dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network &n, int inst0) {
   BNet &N = hn.d;
-  auto &own = hn.owned;
+  DevPool &own = b->pool;
   bool ok = true;
   const int nb = n.n_bus, nl = n.n_line, ng = n.n_gen, B = n.n_inst;
   std::vector<int> cols(n.gen_bus, n.gen_bus + ng);
@@ -1649,11 +1673,12 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
   const size_t ldb = (size_t)round_up(nb, 4), nlp16 = (size_t)round_up(nl, 16);
   double *Hd = nullptr, *Dm = nullptr, *tmp = nullptr, *fdt = nullptr;
   int *dcols = nullptr;
-  chk(hipMalloc(&Hd, nlp16 * ldb * 8));
-  chk(hipMalloc(&Dm, Bp * ldb * 8));
-  chk(hipMalloc(&tmp, nlp * ldc * 8));
-  chk(hipMalloc(&fdt, Bp * nlp16 * 8));
-  chk(hipMalloc(&dcols, (size_t)nc * 4));
+  Hd = b->pool.get_n<double>(nlp16 * ldb);
+  Dm = b->pool.get_n<double>(Bp * ldb);
+  tmp = b->pool.get_n<double>(nlp * ldc);
+  fdt = b->pool.get_n<double>(Bp * nlp16);
+  dcols = b->pool.get_n<int>((size_t)nc);
+  if (!Hd || !Dm || !tmp || !fdt || !dcols) chk(hipErrorOutOfMemory);
   if (e == hipSuccess) {
     chk(hipMemsetAsync(Hd, 0, nlp16 * ldb * 8, s));
     chk(hipMemcpy2DAsync(Hd, ldb * 8, n.H, (size_t)nb * 8, (size_t)nb * 8, nl,
@@ -1708,11 +1733,11 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
     chk(hipMemsetAsync(N.X64, 0, Bp * ldc * 8, s));
     chk(hipStreamSynchronize(s));
   }
-  if (Hd) (void)hipFree(Hd);
-  if (Dm) (void)hipFree(Dm);
-  if (tmp) (void)hipFree(tmp);
-  if (fdt) (void)hipFree(fdt);
-  if (dcols) (void)hipFree(dcols);
+  b->pool.put(Hd);
+  b->pool.put(Dm);
+  b->pool.put(tmp);
+  b->pool.put(fdt);
+  b->pool.put(dcols);
   if (e != hipSuccess)
     return set_error(std::string("HIP error in batch setup: ") + hipGetErrorString(e)),
            DCOPF_E_HIP;
@@ -1768,6 +1793,7 @@ dcopf_status dcopf_batch_create(const dcopf_batch_network *nets, int32_t n_nets,
   b->opts = o;
   b->prm = BParams{o.rule, o.literal, o.beta1, o.beta2, o.eps, o.decay};
   b->stream = (hipStream_t)hip_stream;
+  b->pool.mem = current_devmem(hip_stream);
   b->nets.resize(n_nets);
   b->n_total = (int)total;
   int inst0 = 0;
@@ -1788,13 +1814,17 @@ dcopf_status dcopf_batch_create(const dcopf_batch_network *nets, int32_t n_nets,
     }
   b->n_units = (int)units.size();
   b->gcap = o.gamma_cap;
-  hipError_t e = hipMalloc(&b->d_nets, n_nets * sizeof(BNet));
-  if (e == hipSuccess) e = hipMalloc(&b->d_inst, inst.size() * sizeof(int2));
-  if (e == hipSuccess) e = hipMalloc(&b->d_units, units.size() * sizeof(int4));
+  b->d_nets = b->pool.get_n<BNet>(n_nets);
+  b->d_inst = b->pool.get_n<int2>(inst.size());
+  b->d_units = b->pool.get_n<int4>(units.size());
+  hipError_t e = (b->d_nets && b->d_inst && b->d_units) ? hipSuccess : hipErrorOutOfMemory;
   if (e == hipSuccess)
     e = hipMemcpy(b->d_units, units.data(), units.size() * sizeof(int4), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc(&b->sc, sizeof(BScal));
-  if (e == hipSuccess) e = hipMalloc(&b->gam, (size_t)b->gcap * total * 8);
+  if (e == hipSuccess) {
+    b->sc = b->pool.get_n<BScal>(1);
+    b->gam = b->pool.get_n<double>((size_t)b->gcap * total);
+    if (!b->sc || !b->gam) e = hipErrorOutOfMemory;
+  }
   if (e == hipSuccess)
     e = hipMemcpy(b->d_inst, inst.data(), inst.size() * sizeof(int2), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(b->gam, 0, (size_t)b->gcap * total * 8);
@@ -2049,8 +2079,8 @@ dcopf_status dcopf_batch_set_start_dev(dcopf_batch_t b, int32_t net, const float
   if (ld < 2 * N.n_l + 1) return set_error("ld must be >= 2 n_line + 1"), DCOPF_E_INVALID;
   DCOPF_HIP_TRY(hipStreamSynchronize(b->stream));
   DCOPF_HIP_TRY(reset_state(b, 0, net));
-  int *bad = nullptr;
-  DCOPF_HIP_TRY(hipMalloc(&bad, sizeof(int)));
+  int *bad = b->pool.get_n<int>(1);
+  if (!bad) return set_error("set_start_dev: device allocation failed"), DCOPF_E_NOMEM;
   hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), b->stream);
   dim3 vg((unsigned)std::min(64, (N.ldl + 255) / 256), (unsigned)N.B);
   if (e == hipSuccess) {
@@ -2061,12 +2091,56 @@ dcopf_status dcopf_batch_set_start_dev(dcopf_batch_t b, int32_t net, const float
   int hbad = 0;
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e == hipSuccess) e = hipMemcpy(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost);
-  (void)hipFree(bad);
+  b->pool.put(bad);
   if (e != hipSuccess)
     return set_error(std::string("set_start_dev: ") + hipGetErrorString(e)), DCOPF_E_HIP;
   std::fill(b->best.begin(), b->best.end(), -INFINITY);
   std::fill(b->best_iter.begin(), b->best_iter.end(), -1);
   if (hbad) return set_error("non-finite start values"), DCOPF_E_NONFINITE;
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_batch_adopt_better(dcopf_batch_t dst, int32_t dnet, dcopf_batch_t src,
+                                      int32_t snet, int32_t *kept) {
+  if (!dst || !src || dst == src || dnet < 0 || dnet >= (int)dst->nets.size() || snet < 0 ||
+      snet >= (int)src->nets.size())
+    return set_error("adopt: bad arguments"), DCOPF_E_INVALID;
+  const BNet &D = dst->nets[dnet].d, &S = src->nets[snet].d;
+  if (D.B != S.B || D.n_l != S.n_l || D.n_c != S.n_c || D.n_g != S.n_g || D.ldl != S.ldl)
+    return set_error("adopt: the two networks differ in shape"), DCOPF_E_INVALID;
+  if (dst->iters != src->iters)
+    return set_error("adopt: the two batches are at different iterations"), DCOPF_E_STATE;
+  if (dst->prm.rule != src->prm.rule)
+    return set_error("adopt: the two batches use different step rules"), DCOPF_E_INVALID;
+  // the same instances: equal total loads, instance by instance
+  {
+    std::vector<double> a(D.B), c(S.B);
+    DCOPF_HIP_TRY(hipMemcpy(a.data(), D.D, (size_t)D.B * 8, hipMemcpyDeviceToHost));
+    DCOPF_HIP_TRY(hipMemcpy(c.data(), S.D, (size_t)S.B * 8, hipMemcpyDeviceToHost));
+    for (int i = 0; i < D.B; ++i)
+      if (a[i] != c[i]) return set_error("adopt: instance loads differ"), DCOPF_E_INVALID;
+  }
+  DCOPF_HIP_TRY(hipStreamSynchronize(src->stream));
+  dcopf_status st = eval_bounds(src);
+  if (st == DCOPF_OK) st = eval_bounds(dst);
+  if (st != DCOPF_OK) return st;
+  int *dk = dst->pool.get_n<int>((size_t)D.B);
+  if (!dk) return set_error("adopt: device allocation failed"), DCOPF_E_NOMEM;
+  dim3 g((unsigned)std::min(64, (D.ldl + 255) / 256), (unsigned)D.B);
+  badopt_kernel<<<g, 256, 0, dst->stream>>>(D, S, (int)(dst->iters & 1), dk);
+  std::vector<int> hk(D.B);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(dst->stream);
+  if (e == hipSuccess) e = hipMemcpy(hk.data(), dk, (size_t)D.B * sizeof(int), hipMemcpyDeviceToHost);
+  dst->pool.put(dk);
+  if (e != hipSuccess) return set_error(std::string("adopt: ") + hipGetErrorString(e)), DCOPF_E_HIP;
+  for (int i = 0; i < D.B; ++i) {
+    if (hk[i]) {
+      dst->best[D.inst0 + i] = src->best[S.inst0 + i];
+      dst->best_iter[D.inst0 + i] = src->best_iter[S.inst0 + i];
+    }
+    if (kept) kept[i] = hk[i];
+  }
   return DCOPF_OK;
 }
 
@@ -2138,7 +2212,7 @@ dcopf_status dcopf_batch_repair(dcopf_batch_t b, int32_t net, const double *p_in
   auto &R = hn.rep;
   if (!R.ready) {
     bool ok = true;
-    std::vector<void *> &own = hn.owned;
+    DevPool &own = b->pool;
     R.pin = balloc<double>(own, (size_t)B * ng, &ok);
     R.p = balloc<double>(own, (size_t)B * ng, &ok);
     R.p0c = balloc<double>(own, (size_t)B * ng, &ok);

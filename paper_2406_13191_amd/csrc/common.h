@@ -9,6 +9,9 @@
 #include <utility>
 #include <cstdio>
 #include <string>
+#include <vector>
+
+#include "../../include/dcopf_dual.h"
 
 namespace dcopf {
 
@@ -17,6 +20,55 @@ constexpr int kWave = 64;
 // Thread-local last-error message, returned by dcopf_last_error().
 void set_error(const std::string &msg);
 const char *get_error();
+
+// Device memory of one handle: the caller's allocator (dcopf_set_allocator)
+// captured at create, or hipMalloc / hipFree.
+struct DevMem {
+  dcopf_alloc_fn fa = nullptr;
+  dcopf_free_fn ff = nullptr;
+  void *ctx = nullptr;
+  void *stream = nullptr;
+  void *get(size_t bytes) const {
+    void *p = nullptr;
+    if (!fa) return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+    return fa(bytes, stream, ctx);
+  }
+  void put(void *p, size_t bytes) const {
+    if (!p) return;
+    if (!ff) (void)hipFree(p);
+    else ff(p, bytes, stream, ctx);
+  }
+};
+
+// The calling thread's allocator, for work on `stream`.
+DevMem current_devmem(void *stream);
+
+// Every buffer a handle owns, returned together at destroy; temporaries are
+// returned one by one (put).
+struct DevPool {
+  DevMem mem;
+  std::vector<std::pair<void *, size_t>> bufs;
+  void *get(size_t bytes) {
+    if (bytes == 0) bytes = 1;
+    void *p = mem.get(bytes);
+    if (p) bufs.emplace_back(p, bytes);
+    return p;
+  }
+  template <typename T> T *get_n(size_t n) { return static_cast<T *>(get(n * sizeof(T))); }
+  void put(void *p) {
+    if (!p) return;
+    for (size_t i = bufs.size(); i-- > 0;)
+      if (bufs[i].first == p) {
+        mem.put(p, bufs[i].second);
+        bufs.erase(bufs.begin() + (long)i);
+        return;
+      }
+  }
+  void release_all() {
+    for (size_t i = bufs.size(); i-- > 0;) mem.put(bufs[i].first, bufs[i].second);
+    bufs.clear();
+  }
+};
 
 #define DCOPF_HIP_TRY(expr)                                                    \
   do {                                                                         \

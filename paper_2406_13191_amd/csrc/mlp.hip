@@ -266,24 +266,20 @@ struct dcopf_mlp_s {
         *dZ1 = nullptr;
   double *part = nullptr, *loss = nullptr;
   long long t = 0;
-  std::vector<void *> owned;
+  DevPool pool;  // every device buffer of the network (the caller's allocator)
 };
 
 namespace {
 
 template <typename T> T *malloc_m(dcopf_mlp_s *m, size_t n, bool *ok) {
-  void *p = nullptr;
-  if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
-    *ok = false;
-    return nullptr;
-  }
-  m->owned.push_back(p);
-  return static_cast<T *>(p);
+  T *p = m->pool.get_n<T>(std::max<size_t>(n, 1));
+  if (!p) *ok = false;
+  return p;
 }
 
 void free_mlp(dcopf_mlp_s *m) {
   if (!m) return;
-  for (void *p : m->owned) (void)hipFree(p);
+  m->pool.release_all();
   delete m;
 }
 
@@ -382,6 +378,7 @@ dcopf_status dcopf_mlp_create(const dcopf_mlp_config *cfg, void *hip_stream, dco
   auto *m = new dcopf_mlp_s();
   m->cfg = c;
   m->stream = (hipStream_t)hip_stream;
+  m->pool.mem = current_devmem(hip_stream);
   m->I = (int)round_up(c.n_in, 64);
   m->A1 = (int)round_up(c.h1, 64);
   m->A2 = (int)round_up(c.h2, 64);

@@ -481,8 +481,13 @@ extern "C" dcopf_status dcopf_ptdf(int32_t n_bus, int32_t n_line, const int32_t 
   const int n = n_bus - 1, T = (n + kT - 1) / kT, N = T * kT;
   const size_t NN = (size_t)N * N;
   Workspace ws;
+  const DevMem mem = current_devmem(hip_stream);
+  std::vector<std::pair<void *, size_t>> got;
   auto alloc = [&](void **p, size_t bytes) {
-    if (st == DCOPF_OK && hipMalloc(p, bytes) != hipSuccess) st = DCOPF_E_NOMEM;
+    if (st != DCOPF_OK) return;
+    *p = mem.get(bytes);
+    if (*p) got.emplace_back(*p, bytes);
+    else st = DCOPF_E_NOMEM;
   };
   alloc((void **)&ws.A, NN * 8);
   alloc((void **)&ws.W, NN * 8);
@@ -495,9 +500,7 @@ extern "C" dcopf_status dcopf_ptdf(int32_t n_bus, int32_t n_line, const int32_t 
   alloc((void **)&ws.flag, 4);
   if (st == DCOPF_OK) st = build(n_bus, n_line, fbus, tbus, b, slack, (hipStream_t)hip_stream, H, ws);
   else set_error("ptdf: device allocation failed");
-  void *ptrs[] = {ws.A, ws.W, ws.Yd, ws.b, ws.start, ws.adj, ws.fbus, ws.tbus, ws.flag};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
+  for (auto &g : got) mem.put(g.first, g.second);
   return st;
 }
 

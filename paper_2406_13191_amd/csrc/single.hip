@@ -38,6 +38,13 @@ thread_local std::string g_err;
 void set_error(const std::string &m) { g_err = m; }
 const char *get_error() { return g_err.c_str(); }
 
+thread_local DevMem g_mem;  // the allocator installed on this thread
+DevMem current_devmem(void *stream) {
+  DevMem m = g_mem;
+  m.stream = stream;
+  return m;
+}
+
 // Scalars of one iteration.  Two slots, indexed by the parity of the
 // iteration, so a kernel can read the previous iteration's slot while its
 // workgroup 0 writes the current one.
@@ -1578,14 +1585,10 @@ namespace {
 
 constexpr long long kGamCap = 1LL << 20;  // monitor ring capacity (power of 2)
 
-template <typename T> T *dalloc(size_t n, dcopf_status *st) {
-  void *p = nullptr;
-  if (n == 0) n = 1;
-  if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
-    *st = DCOPF_E_NOMEM;
-    return nullptr;
-  }
-  return static_cast<T *>(p);
+template <typename T> T *dalloc(DevPool &pool, size_t n, dcopf_status *st) {
+  T *p = pool.get_n<T>(n == 0 ? 1 : n);
+  if (!p) *st = DCOPF_E_NOMEM;
+  return p;
 }
 
 bool finite_all(const double *p, size_t n) {
@@ -1597,6 +1600,7 @@ bool finite_all(const double *p, size_t n) {
 }  // namespace
 
 struct dcopf_dual_s {
+  DevPool pool;  // every device buffer of the handle (the caller's allocator)
   int n_bus = 0, n_lines = 0, n_gen = 0, n_cols = 0, ldc = 0, ldl = 0;
   dcopf_opts opts{};
   StepParams prm{};
@@ -1949,18 +1953,7 @@ void free_handle(dcopf_dual_s *h) {
   if (!h) return;
   if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
-  void *ptrs[] = {h->P32, h->P32T, h->P64, h->P64T, h->fd, h->fmax, h->c, h->q,
-                  h->pmin, h->pmax, h->seg, h->gperm, h->mu_p, h->mu_m, h->v_p, h->v_m,
-                  h->s_p, h->s_m, h->vbuf, h->xbuf, h->v64b, h->part_a, h->part_b,
-                  h->part_c, h->part_d, h->counters, h->sc, h->gam, h->psum, h->pbar,
-                  h->xbar, h->ppart, h->primal, h->s_unit, h->v_unit, h->part_w};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
-  auto &R = h->rep;
-  void *rptrs[] = {R.pin, R.p, R.p0c, R.x, R.W, R.F, R.t, R.y, R.G, R.L, R.A, R.pc, R.pl,
-                   R.pos, R.rows, R.sgn, R.st, R.out};
-  for (void *p : rptrs)
-    if (p) (void)hipFree(p);
+  h->pool.release_all();
   delete h;
 }
 
@@ -1975,6 +1968,13 @@ extern "C" {
 
 const char *dcopf_last_error(void) { return get_error(); }
 
+dcopf_status dcopf_set_allocator(dcopf_alloc_fn alloc, dcopf_free_fn free, void *ctx) {
+  if ((alloc == nullptr) != (free == nullptr))
+    return set_error("set_allocator: give both functions or neither"), DCOPF_E_INVALID;
+  g_mem = DevMem{alloc, free, alloc ? ctx : nullptr, nullptr};
+  return DCOPF_OK;
+}
+
 dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void *hip_stream,
                                dcopf_dual_t *out) {
   if (!out) return set_error("out is NULL"), DCOPF_E_INVALID;
@@ -1984,6 +1984,7 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   if (st != DCOPF_OK) return st;
   auto *h = new dcopf_dual_s();
   h->stream = (hipStream_t)hip_stream;
+  h->pool.mem = current_devmem(hip_stream);
   h->opts = *o;
   h->prm = StepParams{o->rule, o->literal, o->alpha, o->rho, o->beta1, o->beta2, o->eps,
                       o->decay};
@@ -2100,51 +2101,51 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
   st = DCOPF_OK;
   const size_t panel = (size_t)nl * h->ldc, panelT = (size_t)nc * h->ldl;
   if (fp32) {
-    h->P32 = dalloc<float>(panel, &st);
-    if (!h->fused) h->P32T = dalloc<float>(panelT, &st);
+    h->P32 = dalloc<float>(h->pool, panel, &st);
+    if (!h->fused) h->P32T = dalloc<float>(h->pool, panelT, &st);
   } else {
-    h->P64 = dalloc<double>(panel, &st);
+    h->P64 = dalloc<double>(h->pool, panel, &st);
   }
-  h->P64T = dalloc<double>(panelT, &st);
-  h->fd = dalloc<double>(nl, &st);
-  h->fmax = dalloc<double>(nl, &st);
-  h->c = dalloc<double>(ng, &st);
-  h->q = dalloc<double>(ng, &st);
-  h->pmin = dalloc<double>(ng, &st);
-  h->pmax = dalloc<double>(ng, &st);
-  h->seg = dalloc<int>(nc + 1, &st);
-  h->gperm = dalloc<int>(ng, &st);
+  h->P64T = dalloc<double>(h->pool, panelT, &st);
+  h->fd = dalloc<double>(h->pool, nl, &st);
+  h->fmax = dalloc<double>(h->pool, nl, &st);
+  h->c = dalloc<double>(h->pool, ng, &st);
+  h->q = dalloc<double>(h->pool, ng, &st);
+  h->pmin = dalloc<double>(h->pool, ng, &st);
+  h->pmax = dalloc<double>(h->pool, ng, &st);
+  h->seg = dalloc<int>(h->pool, nc + 1, &st);
+  h->gperm = dalloc<int>(h->pool, ng, &st);
   double **state[] = {&h->mu_p, &h->mu_m, &h->v_p, &h->v_m, &h->s_p, &h->s_m};
-  for (double **s : state) *s = dalloc<double>(nl, &st);
-  h->vbuf = dalloc<unsigned char>((size_t)h->ldl * esz, &st);
-  h->xbuf = dalloc<unsigned char>((size_t)h->ldc * esz, &st);
-  h->v64b = dalloc<double>(h->ldl, &st);
-  h->part_a = dalloc<double>(4 * (size_t)std::max(h->grid_col, h->grid_units), &st);
-  if (h->fused) h->part_w = dalloc<unsigned char>((size_t)h->grid_rl * h->ldc * esz, &st);
-  h->part_b = dalloc<double>(2 * (size_t)h->n_line_part, &st);
-  h->part_c = dalloc<double>((size_t)h->grid_bnd_line, &st);
-  h->part_d = dalloc<double>((size_t)h->grid_bnd_col, &st);
-  h->counters = dalloc<unsigned>(8, &st);
-  h->sc = dalloc<DevScalars>(1, &st);
-  h->psum = dalloc<double>(ng, &st);
+  for (double **s : state) *s = dalloc<double>(h->pool, nl, &st);
+  h->vbuf = dalloc<unsigned char>(h->pool, (size_t)h->ldl * esz, &st);
+  h->xbuf = dalloc<unsigned char>(h->pool, (size_t)h->ldc * esz, &st);
+  h->v64b = dalloc<double>(h->pool, h->ldl, &st);
+  h->part_a = dalloc<double>(h->pool, 4 * (size_t)std::max(h->grid_col, h->grid_units), &st);
+  if (h->fused) h->part_w = dalloc<unsigned char>(h->pool, (size_t)h->grid_rl * h->ldc * esz, &st);
+  h->part_b = dalloc<double>(h->pool, 2 * (size_t)h->n_line_part, &st);
+  h->part_c = dalloc<double>(h->pool, (size_t)h->grid_bnd_line, &st);
+  h->part_d = dalloc<double>(h->pool, (size_t)h->grid_bnd_col, &st);
+  h->counters = dalloc<unsigned>(h->pool, 8, &st);
+  h->sc = dalloc<DevScalars>(h->pool, 1, &st);
+  h->psum = dalloc<double>(h->pool, ng, &st);
   if (o->qp_dual == DCOPF_QP_ITERATED) {
-    h->s_unit = dalloc<double>(ng, &st);
-    h->v_unit = dalloc<double>(ng, &st);
+    h->s_unit = dalloc<double>(h->pool, ng, &st);
+    h->v_unit = dalloc<double>(h->pool, ng, &st);
   }
-  h->pbar = dalloc<double>(ng, &st);
-  h->xbar = dalloc<double>((size_t)h->n_cols, &st);
-  h->ppart = dalloc<double>(5 * (size_t)kPrimalBlocks, &st);  // column and line partials
-  h->primal = dalloc<DevPrimal>(1, &st);
-  h->gam = dalloc<double>(kGamCap, &st);
+  h->pbar = dalloc<double>(h->pool, ng, &st);
+  h->xbar = dalloc<double>(h->pool, (size_t)h->n_cols, &st);
+  h->ppart = dalloc<double>(h->pool, 5 * (size_t)kPrimalBlocks, &st);  // column and line partials
+  h->primal = dalloc<DevPrimal>(h->pool, 1, &st);
+  h->gam = dalloc<double>(h->pool, kGamCap, &st);
   double *Hd = nullptr, *dd = nullptr;
   int *dcols = nullptr;
-  Hd = dalloc<double>((size_t)nl * nb, &st);
-  dd = dalloc<double>(nb, &st);
-  dcols = dalloc<int>(nc, &st);
+  Hd = dalloc<double>(h->pool, (size_t)nl * nb, &st);
+  dd = dalloc<double>(h->pool, nb, &st);
+  dcols = dalloc<int>(h->pool, nc, &st);
   auto cleanup_tmp = [&]() {
-    if (Hd) (void)hipFree(Hd);
-    if (dd) (void)hipFree(dd);
-    if (dcols) (void)hipFree(dcols);
+    h->pool.put(Hd);
+    h->pool.put(dd);
+    h->pool.put(dcols);
   };
   if (st != DCOPF_OK) {
     cleanup_tmp();
@@ -2205,12 +2206,13 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
         transpose_kernel<float><<<tg, dim3(32, 8), 0, s>>>(h->P32, nl, h->ldc, nc, h->ldl, h->P32T);
       // FP64 panel for the bound, transposed: gather into the (free) T slot first
       double *tmp = nullptr;
-      chk(hipMalloc(&tmp, panel * 8));
+      tmp = h->pool.get_n<double>(panel);
+      if (!tmp) chk(hipErrorOutOfMemory);
       if (tmp) {
         gather_kernel<double><<<gg, 256, 0, s>>>(Hd, nb, nl, dcols, nc, h->ldc, tmp);
         transpose_kernel<double><<<tg, dim3(32, 8), 0, s>>>(tmp, nl, h->ldc, nc, h->ldl, h->P64T);
         chk(hipStreamSynchronize(s));
-        (void)hipFree(tmp);
+        h->pool.put(tmp);
       }
     } else {
       gather_kernel<double><<<gg, 256, 0, s>>>(Hd, nb, nl, dcols, nc, h->ldc, h->P64);
@@ -2480,9 +2482,15 @@ dcopf_status dcopf_dual_time_phases(dcopf_dual_t h, int64_t n, double *ms_out) {
   // iteration) or the partials of w = P^T v (read-once iteration)
   void *vbuf = h->fused ? h->part_w : h->vbuf;
   const size_t vbytes = h->fused ? (size_t)h->grid_rl * h->ldc * esz : (size_t)h->ldl * esz;
-  DCOPF_HIP_TRY(hipMalloc(&save, 6 * nl * 8));
-  DCOPF_HIP_TRY(hipMalloc(&vsave, vbytes));
-  DCOPF_HIP_TRY(hipMalloc(&ssave, sizeof(DevScalars)));
+  save = h->pool.get_n<double>(6 * nl);
+  vsave = h->pool.get(vbytes);
+  ssave = h->pool.get_n<DevScalars>(1);
+  if (!save || !vsave || !ssave) {
+    h->pool.put(save);
+    h->pool.put(vsave);
+    h->pool.put(ssave);
+    return set_error("time_phases: device allocation failed"), DCOPF_E_NOMEM;
+  }
   double *arrs[] = {h->mu_p, h->mu_m, h->v_p, h->v_m, h->s_p, h->s_m};
   hipStream_t s = h->stream;
   for (int i = 0; i < 6; ++i)
@@ -2514,9 +2522,9 @@ dcopf_status dcopf_dual_time_phases(dcopf_dual_t h, int64_t n, double *ms_out) {
     }
   for (int phase = 0; phase < 2; ++phase) ms_out[phase] = acc[phase] / n;
   for (auto &e : ev) (void)hipEventDestroy(e);
-  (void)hipFree(save);
-  (void)hipFree(vsave);
-  (void)hipFree(ssave);
+  h->pool.put(save);
+  h->pool.put(vsave);
+  h->pool.put(ssave);
   return DCOPF_OK;
 }
 
@@ -2578,24 +2586,24 @@ dcopf_status dcopf_dual_repair(dcopf_dual_t h, const double *p_in, int32_t max_r
   auto &R = h->rep;
   if (!R.ready) {
     dcopf_status st = DCOPF_OK;
-    R.pin = dalloc<double>(ng, &st);
-    R.p = dalloc<double>(ng, &st);
-    R.p0c = dalloc<double>(ng, &st);
-    R.x = dalloc<double>(nc, &st);
-    R.W = dalloc<double>(nc, &st);
-    R.F = dalloc<double>(nl, &st);
-    R.t = dalloc<double>(kRepRows, &st);
-    R.y = dalloc<double>(kRepRows, &st);
-    R.G = dalloc<double>((size_t)kRepRows * kRepRows, &st);
-    R.L = dalloc<double>((size_t)kRepRows * kRepRows, &st);
-    R.A = dalloc<double>((size_t)kRepRows * h->ldc, &st);
-    R.pc = dalloc<double>(2 * (size_t)kPrimalBlocks, &st);
-    R.pl = dalloc<double>(3 * (size_t)kPrimalBlocks, &st);
-    R.pos = dalloc<int>(nl, &st);
-    R.rows = dalloc<int>(kRepRows, &st);
-    R.sgn = dalloc<int>(kRepRows, &st);
-    R.st = dalloc<RepairState>(1, &st);
-    R.out = dalloc<DevRepair>(1, &st);
+    R.pin = dalloc<double>(h->pool, ng, &st);
+    R.p = dalloc<double>(h->pool, ng, &st);
+    R.p0c = dalloc<double>(h->pool, ng, &st);
+    R.x = dalloc<double>(h->pool, nc, &st);
+    R.W = dalloc<double>(h->pool, nc, &st);
+    R.F = dalloc<double>(h->pool, nl, &st);
+    R.t = dalloc<double>(h->pool, kRepRows, &st);
+    R.y = dalloc<double>(h->pool, kRepRows, &st);
+    R.G = dalloc<double>(h->pool, (size_t)kRepRows * kRepRows, &st);
+    R.L = dalloc<double>(h->pool, (size_t)kRepRows * kRepRows, &st);
+    R.A = dalloc<double>(h->pool, (size_t)kRepRows * h->ldc, &st);
+    R.pc = dalloc<double>(h->pool, 2 * (size_t)kPrimalBlocks, &st);
+    R.pl = dalloc<double>(h->pool, 3 * (size_t)kPrimalBlocks, &st);
+    R.pos = dalloc<int>(h->pool, nl, &st);
+    R.rows = dalloc<int>(h->pool, kRepRows, &st);
+    R.sgn = dalloc<int>(h->pool, kRepRows, &st);
+    R.st = dalloc<RepairState>(h->pool, 1, &st);
+    R.out = dalloc<DevRepair>(h->pool, 1, &st);
     if (st != DCOPF_OK) return set_error("device allocation failed"), st;
     R.ready = true;
   }
@@ -2672,6 +2680,13 @@ dcopf_status dcopf_dual_info(dcopf_dual_t h, int32_t *n_cols, int64_t *iters) {
   if (!h) return set_error("null handle"), DCOPF_E_INVALID;
   if (n_cols) *n_cols = h->n_cols;
   if (iters) *iters = h->iters;
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_dual_scheme(dcopf_dual_t h, int32_t *scheme, int32_t *line_groups) {
+  if (!h) return set_error("null handle"), DCOPF_E_INVALID;
+  if (scheme) *scheme = h->fused ? DCOPF_SCHEME_READ_ONCE : DCOPF_SCHEME_TWO_PASS;
+  if (line_groups) *line_groups = h->fused ? h->grid_rl : 0;
   return DCOPF_OK;
 }
 

@@ -10,9 +10,10 @@ The ascent of Section 3.3 starts from lambda = mu = 0.  Here a network
 3. training: standardised inputs and targets, mean squared error, Adam, on
    the GPU with the library's own forward/backward kernels;
 4. use: predicted multipliers, mu projected onto mu >= 0, set as the start of
-   a batched solve.  Fallback: a cold start runs beside it, and after
-   ``fallback_at`` iterations each instance keeps whichever trajectory has
-   the larger exact bound.  Every bound reported is an exact dual value.
+   a batched solve.  Fallback (``run_with_fallback``): a cold start runs
+   beside it, and after ``fallback_at`` iterations each instance keeps, on
+   the device, whichever trajectory has the larger exact bound.  Every bound
+   reported is an exact dual value.
 
 Every numerical step runs in the HIP library; this module moves arrays.
 """
@@ -164,8 +165,8 @@ def run_to_gap(base, D, opt, alpha, rho, start=None, max_iters=5000, check_every
     on the host; or from a device tensor start of rows [mu+, mu-, lambda]).
     Returns (iteration of the first exact bound within 0.1 % of opt per
     instance, -1 if none; exact bound at iteration probe_at).  If ``stats``
-    is a dict it receives the iterations run and their wall time, the start
-    hand-off included."""
+    is a dict it receives the iterations run, their wall time (the start
+    hand-off included) and the wall time at each checked iteration."""
     C = np.tile(base.c, (D.shape[0], 1))
     net = _abi.BatchNetwork(base, D, C, None, alpha=alpha, rho=rho)
     with _abi.BatchSolver([net], stream=stream, graph_iters=10, gamma_cap=1) as b:
@@ -179,12 +180,14 @@ def run_to_gap(base, D, opt, alpha, rho, start=None, max_iters=5000, check_every
         it = 0
         vals = b.bound()
         hit[(opt - vals) <= 1e-3 * np.abs(opt)] = 0
+        seconds_at = {0: time.perf_counter() - t0}
         while it < max_iters and np.any(hit < 0):
             b.step(check_every)
             it += check_every
             vals = b.bound()
             newly = (hit < 0) & ((opt - vals) <= 1e-3 * np.abs(opt))
             hit[newly] = it
+            seconds_at[it] = time.perf_counter() - t0
             if it == probe_at:
                 probe = vals.copy()
         if probe is None:
@@ -192,7 +195,74 @@ def run_to_gap(base, D, opt, alpha, rho, start=None, max_iters=5000, check_every
         if stats is not None:
             stats["iterations"] = it
             stats["seconds"] = time.perf_counter() - t0
+            stats["seconds_at"] = seconds_at
     return hit, probe
+
+
+def run_with_fallback(base, D, opt, alpha, rho, start, fallback_at=100, max_iters=5000,
+                      check_every=10, stream=None):
+    """The warm start with its fallback, in one pipeline on the device: the
+    scenarios D run from ``start`` (a device tensor of rows [mu+, mu-,
+    lambda]) and, beside them, from the cold start of Algorithm 1 for
+    ``fallback_at`` iterations; then, per instance, the trajectory with the
+    larger exact bound is kept on the device (dcopf_batch_adopt_better) and
+    the cold shadow is destroyed; the kept trajectories continue alone.
+
+    Returns a dict: ``hit`` (iteration of the first exact bound within 0.1 %
+    of opt per instance, -1 if none; before the fallback either trajectory
+    counts), ``kept_cold`` (instances that continued from the cold start),
+    ``bound_after`` (exact bound of the kept trajectory at ``fallback_at``),
+    ``seconds_at`` (wall time from the hand-off of the start to each checked
+    iteration, the shadow's iterations included), ``iterations`` and
+    ``instance_iterations`` (the shadow's included)."""
+    C = np.tile(base.c, (D.shape[0], 1))
+    net_w = _abi.BatchNetwork(base, D, C, None, alpha=alpha, rho=rho)
+    net_c = _abi.BatchNetwork(base, D, C, None, alpha=alpha, rho=rho)
+    n = D.shape[0]
+    hit = np.full(n, -1, np.int64)
+    seconds_at = {}
+    inst_iters = 0
+
+    def record(it, vals):
+        hit[(hit < 0) & ((opt - vals) <= 1e-3 * np.abs(opt))] = it
+
+    with _abi.BatchSolver([net_w], stream=stream, graph_iters=10, gamma_cap=1) as w:
+        cold = _abi.BatchSolver([net_c], stream=stream, graph_iters=10, gamma_cap=1)
+        try:
+            t0 = time.perf_counter()
+            w.set_start_dev(0, start.data_ptr(), start.shape[1])
+            it = 0
+            for b in (w, cold):
+                record(0, b.bound())
+            seconds_at[0] = time.perf_counter() - t0
+            while it < fallback_at:
+                k = min(check_every, fallback_at - it)
+                it += k
+                for b in (w, cold):
+                    b.step(k)
+                    record(it, b.bound())
+                inst_iters += 2 * n * k
+                seconds_at[it] = time.perf_counter() - t0
+            kept_cold = w.adopt_better(0, cold, 0).astype(bool)
+        finally:
+            cold.close()
+        bound_after = w.bound()
+        seconds_at[it] = time.perf_counter() - t0
+        while it < max_iters and np.any(hit < 0):
+            w.step(check_every)
+            it += check_every
+            inst_iters += n * check_every
+            record(it, w.bound())
+            seconds_at[it] = time.perf_counter() - t0
+    return dict(hit=hit, kept_cold=kept_cold, bound_after=bound_after, seconds_at=seconds_at,
+                iterations=it, instance_iterations=inst_iters)
+
+
+def median_seconds(hit, seconds_at, cap_seconds):
+    """Median over instances of the wall time at which each was certified
+    (unreached instances count at ``cap_seconds``)."""
+    t = np.array([seconds_at[h] if h >= 0 else cap_seconds for h in hit])
+    return float(np.median(t))
 
 
 def combine_with_fallback(hit_cold, probe_cold, hit_warm, probe_warm, probe_at):

@@ -76,3 +76,18 @@ def test_destroy_null_is_noop():
     from paper_2406_13191_amd import _abi
     _abi.lib.dcopf_dual_destroy(None)
     assert _abi.lib.dcopf_dual_step(None, 1) == -1
+
+
+def test_set_allocator_needs_both_functions_or_neither():
+    lib = ctypes.CDLL(LIB)
+    alloc_t = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+    free_t = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                              ctypes.c_void_p)
+    lib.dcopf_set_allocator.restype = ctypes.c_int
+    lib.dcopf_set_allocator.argtypes = [alloc_t, free_t, ctypes.c_void_p]
+    a = alloc_t(lambda n, s, c: None)
+    f = free_t(lambda p, n, s, c: None)
+    assert lib.dcopf_set_allocator(a, free_t(), None) == -1
+    assert lib.dcopf_set_allocator(alloc_t(), f, None) == -1
+    assert lib.dcopf_set_allocator(a, f, None) == 0
+    assert lib.dcopf_set_allocator(alloc_t(), free_t(), None) == 0

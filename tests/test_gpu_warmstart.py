@@ -81,8 +81,18 @@ def test_warm_start_gains_over_cold_start():
     print(f"[warm] median iterations to 0.1 %: cold {mc}, warm {mw}, warm+fallback {mf}; "
           f"warm kept for {used.mean():.2f} of instances", flush=True)
     assert mf < mc
-    # the fallback never does worse than cold at the probe
-    assert np.all(np.maximum(pw, pc) >= pc)
+    # the fallback as one pipeline on the device: warm and cold shadow side
+    # by side for 100 iterations, then per instance the trajectory with the
+    # larger exact bound is kept (the shadow dropped).  Both runs are
+    # deterministic, so the kept bound is exactly max(warm, cold) at 100,
+    # the cold one was kept exactly where its bound was larger, and the
+    # iterations to the gap equal the two separate runs merged
+    res = W.run_with_fallback(base, Dev, opt, r["alpha"], r["rho"], start, 100, 5000, 10)
+    np.testing.assert_array_equal(res["kept_cold"], pc > pw)
+    np.testing.assert_array_equal(res["bound_after"], np.maximum(pw, pc))
+    assert np.all(res["bound_after"] >= pc)
+    np.testing.assert_array_equal(res["hit"], hf)
+    assert res["instance_iterations"] >= 2 * 100 * Dev.shape[0]
 
 
 def test_device_start_equals_host_start():
