@@ -540,11 +540,13 @@ def bench_warmstart(args, stream, prep):
                  "the 1000-iteration trend window by enough for the bounds to settle")
     log(f"targets: {ok.sum()} of {ok.size} scenarios kept, {t_data:.1f} s")
     Dtr, T = Dtr[ok], T[ok]
-    sx, st = W.Standardizer.fit(Dtr), W.Standardizer.fit(T)
-    X = torch.tensor(sx.apply(Dtr), dtype=torch.float32, device="cuda")
-    Y = torch.tensor(st.apply(T), dtype=torch.float32, device="cuda")
     dims = (base.n_bus, 1024, 1024, 2 * base.n_line + 1)
     model = _abi.MLP(*dims, max_batch=256, stream=stream.cuda_stream)
+    # standardised inputs and targets, by the library on the device
+    Xraw = torch.tensor(Dtr, dtype=torch.float32, device="cuda")
+    Traw = torch.tensor(T, dtype=torch.float32, device="cuda")
+    sx, st = W.Standardizer.fit(model, Xraw), W.Standardizer.fit(model, Traw)
+    X, Y = sx.apply(model, Xraw), st.apply(model, Traw)
     model.set_params([p.astype(np.float32) for p in
                       W.he_init(np.random.default_rng(0), dims)])
     ms_step = model.time_train(X[:256].data_ptr(), Y[:256].data_ptr(), 256, 20)
@@ -552,7 +554,7 @@ def bench_warmstart(args, stream, prep):
     # inference for the held-out scenarios: the standardisations folded into
     # the first and last layers, raw loads in, raw multipliers out, handed to
     # the batch on the device
-    model.set_params(W.fold_standardizers(model.get_params(), sx, st))
+    W.fold_standardizers(model, sx, st)
     keep = np.isfinite(opt)
     Dev, opt = Dev[keep], opt[keep]
     torch.cuda.synchronize()

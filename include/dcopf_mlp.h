@@ -65,6 +65,34 @@ dcopf_status dcopf_mlp_get_grads(dcopf_mlp_t m, float *grads, size_t len);
 dcopf_status dcopf_mlp_time_train(dcopf_mlp_t m, const float *X, const float *T,
                                   int32_t batch, int32_t n, double *ms);
 
+/* Standardisation of the data the network learns from (a scaling of each
+ * input and each target, so that every column has mean 0 and spread 1):
+ *
+ * column_stats: per column of A [rows x cols] (device FP32, row-major) its
+ *   mean and standard deviation (population form, FP64 sums), written to
+ *   mean[cols] and std[cols] (device FP32); a deviation of at most
+ *   1e-12 (|mean| + 1) becomes 1 (a constant column is left unscaled).
+ * standardize: out = (A - mean) / std per column (inverse = 0), or
+ *   out = A * std + mean (inverse = 1); A, out [rows x cols] device FP32
+ *   (out may equal A).
+ * fold_standardizers: the parameters become those of the same network
+ *   acting on raw inputs and returning raw outputs, for a network trained
+ *   on standardised ones: W1 / std_x (per input column), b1 - W1 (mean_x /
+ *   std_x), std_y W3 (per output row), std_y b3 + mean_y; FP64 sums.  The
+ *   Adam moments are reset (the network is then for inference).  Device
+ *   FP32 vectors x_mean, x_std [n_in], y_mean, y_std [n_out].
+ *
+ * All asynchronous on the handle's stream; DCOPF_E_INVALID for NULL
+ * pointers or sizes out of range.                                          */
+dcopf_status dcopf_mlp_column_stats(dcopf_mlp_t m, const float *A, int32_t rows, int32_t cols,
+                                    float *mean, float *std);
+dcopf_status dcopf_mlp_standardize(dcopf_mlp_t m, const float *A, int32_t rows, int32_t cols,
+                                   const float *mean, const float *std, int32_t inverse,
+                                   float *out);
+dcopf_status dcopf_mlp_fold_standardizers(dcopf_mlp_t m, const float *x_mean,
+                                          const float *x_std, const float *y_mean,
+                                          const float *y_std);
+
 void dcopf_mlp_destroy(dcopf_mlp_t m);   /* NULL is a no-op                  */
 
 #ifdef __cplusplus

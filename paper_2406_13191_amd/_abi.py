@@ -610,6 +610,12 @@ def _bind_mlp():
         "dcopf_mlp_get_grads": (C.c_int, [C.c_void_p, P(C.c_float), C.c_size_t]),
         "dcopf_mlp_time_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                            C.c_int32, P(C.c_double)]),
+        "dcopf_mlp_column_stats": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                            C.c_void_p, C.c_void_p]),
+        "dcopf_mlp_standardize": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                           C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+        "dcopf_mlp_fold_standardizers": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
+                                                  C.c_void_p, C.c_void_p]),
         "dcopf_mlp_destroy": (None, [C.c_void_p]),
     }
     for name, (res, args) in sig.items():
@@ -699,6 +705,20 @@ class MLP:
         check(lib.dcopf_mlp_time_train(self._h, C.c_void_p(x_ptr), C.c_void_p(t_ptr),
                                        int(batch), int(n), C.byref(ms)))
         return ms.value
+
+    def column_stats(self, a_ptr: int, rows: int, cols: int, mean_ptr: int, std_ptr: int):
+        check(lib.dcopf_mlp_column_stats(self._h, C.c_void_p(a_ptr), int(rows), int(cols),
+                                         C.c_void_p(mean_ptr), C.c_void_p(std_ptr)))
+
+    def standardize(self, a_ptr: int, rows: int, cols: int, mean_ptr: int, std_ptr: int,
+                    out_ptr: int, inverse=False):
+        check(lib.dcopf_mlp_standardize(self._h, C.c_void_p(a_ptr), int(rows), int(cols),
+                                        C.c_void_p(mean_ptr), C.c_void_p(std_ptr),
+                                        int(bool(inverse)), C.c_void_p(out_ptr)))
+
+    def fold_standardizers(self, xm_ptr: int, xs_ptr: int, ym_ptr: int, ys_ptr: int):
+        check(lib.dcopf_mlp_fold_standardizers(self._h, C.c_void_p(xm_ptr), C.c_void_p(xs_ptr),
+                                               C.c_void_p(ym_ptr), C.c_void_p(ys_ptr)))
 
 
 # ---------------------------------------------------------------------------

@@ -238,6 +238,71 @@ __global__ __launch_bounds__(256) void wcopy_kernel(const float *__restrict__ W,
   for (int r = r4; r < 64; r += 4) Wt[(size_t)(i0 + r) * OUTp + o0 + c] = t[c][r];
 }
 
+// Column mean and standard deviation of A [rows][cols] (FP64 sums; one
+// workgroup per 64 columns, its four wavefronts each a quarter of the rows,
+// lane = column, quarters combined in order).
+__global__ __launch_bounds__(256) void colstats_kernel(const float *__restrict__ A, int rows,
+                                                       int cols, float *__restrict__ mean,
+                                                       float *__restrict__ sd) {
+  __shared__ double q[2][4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
+  const int cc = c < cols ? c : 0;
+  const int per = (rows + 3) / 4, r0 = wave * per, r1 = min(rows, r0 + per);
+  double s = 0.0;
+  for (int r = r0; r < r1; ++r) s += (double)A[(size_t)r * cols + cc];
+  q[0][wave][lane] = s;
+  __syncthreads();
+  const double mu = (((q[0][0][lane] + q[0][1][lane]) + q[0][2][lane]) + q[0][3][lane]) / rows;
+  double v = 0.0;
+  for (int r = r0; r < r1; ++r) {
+    const double d = (double)A[(size_t)r * cols + cc] - mu;
+    v += d * d;
+  }
+  q[1][wave][lane] = v;
+  __syncthreads();
+  if (wave == 0 && c < cols) {
+    const double var = (((q[1][0][lane] + q[1][1][lane]) + q[1][2][lane]) + q[1][3][lane]) / rows;
+    const double sdv = sqrt(var);
+    mean[c] = (float)mu;
+    sd[c] = sdv > 1e-12 * (fabs(mu) + 1.0) ? (float)sdv : 1.0f;
+  }
+}
+
+__global__ void standardize_kernel(const float *__restrict__ A, int rows, int cols,
+                                   const float *__restrict__ mean, const float *__restrict__ sd,
+                                   int inverse, float *__restrict__ out) {
+  const size_t n = (size_t)rows * cols;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % cols);
+    out[i] = inverse ? A[i] * sd[c] + mean[c] : (A[i] - mean[c]) / sd[c];
+  }
+}
+
+// First layer on raw inputs: b1 <- b1 - W1 (mean_x / std_x) (one thread per
+// output row, FP64 sum in column order), then W1 <- W1 / std_x.
+__global__ void fold_in_kernel(float *__restrict__ W1, float *__restrict__ b1, int out, int in,
+                               const float *__restrict__ mx, const float *__restrict__ sx) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= out) return;
+  float *w = W1 + (size_t)o * in;
+  double t = 0.0;
+  for (int i = 0; i < in; ++i) t += (double)w[i] * ((double)mx[i] / (double)sx[i]);
+  b1[o] = (float)((double)b1[o] - t);
+  for (int i = 0; i < in; ++i) w[i] = (float)((double)w[i] / (double)sx[i]);
+}
+
+// Last layer to raw outputs: W3 <- std_y W3 (per row), b3 <- std_y b3 + mean_y.
+__global__ void fold_out_kernel(float *__restrict__ W3, float *__restrict__ b3, int out, int in,
+                                const float *__restrict__ my, const float *__restrict__ sy) {
+  const int o = blockIdx.y;
+  const double so = sy[o];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < in; i += gridDim.x * blockDim.x)
+    W3[(size_t)o * in + i] = (float)(so * (double)W3[(size_t)o * in + i]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) b3[o] = (float)(so * (double)b3[o] + (double)my[o]);
+}
+
 // compact Y [batch][n_out] from the padded Y
 __global__ void yout_kernel(const float *__restrict__ Yp, int O, int batch, int n_out,
                             float *__restrict__ Y) {
@@ -543,6 +608,46 @@ dcopf_status dcopf_mlp_time_train(dcopf_mlp_t m, const float *X, const float *T,
   refresh_weights(m);
   DCOPF_HIP_TRY(hipGetLastError());
   DCOPF_HIP_TRY(hipStreamSynchronize(m->stream));
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_mlp_column_stats(dcopf_mlp_t m, const float *A, int32_t rows, int32_t cols,
+                                    float *mean, float *std) {
+  if (!m || !A || !mean || !std || rows < 1 || cols < 1)
+    return set_error("column_stats: bad arguments"), DCOPF_E_INVALID;
+  colstats_kernel<<<(cols + 63) / 64, 256, 0, m->stream>>>(A, rows, cols, mean, std);
+  DCOPF_HIP_TRY(hipGetLastError());
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_mlp_standardize(dcopf_mlp_t m, const float *A, int32_t rows, int32_t cols,
+                                   const float *mean, const float *std, int32_t inverse,
+                                   float *out) {
+  if (!m || !A || !mean || !std || !out || rows < 1 || cols < 1)
+    return set_error("standardize: bad arguments"), DCOPF_E_INVALID;
+  const size_t n = (size_t)rows * cols;
+  const int g = (int)std::min<size_t>(4096, (n + 255) / 256);
+  standardize_kernel<<<g, 256, 0, m->stream>>>(A, rows, cols, mean, std, inverse ? 1 : 0, out);
+  DCOPF_HIP_TRY(hipGetLastError());
+  return DCOPF_OK;
+}
+
+dcopf_status dcopf_mlp_fold_standardizers(dcopf_mlp_t m, const float *x_mean,
+                                          const float *x_std, const float *y_mean,
+                                          const float *y_std) {
+  if (!m || !x_mean || !x_std || !y_mean || !y_std)
+    return set_error("fold_standardizers: null pointer"), DCOPF_E_INVALID;
+  const dcopf_mlp_config &c = m->cfg;
+  hipStream_t s = m->stream;
+  fold_in_kernel<<<(c.h1 + 255) / 256, 256, 0, s>>>(m->p + m->off[0], m->p + m->off[1], c.h1,
+                                                     c.n_in, x_mean, x_std);
+  fold_out_kernel<<<dim3((unsigned)std::min(64, (c.h2 + 255) / 256), (unsigned)c.n_out), 256, 0,
+                    s>>>(m->p + m->off[4], m->p + m->off[5], c.n_out, c.h2, y_mean, y_std);
+  DCOPF_HIP_TRY(hipMemsetAsync(m->mo, 0, m->off[6] * 4, s));
+  DCOPF_HIP_TRY(hipMemsetAsync(m->ve, 0, m->off[6] * 4, s));
+  m->t = 0;
+  refresh_weights(m);
+  DCOPF_HIP_TRY(hipGetLastError());
   return DCOPF_OK;
 }
 

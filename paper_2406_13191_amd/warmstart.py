@@ -29,20 +29,34 @@ from . import _abi, synth
 
 @dataclasses.dataclass
 class Standardizer:
-    mean: np.ndarray
-    std: np.ndarray
+    """Per-column mean and spread of a device matrix (torch tensors on the
+    GPU), computed and applied by the library (dcopf_mlp_column_stats /
+    dcopf_mlp_standardize)."""
+    mean: "object"
+    std: "object"
 
     @staticmethod
-    def fit(a: np.ndarray) -> "Standardizer":
-        mean = a.mean(0)
-        std = a.std(0)
-        return Standardizer(mean, np.where(std > 1e-12 * (np.abs(mean) + 1), std, 1.0))
+    def fit(model: "_abi.MLP", A) -> "Standardizer":
+        import torch
+        rows, cols = A.shape
+        mean = torch.empty(cols, dtype=torch.float32, device=A.device)
+        std = torch.empty(cols, dtype=torch.float32, device=A.device)
+        model.column_stats(A.data_ptr(), rows, cols, mean.data_ptr(), std.data_ptr())
+        return Standardizer(mean, std)
 
-    def apply(self, a):
-        return (a - self.mean) / self.std
+    def apply(self, model: "_abi.MLP", A, inverse=False):
+        import torch
+        out = torch.empty_like(A)
+        model.standardize(A.data_ptr(), A.shape[0], A.shape[1], self.mean.data_ptr(),
+                          self.std.data_ptr(), out.data_ptr(), inverse)
+        return out
 
-    def invert(self, a):
-        return a * self.std + self.mean
+
+def fold_standardizers(model: "_abi.MLP", sx: Standardizer, st: Standardizer):
+    """The model's parameters become those of the same network acting on raw
+    loads and returning raw multipliers (dcopf_mlp_fold_standardizers)."""
+    model.fold_standardizers(sx.mean.data_ptr(), sx.std.data_ptr(), st.mean.data_ptr(),
+                             st.std.data_ptr())
 
 
 def he_init(rng, dims):
@@ -114,34 +128,20 @@ def train(model: "_abi.MLP", X, T, epochs, batch, lr, seed=0, lr_decay=0.9, log=
     return losses
 
 
-def predict(model: "_abi.MLP", X, sx: Standardizer, st: Standardizer, n_line, batch=256):
-    """Warm-start multipliers for load vectors X [N, n_bus] (host): returns
-    (lambda [N], mu+ [N, n_line], mu- [N, n_line]) with mu >= 0."""
+def predict(model: "_abi.MLP", X, sx: Standardizer, st: Standardizer, batch=256):
+    """Warm-start rows [N, 2 n_line + 1] = [mu+, mu-, lambda] on the device
+    for raw load vectors X [N, n_bus] (host), from a model trained on
+    standardised data: inputs standardised and outputs mapped back by the
+    library (mu is projected onto mu >= 0 where the rows become a start)."""
     import torch
     N = X.shape[0]
-    Xn = torch.tensor(sx.apply(X), dtype=torch.float32, device="cuda")
-    Y = torch.empty((N, 2 * n_line + 1), dtype=torch.float32, device="cuda")
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    Xn = sx.apply(model, Xd)
+    Y = torch.empty((N, model.dims[-1]), dtype=torch.float32, device="cuda")
     for s in range(0, N, batch):
         n = min(batch, N - s)
         model.forward(Xn[s:s + n].data_ptr(), n, Y[s:s + n].data_ptr())
-    torch.cuda.synchronize()
-    Yh = st.invert(Y.cpu().numpy().astype(np.float64))
-    mp = np.maximum(Yh[:, :n_line], 0.0)
-    mm = np.maximum(Yh[:, n_line:2 * n_line], 0.0)
-    return Yh[:, -1], mp, mm
-
-
-def fold_standardizers(params, sx: Standardizer, st: Standardizer):
-    """Parameters of the same network acting on raw loads and returning raw
-    multipliers: the input standardisation folded into the first layer
-    (W1 / std_x per input, b1 - W1 (mean_x / std_x)) and the output one into
-    the last (std_y W3 per output, std_y b3 + mean_y)."""
-    W1, b1, W2, b2, W3, b3 = [np.asarray(p, np.float64) for p in params]
-    W1f = W1 / sx.std[None, :]
-    b1f = b1 - W1 @ (sx.mean / sx.std)
-    W3f = st.std[:, None] * W3
-    b3f = st.std * b3 + st.mean
-    return [a.astype(np.float32) for a in (W1f, b1f, W2, b2, W3f, b3f)]
+    return st.apply(model, Y, inverse=True)
 
 
 def predict_dev(model: "_abi.MLP", X, batch=256):

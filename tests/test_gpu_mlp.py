@@ -175,3 +175,51 @@ def test_training_reduces_loss():
         last = m.train_step(Xd.data_ptr(), Td.data_ptr(), batch, 1e-3, want_loss=True)
     print(f"loss {first:.4e} -> {last:.4e}", flush=True)
     assert last < 0.1 * first
+
+
+def test_standardize_and_fold_on_device():
+    """Library-side standardisation: column means and deviations against
+    numpy's (a constant column keeps deviation 1), the standardisation and
+    its inverse, and the folded parameters against the same algebra written
+    out in FP64 here, which make the network on raw inputs equal the
+    original on standardised inputs mapped back (FP64 reference forward)."""
+    import torch
+    A = _abi()
+    rng = np.random.default_rng(4)
+    dims = (12, 16, 16, 9)
+    params = [p.astype(np.float32).astype(np.float64) for p in R.init_params(rng, dims)]
+    params[1] = rng.normal(0, 0.1, dims[1])
+    params[5] = rng.normal(0, 0.1, dims[3])
+    X = rng.lognormal(0.0, 1.0, (40, dims[0]))
+    X[:, 3] = 2.5
+    T = rng.normal(3.0, 2.0, (40, dims[-1]))
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    Td = torch.tensor(T, dtype=torch.float32, device="cuda")
+    X32, T32 = X.astype(np.float32).astype(np.float64), T.astype(np.float32).astype(np.float64)
+    with A.MLP(*dims, max_batch=64) as m:
+        from paper_2406_13191_amd import warmstart as W
+        m.set_params(params)
+        sx, st = W.Standardizer.fit(m, Xd), W.Standardizer.fit(m, Td)
+        Xn = sx.apply(m, Xd)
+        back = sx.apply(m, Xn, inverse=True)
+        mx, sxd = sx.mean.cpu().numpy(), sx.std.cpu().numpy()
+        my, syd = st.mean.cpu().numpy(), st.std.cpu().numpy()
+        W.fold_standardizers(m, sx, st)
+        folded = [np.asarray(p, np.float64) for p in m.get_params()]
+        Xn, back = Xn.cpu().numpy(), back.cpu().numpy()
+    ref_std = np.where(np.arange(dims[0]) == 3, 1.0, X32.std(0))
+    np.testing.assert_allclose(mx, X32.mean(0), rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(sxd, ref_std, rtol=1e-6)
+    np.testing.assert_allclose(my, T32.mean(0), rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(syd, T32.std(0), rtol=1e-6)
+    np.testing.assert_allclose(Xn, (X32 - mx) / sxd, rtol=1e-6, atol=1e-6)
+    assert np.all(Xn[:, 3] == 0.0)
+    np.testing.assert_allclose(back, X32, rtol=1e-6, atol=1e-6)
+    mx, sxd, my, syd = (np.asarray(a, np.float64) for a in (mx, sxd, my, syd))
+    W1, b1, W2, b2, W3, b3 = params
+    expect = [W1 / sxd[None, :], b1 - W1 @ (mx / sxd), W2, b2, syd[:, None] * W3, syd * b3 + my]
+    for k, (a, b) in enumerate(zip(folded, expect)):
+        np.testing.assert_allclose(a, b, rtol=1e-6, atol=1e-6 * np.abs(b).max(), err_msg=str(k))
+    ref = R.forward(params, (X32 - mx) / sxd)[0] * syd + my
+    got = R.forward(folded, X32)[0]
+    np.testing.assert_allclose(got, ref, rtol=1e-5, atol=1e-5 * np.abs(ref).max())

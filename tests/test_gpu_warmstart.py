@@ -47,29 +47,33 @@ def test_warm_start_gains_over_cold_start():
     ok = W.settled(tb, te, cost_ub) & np.all(np.isfinite(T), axis=1)
     print(f"[warm] kept {ok.sum()} of {ok.size} training scenarios", flush=True)
     Dtr, T = Dtr[ok], T[ok]
-    sx, st = W.Standardizer.fit(Dtr), W.Standardizer.fit(T)
-    X = torch.tensor(sx.apply(Dtr), dtype=torch.float32, device="cuda")
-    Y = torch.tensor(st.apply(T), dtype=torch.float32, device="cuda")
     rng = np.random.default_rng(0)
     from oracle import mlp as R  # initial weights only (He initialisation)
     dims = (base.n_bus, 1024, 1024, 2 * base.n_line + 1)
     with _abi.MLP(*dims, max_batch=256) as model:
+        # standardised inputs and targets, by the library on the device
+        Xraw = torch.tensor(Dtr, dtype=torch.float32, device="cuda")
+        Traw = torch.tensor(T, dtype=torch.float32, device="cuda")
+        sx, st = W.Standardizer.fit(model, Xraw), W.Standardizer.fit(model, Traw)
+        X, Y = sx.apply(model, Xraw), st.apply(model, Traw)
         model.set_params([p.astype(np.float32) for p in R.init_params(rng, dims)])
         losses = W.train(model, X, Y, epochs=15, batch=256, lr=1e-3,
                          log=lambda s: print("[warm]", s, flush=True))
         assert losses[-1] < 0.5 * losses[0]
-        start_host = W.predict(model, Dev, sx, st, base.n_line)
+        start_std = W.predict(model, Dev, sx, st).cpu().numpy().astype(np.float64)
         # the standardisations folded into the weights: raw loads in, raw
         # multipliers out, handed over on the device
-        model.set_params(W.fold_standardizers(model.get_params(), sx, st))
+        W.fold_standardizers(model, sx, st)
         print("[warm] optima", flush=True)
         opt = highs_optima(net, base, Dev)
         keep = np.isfinite(opt)
         Dev, opt = Dev[keep], opt[keep]
         start = W.predict_dev(model, Dev)
-    lam_h, mp_h, mm_h = (a[keep] for a in start_host)
-    Yh = start.cpu().numpy().astype(np.float64)
     nl = base.n_line
+    start_std = start_std[keep]
+    lam_h, mp_h, mm_h = (start_std[:, -1], np.maximum(start_std[:, :nl], 0),
+                         np.maximum(start_std[:, nl:2 * nl], 0))
+    Yh = start.cpu().numpy().astype(np.float64)
     scale = np.abs(mp_h).max() + np.abs(mm_h).max() + 1.0
     # same network up to the BF16 rounding of the folded weights
     assert np.abs(np.maximum(Yh[:, :nl], 0) - mp_h).max() <= 3e-2 * scale

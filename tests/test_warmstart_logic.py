@@ -1,5 +1,6 @@
 """Host logic of the warm-start pipeline (no GPU): the fallback combination,
-the standardiser and the capped median."""
+the settled test and the capped median.  (Standardisation and folding run
+in the library: tests/test_gpu_mlp.py.)"""
 import numpy as np
 
 from paper_2406_13191_amd import warmstart as W
@@ -19,18 +20,6 @@ def test_fallback_rule():
     np.testing.assert_array_equal(used, [True, True, False, True, False, False])
 
 
-def test_standardizer_roundtrip_and_constant_columns():
-    rng = np.random.default_rng(0)
-    a = rng.normal(3, 2, (100, 5))
-    a[:, 2] = 7.0
-    s = W.Standardizer.fit(a)
-    z = s.apply(a)
-    np.testing.assert_allclose(z[:, [0, 1, 3, 4]].mean(0), 0, atol=1e-12)
-    np.testing.assert_allclose(z[:, [0, 1, 3, 4]].std(0), 1, atol=1e-12)
-    np.testing.assert_allclose(z[:, 2], 0, atol=1e-12)
-    np.testing.assert_allclose(s.invert(z), a, atol=1e-12)
-
-
 def test_median_counts_unreached_at_cap():
     assert W.median_iters(np.array([10, -1, -1]), 5000) == 5000
     assert W.median_iters(np.array([10, 20, -1]), 5000) == 20
@@ -43,21 +32,3 @@ def test_settled_drops_rising_and_oversized_bounds():
     ok = W.settled(bound, earlier, cost_ub=1000.0, rel=1e-3)
     # settled; rose 10 %; flat; above the largest cost; NaN; infinite history
     assert ok.tolist() == [True, False, True, False, False, False]
-
-
-def test_folded_standardisers_are_the_same_network():
-    """fold_standardizers: the network on raw inputs with folded parameters
-    equals the de-standardised output of the original on standardised
-    inputs (FP64 reference forward)."""
-    from oracle import mlp as R
-    rng = np.random.default_rng(4)
-    dims = (12, 16, 16, 9)
-    params = R.init_params(rng, dims)
-    X = rng.lognormal(0.0, 1.0, (40, dims[0]))
-    T = rng.normal(3.0, 2.0, (40, dims[-1]))
-    sx, st = W.Standardizer.fit(X), W.Standardizer.fit(T)
-    folded = [np.asarray(p, np.float64) for p in W.fold_standardizers(params, sx, st)]
-    ref = st.invert(R.forward([np.asarray(p, np.float64) for p in params], sx.apply(X))[0])
-    got = R.forward(folded, X)[0]
-    # the folded parameters are stored in FP32
-    np.testing.assert_allclose(got, ref, rtol=1e-5, atol=1e-5 * np.abs(ref).max())
