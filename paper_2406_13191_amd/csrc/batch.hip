@@ -43,6 +43,7 @@ namespace {
 struct BNet {
   int n_l, n_c, n_g, B, Bp, ldl, ldc, ncp, nlp, S, kchunk, inst0, ntl;
   int cfg_w, cfg_f;  // workgroup tile shape codes of the W and F products
+  int nt_panel;      // panel operands read nontemporally (a panel too large to stay cached)
   double alpha, rho;
   const __bf16 *PT_hi, *PT_lo, *P_hi, *P_lo;
   const double *P64T;
@@ -121,6 +122,13 @@ template <typename T> __device__ __forceinline__ void st_at(T *p, unsigned byte_
 // partial of its column in registers)
 constexpr int kMaxSplit = 32;
 
+// Split panels (hi and lo, both orientations) of at least this many bytes
+// are read nontemporally
+#ifndef DCOPF_BATCH_NT_PANEL_BYTES
+#define DCOPF_BATCH_NT_PANEL_BYTES (128.0 * 1024 * 1024)
+#endif
+constexpr double kNtPanelBytes = DCOPF_BATCH_NT_PANEL_BYTES;
+
 // ---------------------------------------------------------------------------
 // Workgroup tile of a split-BF16 product, staged through LDS.
 //
@@ -147,7 +155,8 @@ __device__ __forceinline__ void tile_mma(const __bf16 *__restrict__ Ah,
                                          const __bf16 *__restrict__ Bh,
                                          const __bf16 *__restrict__ Bl, int ldb, int kb, int ke,
                                          TileLds<BM, BN> &sm,
-                                         f32x16 (&acc)[BM / (WM * 32)][BN / (WN * 32)]) {
+                                         f32x16 (&acc)[BM / (WM * 32)][BN / (WN * 32)],
+                                         bool nt_b) {
   constexpr int TM = BM / (WM * 32), TN = BN / (WN * 32);
   constexpr int RA = BM / 32, RB = BN / 32;  // 32-row groups per operand tile
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -166,8 +175,13 @@ __device__ __forceinline__ void tile_mma(const __bf16 *__restrict__ Ah,
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       const size_t off = (size_t)(r * 32 + lrow) * ldb + k + lchunk;
-      pb[0][r] = ldg(reinterpret_cast<const bf16x8 *>(Bh + off));
-      pb[1][r] = ldg(reinterpret_cast<const bf16x8 *>(Bl + off));
+      if (nt_b) {
+        pb[0][r] = __builtin_nontemporal_load(reinterpret_cast<const bf16x8 *>(Bh + off));
+        pb[1][r] = __builtin_nontemporal_load(reinterpret_cast<const bf16x8 *>(Bl + off));
+      } else {
+        pb[0][r] = ldg(reinterpret_cast<const bf16x8 *>(Bh + off));
+        pb[1][r] = ldg(reinterpret_cast<const bf16x8 *>(Bl + off));
+      }
     }
   };
   const int fr = lane & 31, fk = (lane >> 5) * 8;
@@ -259,7 +273,8 @@ __device__ __forceinline__ void wgemm_body(const BNet &N, int4 t, unsigned char 
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
   tile_mma<BM, BN, WM, WN, LOLO>(N.V_hi + (size_t)m0 * N.ldl, N.V_lo + (size_t)m0 * N.ldl,
                                  N.ldl, N.PT_hi + (size_t)n0 * N.ldl,
-                                 N.PT_lo + (size_t)n0 * N.ldl, N.ldl, kb, ke, sm, acc);
+                                 N.PT_lo + (size_t)n0 * N.ldl, N.ldl, kb, ke, sm, acc,
+                                 N.nt_panel != 0);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / WN, wn = wave % WN;
 #pragma unroll
@@ -478,7 +493,8 @@ __device__ __forceinline__ void fgemm_body(const BNet &N, int4 t, const BScal *s
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
   tile_mma<BM, BN, WM, WN, LOLO>(N.X_hi + (size_t)m0 * N.ldc, N.X_lo + (size_t)m0 * N.ldc,
                                  N.ldc, N.P_hi + (size_t)n0 * N.ldc,
-                                 N.P_lo + (size_t)n0 * N.ldc, N.ldc, 0, N.ldc, sm, acc);
+                                 N.P_lo + (size_t)n0 * N.ldc, N.ldc, 0, N.ldc, sm, acc,
+                                 N.nt_panel != 0);
   const long long k = sc->it[par].k;
   const double kk = (double)k;
   const float a = (float)((prm.decay == 0.0 ? N.alpha : N.alpha / (1.0 + prm.decay * kk)));
@@ -1609,10 +1625,13 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
   N.inst0 = inst0;
   N.alpha = n.alpha;
   N.rho = n.rho;
-  // default shapes: instances along the workgroup when there are many
   // default shapes: tall tiles when there are many instances, wide otherwise
   N.cfg_w = B >= 128 ? 0 : (B > 32 ? 1 : 2);
   N.cfg_f = N.cfg_w;
+  // a network whose split panels (both orientations) would take most of the
+  // last-level cache streams them nontemporally, leaving the cache to the
+  // other networks' panels and the line state
+  N.nt_panel = (double)4 * 2 * (double)nl * (double)nc >= kNtPanelBytes ? 1 : 0;
   set_split(N, N.Bp >= 256 ? 1 : std::max(1, N.ldl / 2048));
   const size_t Bp = N.Bp, ldl = N.ldl, ldc = N.ldc, ncp = N.ncp, nlp = N.nlp;
   __bf16 *PT_hi = balloc<__bf16>(own, ncp * ldl, &ok), *PT_lo = balloc<__bf16>(own, ncp * ldl, &ok);

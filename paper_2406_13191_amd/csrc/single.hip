@@ -1027,18 +1027,17 @@ __device__ __forceinline__ void lane_units(double w, double lam, int g0, int g1,
   *phij = ph;
 }
 
-// Unit pass of the read-once iteration k.  Workgroup j owns the 16 columns
-// 16 j .. 16 j + 15; thread (r, c) = (t / 16, t % 16) loads the partials
-// g = r, r + 16, ... (< 16 MP of them) of column 16 j + c, all before its
-// first wait, and sums them in FP64 in that order; the 16 row sums of a
-// column meet in LDS in row order.  Wavefront 0 folds iteration k-1 (as the
-// column pass does), then its lanes c < 16 run the units of column 16 j + c
-// and write x; lane 0 writes the workgroup's sums of p* and phi.
-#ifndef DCOPF_UNIT_COLS
-#define DCOPF_UNIT_COLS 16
-#endif
-constexpr int kUnitCols = DCOPF_UNIT_COLS;
-template <typename T, int MP>
+// Unit pass of the read-once iteration k.  Workgroup j owns the UC columns
+// UC j .. UC j + UC - 1 (kUnitCols = UC, 16 or 64); thread (r, c) = (t / UC,
+// t % UC) loads the partials g = r, r + 256 / UC, ... (MP of them at most)
+// of column UC j + c, all before its first wait, and sums them in FP64 in
+// that order; the row sums of a column meet in LDS in row order.
+// Wavefront 0 folds iteration k-1 (as the column pass does), then its lanes
+// c < UC run the units of column UC j + c and write x; lane 0 writes the
+// workgroup's sums of p* and phi.  Every workgroup repeats the fold, whose
+// partials grow with the number of workgroups: wide panels take 64 columns
+// per workgroup, narrow ones 16 (more workgroups in flight).
+template <typename T, int MP, int kUnitCols>
 __global__ __launch_bounds__(256) void runits_kernel(
     const T *__restrict__ part_w, int gw, int ldc, int n_cols, const int *__restrict__ seg,
     const double *__restrict__ c, const double *__restrict__ q,
@@ -1649,7 +1648,7 @@ struct dcopf_dual_s {
   int line_xr = 0;  // x chunks per lane held in registers (0: LDS / global)
   // read-once iteration (line pass forms the next w's partials; unit pass)
   bool fused = false;
-  int rl_qw = 1, rl_rw = 4, rl_cpl = 1, grid_rl = 0, grid_units = 0;
+  int rl_qw = 1, rl_rw = 4, rl_cpl = 1, grid_rl = 0, grid_units = 0, unit_cols = 16;
   size_t lds_rl = 0;
   void *part_w = nullptr;  // [grid_rl][ldc] in the loop precision
   // graph of graph_iters iterations (even), starting at an even iteration
@@ -1695,6 +1694,8 @@ constexpr int kQw1MaxCpl = DCOPF_QW1_MAX_CPL;
 #define DCOPF_READ_ONCE_MIN_BYTES (10 << 20)
 #endif
 constexpr double kReadOnceMinBytes = DCOPF_READ_ONCE_MIN_BYTES;
+// Panels wider than this many columns are "wide" for the read-once layout
+constexpr int kWideUnitCols = 4096;
 static_assert(kQw1MaxCpl == 4 || kQw1MaxCpl == 12, "one-wavefront rows: 4 or 12 chunks");
 
 template <typename T, int CB, int UNR>
@@ -1798,9 +1799,9 @@ void launch_rlines(dcopf_dual_s *h, hipStream_t s, int par, int prime, hipEvent_
   }
 }
 
-template <typename T, int MP>
+template <typename T, int MP, int UC>
 void launch_runits_mp(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hipEvent_t e1) {
-  (void)launch_k(runits_kernel<T, MP>, dim3(h->grid_units), dim3(256), 0, s, e0, e1,
+  (void)launch_k(runits_kernel<T, MP, UC>, dim3(h->grid_units), dim3(256), 0, s, e0, e1,
                  (T *)h->part_w, h->grid_rl, h->ldc, h->n_cols, h->seg, h->c, h->q, h->pmin,
                  h->pmax, h->sc, par, (T *)h->xbuf, h->part_a, h->grid_units, h->part_b,
                  h->n_line_part, h->prm, h->gam, kGamCap - 1, h->psum,
@@ -1808,14 +1809,20 @@ void launch_runits_mp(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hi
 }
 
 // partials per thread: at most 16 MP line-pass workgroups
+template <typename T, int UC>
+void launch_runits_uc(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hipEvent_t e1) {
+  constexpr int NR = 256 / UC;
+  if (h->grid_rl <= NR * 4) launch_runits_mp<T, 4, UC>(h, s, par, e0, e1);
+  else if (h->grid_rl <= NR * 8) launch_runits_mp<T, 8, UC>(h, s, par, e0, e1);
+  else if (h->grid_rl <= NR * 16) launch_runits_mp<T, 16, UC>(h, s, par, e0, e1);
+  else if (h->grid_rl <= NR * 32) launch_runits_mp<T, 32, UC>(h, s, par, e0, e1);
+  else launch_runits_mp<T, 64, UC>(h, s, par, e0, e1);
+}
+
 template <typename T>
 void launch_runits(dcopf_dual_s *h, hipStream_t s, int par, hipEvent_t e0, hipEvent_t e1) {
-  constexpr int NR = 256 / kUnitCols;
-  if (h->grid_rl <= NR * 4) launch_runits_mp<T, 4>(h, s, par, e0, e1);
-  else if (h->grid_rl <= NR * 8) launch_runits_mp<T, 8>(h, s, par, e0, e1);
-  else if (h->grid_rl <= NR * 16) launch_runits_mp<T, 16>(h, s, par, e0, e1);
-  else if (h->grid_rl <= NR * 32) launch_runits_mp<T, 32>(h, s, par, e0, e1);
-  else launch_runits_mp<T, 64>(h, s, par, e0, e1);
+  if (h->unit_cols == 16) launch_runits_uc<T, 16>(h, s, par, e0, e1);
+  else launch_runits_uc<T, 64>(h, s, par, e0, e1);
 }
 
 // Partials of w = P^T v for the current multipliers (after create or a set
@@ -2080,12 +2087,18 @@ dcopf_status dcopf_dual_create(const dcopf_problem *p, const dcopf_opts *o, void
             v > 0)
           n_cu = v;
       }
-      const int target = std::max(1, kReadOnceGroupsPerCU * n_cu);
+      // wide panels: 64 columns per unit-pass workgroup and one line-pass
+      // workgroup per compute unit (half the partials); narrow ones: 16
+      // columns and two per compute unit
+      const bool wide = nc > kWideUnitCols;
+      h->unit_cols = wide ? 64 : 16;
+      const int target = std::max(1, (wide ? 1 : kReadOnceGroupsPerCU) * n_cu);
       h->grid_rl = std::min(target, (nl + rows_m - 1) / rows_m);
       h->grid_rl = std::max(1, std::min(h->grid_rl, nl));
+      h->grid_rl = std::min(h->grid_rl, (256 / h->unit_cols) * 64);  // the unit pass's limit
       h->lds_rl = (size_t)(4 / qw - 1) * h->ldc * (fp32 ? 4 : 8);
       h->n_line_part = h->grid_rl;
-      h->grid_units = (nc + kUnitCols - 1) / kUnitCols;
+      h->grid_units = (nc + h->unit_cols - 1) / h->unit_cols;
       h->panel_nt = (size_t)nl * h->ldc * (fp32 ? 4 : 8) > kMallBytes;
     }
   }
