@@ -171,9 +171,7 @@ def prep_mixed(log):
                 jobs.append((topo, light.replace(d=Dm[i], c=Cc[i])))
                 owner.append((k, i))
     log(f"HiGHS optima for {len(jobs)} LP instances")
-    with _pool(16) as pool:
-        opts = pool.map(_highs_opt, jobs, chunksize=8)
-        _finish(pool)
+    opts = _cached_optima("mixed", jobs)
     for n in nets:
         n["opt"] = np.full(n["B"], np.nan)
     for (k, i), o in zip(owner, opts):
@@ -495,6 +493,36 @@ def _highs_opt(args):
     return _lp_optimum(net, prob)
 
 
+def _cached_optima(tag, jobs):
+    """HiGHS optima of the jobs (a pool of 16 processes).  When
+    DCOPF_SYNTH_CACHE names a cache directory (as for the synthetic
+    networks), they are kept there, keyed by the instances' data and by the
+    sources of the generator and of this reference, so that later runs (a
+    profiled one, say) reuse them instead of starting the pool."""
+    import numpy as np
+    root = os.environ.get("DCOPF_SYNTH_CACHE")
+    path = None
+    if root:
+        h = hashlib.sha256()
+        for f in ("paper_2406_13191_amd/synth.py", "bench.py"):
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        for net, prob in jobs:
+            for a in (net.fbus, net.tbus, net.b, prob.gen_bus, prob.c, prob.q, prob.p_min,
+                      prob.p_max, prob.d, prob.f_max):
+                h.update(b"-" if a is None else np.ascontiguousarray(a, np.float64).tobytes())
+        path = os.path.join(root, f"highs_{tag}_{h.hexdigest()[:16]}.npy")
+        if os.path.exists(path):
+            return list(np.load(path, allow_pickle=False))
+    with _pool(16) as pool:
+        opts = pool.map(_highs_opt, jobs, chunksize=8)
+        _finish(pool)
+    if path:
+        os.makedirs(root, exist_ok=True)
+        np.save(path, np.asarray(opts, dtype=np.float64), allow_pickle=False)
+    return opts
+
+
 def prep_warmstart(args, log):
     """Host-side inputs of the warm-start workload, before any GPU call: the
     2000-bus network, training and held-out load scenarios, and the HiGHS
@@ -782,10 +810,11 @@ def bench_single(args, stream, name, net, p, steps, warmup, log, with_cpu=True,
                           "linepass (F = P x - f_d, mu step)"),
              "read_once": ("unit pass (w from the line pass's partials, inner minimiser)",
                            "line pass (F = P x - f_d, mu step, partials of the next P^T v)")}
+    first = "colpass" if scheme == "two_pass" else "unitpass"
     if ms_line >= ms_col:
         kkey, kname, kms, kbytes = "linepass", names[scheme][1], ms_line, b_line
     else:
-        kkey, kname, kms, kbytes = "colpass", names[scheme][0], ms_col, b_col
+        kkey, kname, kms, kbytes = first, names[scheme][0], ms_col, b_col
     achieved = kbytes / (kms * 1e-3) / 1e9
     traffic = measured_traffic(f"{name}/{args.panel}/{scheme}:{kkey}", SINGLE_SRC)
     it_bytes = b_col + b_line

@@ -766,7 +766,9 @@ def _install_default_allocator():
         import torch
     except ImportError:
         return
-    if torch.cuda.is_available():
+    # DCOPF_ALLOCATOR=hip keeps hipMalloc / hipFree (for tools that do not
+    # follow memory handed out by torch's pool)
+    if torch.cuda.is_available() and os.environ.get("DCOPF_ALLOCATOR", "torch") != "hip":
         use_torch_allocator()
 
 

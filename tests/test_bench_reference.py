@@ -53,7 +53,7 @@ def test_traffic_lookup_follows_source_hash():
     import re
     with open(bench.TRAFFIC_FILE) as f:
         table = json.loads(re.search(r"```json\n(.*?)\n```", f.read(), re.S).group(1))
-    key = "bus2000/genbus:colpass"
+    key = "bus2000/genbus/two_pass:colpass"
     files = ("paper_2406_13191_amd/csrc/common.h", "paper_2406_13191_amd/csrc/single.hip")
     e, cal = table["kernels"][key], table["copy_calibration"]
     if e["source_sha256"] == bench.source_sha(files):
