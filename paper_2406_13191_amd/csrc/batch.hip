@@ -57,6 +57,7 @@ struct BNet {
   const double *pmin, *pmax;                    // [n_g]
   const int *seg;                               // units of column j: seg[j] .. seg[j+1]-1
                                                 // (unit data stored column-sorted)
+  const int *ucol;                              // [n_g]: column of each unit
   double *lam, *vlam, *slam;                    // [2][B]: state used by the iteration of that parity
   double *D;                                    // [B]
   int ncb;                                      // column blocks of the unit pass
@@ -288,34 +289,10 @@ __device__ __forceinline__ void wgemm_body(const BNet &N, int4 t, unsigned char 
     }
 }
 
-template <bool LOLO>
-__global__ __launch_bounds__(256) void wgemm_kernel(const BNet *__restrict__ nets,
-                                                    const int4 *__restrict__ tiles) {
-  __shared__ __align__(16) unsigned char lds[kTileLdsBytes];
-  const int4 t = tiles[blockIdx.x];
-  const BNet &N = nets[t.x];
-#define DCOPF_WBODY(BM, BN, WM, WN) wgemm_body<BM, BN, WM, WN, LOLO>(N, t, lds)
-  DCOPF_TILE_SWITCH(N.cfg_w, DCOPF_WBODY)
-#undef DCOPF_WBODY
-}
-
-// Folding iteration k-1 of instance i: this thread's share of the partial
-// sums it left (sum of p*, sum of phi over unit-pass workgroups of parity pp;
-// line terms of the F product), to be summed over the workgroup.
-__device__ __forceinline__ void fold_partials(const BNet &N, int i, int pp, double (&f)[3]) {
-  const double *up = N.unitpart + (size_t)pp * N.ncb * N.Bp * 2;
-  for (int t = threadIdx.x; t < N.ncb; t += blockDim.x) {
-    f[0] += ldg(up + ((size_t)t * N.Bp + i) * 2);
-    f[1] += ldg(up + ((size_t)t * N.Bp + i) * 2 + 1);
-  }
-  for (int t = threadIdx.x; t < N.ntl; t += blockDim.x)
-    f[2] += ldg(N.linepart + (size_t)t * N.Bp + i);
-}
 
 // The state (lambda, velocity or first moment, second moment) of iteration
 // k from that of iteration k-1 (slot pp) and its sums f = (sum p*, sum phi,
-// line terms), and the dual value gamma of iteration k-1.  Every workgroup
-// of the instance computes it identically.
+// line terms), and the dual value gamma of iteration k-1.
 struct LamState {
   double lam, v, s, gamma;
 };
@@ -347,53 +324,108 @@ __device__ __forceinline__ LamState fold_finish(const BNet &N, int i, int pp, lo
   return r;
 }
 
+// Fold of iteration k-1 (parity pp) of instance i by one wavefront: the
+// lanes stride over the partial sums that iteration left (the unit pass's
+// sums of p* and phi per column block, the F product's line terms per 32-line
+// tile), a butterfly over the wavefront adds them up (every lane ends with
+// the same sums, in a fixed order), then lambda's state for iteration k goes
+// to slot pp ^ 1 and gamma of iteration k-1 to the ring.
+__device__ __forceinline__ void fold_wave(const BNet &N, int i, int pp, long long k_prev,
+                                          const BParams &prm, double *__restrict__ gam_ring,
+                                          long long gmask, int n_total) {
+  const int lane = threadIdx.x & 63;
+  double f[3] = {0.0, 0.0, 0.0};
+  const double *up = N.unitpart + (size_t)pp * N.ncb * N.Bp * 2;
+  for (int t = lane; t < N.ncb; t += 64) {
+    f[0] += ldg(up + ((size_t)t * N.Bp + i) * 2);
+    f[1] += ldg(up + ((size_t)t * N.Bp + i) * 2 + 1);
+  }
+  for (int t = lane; t < N.ntl; t += 64) f[2] += ldg(N.linepart + (size_t)t * N.Bp + i);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int v = 0; v < 3; ++v) f[v] += __shfl_xor(f[v], o, 64);
+  const LamState r = fold_finish(N, i, pp, k_prev, prm, f);
+  if (lane == 0) {
+    const int np = pp ^ 1;
+    N.lam[(size_t)np * N.B + i] = r.lam;
+    N.vlam[(size_t)np * N.B + i] = r.v;
+    N.slam[(size_t)np * N.B + i] = r.s;
+    gam_ring[(size_t)(k_prev & gmask) * n_total + N.inst0 + i] = r.gamma;
+  }
+}
+
+// Workgroups 0 .. n_tiles-1: the W product's tiles.  The ones after them
+// (dispatched last, so they fill the tail of the launch) fold iteration k-1
+// of four instances each, one per wavefront, so that the unit pass of
+// iteration k finds lambda ready.
+template <bool LOLO>
+__global__ __launch_bounds__(256) void wgemm_kernel(const BNet *__restrict__ nets,
+                                                    const int4 *__restrict__ tiles, int n_tiles,
+                                                    const int2 *__restrict__ inst_tab,
+                                                    const BScal *sc, int par, BParams prm,
+                                                    double *__restrict__ gam_ring,
+                                                    long long gmask, int n_total) {
+  __shared__ __align__(16) unsigned char lds[kTileLdsBytes];
+  if ((int)blockIdx.x >= n_tiles) {
+    const BIter it = sc->it[par];
+    const int slot = ((int)blockIdx.x - n_tiles) * 4 + (int)(threadIdx.x >> 6);
+    if (it.pending && slot < n_total) {
+      const int2 e = inst_tab[slot];
+      fold_wave(nets[e.x], e.y, par ^ 1, it.k - 1, prm, gam_ring, gmask, n_total);
+    }
+    return;
+  }
+  const int4 t = tiles[blockIdx.x];
+  const BNet &N = nets[t.x];
+#define DCOPF_WBODY(BM, BN, WM, WN) wgemm_body<BM, BN, WM, WN, LOLO>(N, t, lds)
+  DCOPF_TILE_SWITCH(N.cfg_w, DCOPF_WBODY)
+#undef DCOPF_WBODY
+}
+
 // ---------------------------------------------------------------------------
-// Unit pass: workgroup (instance i, column block cb) handles the kUnitCols
-// columns cb*kUnitCols .. , kUnitCPT per thread (columns t and t + 256).
-// Every load that does not depend on lambda (the K-split partials of w, the
-// columns' first units, the previous iteration's partial sums) is issued
-// before the first wait.  The previous iteration is then folded (every
-// workgroup of the instance identically, so lambda needs no extra launch;
-// workgroup cb = 0 records lambda's state and gamma), and the columns'
-// reduced costs, inner minimiser, injections X (BF16 hi/lo) and
-// per-workgroup sums of p* and phi follow.  MAXS bounds the K split.
+// Unit pass: workgroup (instance i, column block cb) handles the columns
+// jb = cb kUnitCols .. je - 1, kUnitCPT per thread (columns jb + t and
+// jb + t + 256), and their units ub .. ue - 1 (unit data are stored
+// column-sorted, so a block's units are contiguous).  Every load that does
+// not depend on lambda is issued first: for the thread's columns the K-split
+// partials of w and the unit boundaries, for its units (one per thread and
+// round, consecutive threads on consecutive units) their data and column.
+// Lambda of this iteration was folded in the W launch.  Then w of every
+// column goes to LDS; the units are evaluated (reduced cost, inner
+// minimiser, phi) into LDS, kUnitChunk at a time; each column adds its
+// units' p* and phi in unit order; the injections X (BF16 hi/lo) and the
+// workgroup's sums of p* and phi are stored.  MAXS bounds the K split.
 // ---------------------------------------------------------------------------
 constexpr int kUnitCPT = 2;
 constexpr int kUnitCols = 256 * kUnitCPT;
+constexpr int kUnitRounds = 3;  // units per thread and chunk
+constexpr int kUnitChunk = 256 * kUnitRounds;
 
 template <int MAXS>
 __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ nets,
                                                     const int4 *__restrict__ unit_tab,
-                                                    BScal *sc, int par, BParams prm,
-                                                    double *__restrict__ gam_ring,
-                                                    long long gmask, int n_total) {
-  __shared__ double red[3 * 4];
+                                                    BScal *sc, int par) {
+  __shared__ double wcol[kUnitCols];
+  __shared__ double pch[kUnitChunk], phch[kUnitChunk];
+  __shared__ double red[2 * 4];
   const int4 e = unit_tab[blockIdx.x];
   const BNet &N = nets[e.x];
   const int i = e.y, cb = e.z;
-  const BIter it = sc->it[par];
+  const int jb = cb * kUnitCols, je = min(N.n_c, jb + kUnitCols);
+  const int ub = ldg(N.seg + jb), ue = ldg(N.seg + je);
   // loads are issued unconditionally from clamped (in-range) indices and
   // masked afterwards, so that none of them waits for another
   int jj[kUnitCPT], u0[kUnitCPT], u1[kUnitCPT];
   bool valid[kUnitCPT];
 #pragma unroll
   for (int h = 0; h < kUnitCPT; ++h) {
-    const int j = cb * kUnitCols + h * 256 + threadIdx.x;
-    valid[h] = j < N.n_c;
-    jj[h] = valid[h] ? j : 0;
+    const int j = jb + h * 256 + threadIdx.x;
+    valid[h] = j < je;
+    jj[h] = valid[h] ? j : jb;
     u0[h] = ldg(N.seg + jj[h]);
     u1[h] = ldg(N.seg + jj[h] + 1);
     if (!valid[h]) u1[h] = u0[h];
-  }
-  const double *ci = N.c + (size_t)i * N.n_g, *qi = N.q + (size_t)i * N.n_g;
-  double c0[kUnitCPT], q0[kUnitCPT], lo0[kUnitCPT], hi0[kUnitCPT];
-#pragma unroll
-  for (int h = 0; h < kUnitCPT; ++h) {
-    const int uc = u0[h] < u1[h] ? u0[h] : 0;
-    c0[h] = ldg(ci + uc);
-    q0[h] = ldg(qi + uc);
-    lo0[h] = ldg(N.pmin + uc);
-    hi0[h] = ldg(N.pmax + uc);
   }
   // all K-split partials of w at once (S <= MAXS), summed in split order
   float wpart[kUnitCPT][MAXS];
@@ -409,23 +441,20 @@ __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ net
       }
     }
   }
-  double f[3] = {0.0, 0.0, 0.0};
-  if (it.pending) fold_partials(N, i, par ^ 1, f);
-  block_sums<3>(f, red);
-  double lam;
-  if (it.pending) {
-    const LamState r = fold_finish(N, i, par ^ 1, it.k - 1, prm, f);
-    lam = r.lam;
-    if (cb == 0 && threadIdx.x == 0) {
-      N.lam[(size_t)par * N.B + i] = r.lam;
-      N.vlam[(size_t)par * N.B + i] = r.v;
-      N.slam[(size_t)par * N.B + i] = r.s;
-      gam_ring[(size_t)((it.k - 1) & gmask) * n_total + N.inst0 + i] = r.gamma;
-    }
-  } else {
-    lam = N.lam[(size_t)par * N.B + i];
+  const double *ci = N.c + (size_t)i * N.n_g, *qi = N.q + (size_t)i * N.n_g;
+  double cu[kUnitRounds], qu[kUnitRounds], lo[kUnitRounds], hi[kUnitRounds];
+  int uj[kUnitRounds];
+#pragma unroll
+  for (int a = 0; a < kUnitRounds; ++a) {
+    const int u = ub + a * 256 + threadIdx.x;
+    const int uc = u < ue ? u : ub;
+    cu[a] = ldg(ci + uc);
+    qu[a] = ldg(qi + uc);
+    lo[a] = ldg(N.pmin + uc);
+    hi[a] = ldg(N.pmax + uc);
+    uj[a] = ldg(N.ucol + uc);
   }
-  double xs = 0.0, phs = 0.0;
+  const double lam = N.lam[(size_t)par * N.B + i];
   const bool avg = sc->avg_on;
 #pragma unroll
   for (int h = 0; h < kUnitCPT; ++h) {
@@ -433,26 +462,51 @@ __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ net
     double w = 0.0;
 #pragma unroll
     for (int t = 0; t < MAXS; ++t) w += (double)wpart[h][t];
-    double x = 0.0;
-    for (int u = u0[h]; u < u1[h]; ++u) {
-      double cu = c0[h], qu = q0[h], lo = lo0[h], hi = hi0[h];
-      if (u != u0[h]) {
-        cu = ci[u];
-        qu = qi[u];
-        lo = N.pmin[u];
-        hi = N.pmax[u];
+    wcol[jj[h] - jb] = w;
+  }
+  double x[kUnitCPT], phs = 0.0;
+#pragma unroll
+  for (int h = 0; h < kUnitCPT; ++h) x[h] = 0.0;
+  for (int cs = ub; cs < ue; cs += kUnitChunk) {  // uniform: every block has a unit
+    __syncthreads();  // w is in LDS; the previous chunk has been added up
+#pragma unroll
+    for (int a = 0; a < kUnitRounds; ++a) {
+      const int u = cs + a * 256 + threadIdx.x;
+      if (u >= ue) continue;
+      double cc = cu[a], qq = qu[a], ll = lo[a], hh = hi[a];
+      int j = uj[a];
+      if (cs != ub) {  // beyond the first chunk (rare): loaded here
+        cc = ci[u];
+        qq = qi[u];
+        ll = N.pmin[u];
+        hh = N.pmax[u];
+        j = N.ucol[u];
       }
-      const double r = cu - lam + w;
-      const double p = inner_min_b(r, qu, lo, hi);
-      phs += r * p + qu * p * p;
-      x += p;
+      const double r = cc - lam + wcol[j - jb];
+      const double p = inner_min_b(r, qq, ll, hh);
+      pch[u - cs] = p;
+      phch[u - cs] = r * p + qq * p * p;
       if (avg) N.psum[(size_t)i * N.n_g + u] += p;  // unit u of instance i: one owner
     }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < kUnitCPT; ++h) {
+      const int a0 = max(u0[h], cs), a1 = min(u1[h], cs + kUnitChunk);
+      for (int u = a0; u < a1; ++u) {
+        x[h] += pch[u - cs];
+        phs += phch[u - cs];
+      }
+    }
+  }
+  double xs = 0.0;
+#pragma unroll
+  for (int h = 0; h < kUnitCPT; ++h) {
+    if (!valid[h]) continue;
     __bf16 xh, xl;
-    split_bf16((float)x, &xh, &xl);
+    split_bf16((float)x[h], &xh, &xl);
     N.X_hi[(size_t)i * N.ldc + jj[h]] = xh;
     N.X_lo[(size_t)i * N.ldc + jj[h]] = xl;
-    xs += x;
+    xs += x[h];
   }
   double sums[2] = {xs, phs};
   block_sums<2>(sums, red);
@@ -462,7 +516,7 @@ __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ net
     up[1] = sums[1];
     if (blockIdx.x == 0) {
       BIter nx;
-      nx.k = it.k + 1;
+      nx.k = sc->it[par].k + 1;
       nx.pending = 1;
       nx.pad = 0;
       sc->it[par ^ 1] = nx;
@@ -649,22 +703,12 @@ __global__ __launch_bounds__(256) void bfinal_kernel(const BNet *__restrict__ ne
                                                      BScal *sc, int pp, long long k_prev,
                                                      BParams prm, double *__restrict__ gam_ring,
                                                      long long gmask, int n_total) {
-  __shared__ double red[3 * 4];
-  const int2 e = inst_tab[blockIdx.x];
-  const BNet &N = nets[e.x];
-  const int i = e.y;
-  double f[3] = {0.0, 0.0, 0.0};
-  fold_partials(N, i, pp, f);
-  block_sums<3>(f, red);
-  const LamState r = fold_finish(N, i, pp, k_prev, prm, f);
-  if (threadIdx.x == 0) {
-    const int np = pp ^ 1;
-    N.lam[(size_t)np * N.B + i] = r.lam;
-    N.vlam[(size_t)np * N.B + i] = r.v;
-    N.slam[(size_t)np * N.B + i] = r.s;
-    gam_ring[(size_t)(k_prev & gmask) * n_total + N.inst0 + i] = r.gamma;
-    if (blockIdx.x == 0) sc->it[np].pending = 0;
+  const int slot = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (slot < n_total) {
+    const int2 e = inst_tab[slot];
+    fold_wave(nets[e.x], e.y, pp, k_prev, prm, gam_ring, gmask, n_total);
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->it[pp ^ 1].pending = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1340,11 +1384,13 @@ void set_split(BNet &N, int S) {
 
 // the three passes of one iteration; with events e0/e1 the launch records
 // the dispatch's own start and end
-void launch_w(dcopf_batch_s *b, hipStream_t s, const int4 *tiles, int n,
+void launch_w(dcopf_batch_s *b, hipStream_t s, const int4 *tiles, int n, int par,
               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-  if (n == 0) return;
-  (void)launch_k(b->opts.lolo ? wgemm_kernel<true> : wgemm_kernel<false>, dim3(n), dim3(256), 0,
-                 s, e0, e1, b->d_nets, tiles);
+  // the tiles, then one fold workgroup per four instances
+  const int nf = (b->n_total + 3) / 4;
+  (void)launch_k(b->opts.lolo ? wgemm_kernel<true> : wgemm_kernel<false>, dim3(n + nf), dim3(256),
+                 0, s, e0, e1, b->d_nets, tiles, n, b->d_inst, b->sc, par, b->prm, b->gam,
+                 b->gcap - 1, b->n_total);
 }
 
 void launch_u(dcopf_batch_s *b, hipStream_t s, int par, hipEvent_t e0 = nullptr,
@@ -1353,7 +1399,7 @@ void launch_u(dcopf_batch_s *b, hipStream_t s, int par, hipEvent_t e0 = nullptr,
   for (auto &n : b->nets) maxs = std::max(maxs, n.d.S);
   auto kern = maxs <= 8 ? units_kernel<8> : (maxs <= 16 ? units_kernel<16> : units_kernel<32>);
   (void)launch_k(kern, dim3(b->n_units), dim3(256), 0, s, e0, e1, b->d_nets, b->d_units,
-                 b->sc, par, b->prm, b->gam, b->gcap - 1, b->n_total);
+                 b->sc, par);
 }
 
 void launch_f(dcopf_batch_s *b, hipStream_t s, const int4 *tiles, int n, int par,
@@ -1366,7 +1412,7 @@ void launch_f(dcopf_batch_s *b, hipStream_t s, const int4 *tiles, int n, int par
 void launch_iters_b(dcopf_batch_s *b, hipStream_t s, long long first, int64_t n) {
   for (int64_t t = 0; t < n; ++t) {
     const int par = (int)((first + t) & 1);
-    launch_w(b, s, b->d_wtiles, b->n_wtiles);
+    launch_w(b, s, b->d_wtiles, b->n_wtiles, par);
     launch_u(b, s, par);
     launch_f(b, s, b->d_ftiles, b->n_ftiles, par);
   }
@@ -1375,8 +1421,8 @@ void launch_iters_b(dcopf_batch_s *b, hipStream_t s, long long first, int64_t n)
 void launch_final_b(dcopf_batch_s *b, hipStream_t s) {
   if (b->iters <= 0) return;
   const int pp = (int)((b->iters - 1) & 1);  // parity of the last iteration
-  bfinal_kernel<<<b->n_total, 256, 0, s>>>(b->d_nets, b->d_inst, b->sc, pp, b->iters - 1, b->prm,
-                                           b->gam, b->gcap - 1, b->n_total);
+  bfinal_kernel<<<(b->n_total + 3) / 4, 256, 0, s>>>(b->d_nets, b->d_inst, b->sc, pp, b->iters - 1,
+                                                     b->prm, b->gam, b->gcap - 1, b->n_total);
 }
 
 // cold start (multipliers, optimiser state, V) of network `only`, or of
@@ -1610,6 +1656,9 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
   std::vector<int> seg(nc + 1, 0);
   for (int g = 0; g < ng; ++g) seg[col_of_bus[n.gen_bus[g]] + 1]++;
   for (int j = 0; j < nc; ++j) seg[j + 1] += seg[j];
+  std::vector<int> ucol(ng);
+  for (int j = 0; j < nc; ++j)
+    for (int u = seg[j]; u < seg[j + 1]; ++u) ucol[u] = j;
   hn.n_bus = nb;
   hn.gperm = gperm;
   N.n_l = nl;
@@ -1651,6 +1700,7 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
   double *c = balloc<double>(own, (size_t)B * ng, &ok), *q = balloc<double>(own, (size_t)B * ng, &ok);
   double *pmin = balloc<double>(own, ng, &ok), *pmax = balloc<double>(own, ng, &ok);
   int *dseg = balloc<int>(own, nc + 1, &ok);
+  int *ducol = balloc<int>(own, ng, &ok);
   N.lam = balloc<double>(own, (size_t)2 * B, &ok);
   N.vlam = balloc<double>(own, (size_t)2 * B, &ok);
   N.slam = balloc<double>(own, (size_t)2 * B, &ok);
@@ -1682,6 +1732,7 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
   N.pmin = pmin;
   N.pmax = pmax;
   N.seg = dseg;
+  N.ucol = ducol;
   N.D = D;
   hipStream_t s = b->stream;
   hipError_t e = hipSuccess;
@@ -1743,6 +1794,7 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
     chk(hipMemcpyAsync(pmin, lo.data(), ng * 8, hipMemcpyHostToDevice, s));
     chk(hipMemcpyAsync(pmax, hi.data(), ng * 8, hipMemcpyHostToDevice, s));
     chk(hipMemcpyAsync(dseg, seg.data(), (nc + 1) * 4, hipMemcpyHostToDevice, s));
+    chk(hipMemcpyAsync(ducol, ucol.data(), (size_t)ng * 4, hipMemcpyHostToDevice, s));
     chk(hipMemcpyAsync(D, Dh.data(), B * 8, hipMemcpyHostToDevice, s));
     chk(hipMemsetAsync(N.X_hi, 0, Bp * ldc * 2, s));
     chk(hipMemsetAsync(N.X_lo, 0, Bp * ldc * 2, s));
@@ -2367,7 +2419,7 @@ dcopf_status dcopf_batch_time_phases(dcopf_batch_t b, int64_t n, double *ms_out)
   for (int64_t t = 0; t < n; ++t) {
     const int par = (int)((b->iters + t) & 1);
     hipEvent_t *E = &ev[6 * t];
-    launch_w(b, b->stream, b->d_wtiles, b->n_wtiles, E[0], E[1]);
+    launch_w(b, b->stream, b->d_wtiles, b->n_wtiles, par, E[0], E[1]);
     launch_u(b, b->stream, par, E[2], E[3]);
     launch_f(b, b->stream, b->d_ftiles, b->n_ftiles, par, E[4], E[5]);
   }

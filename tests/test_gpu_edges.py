@@ -1,6 +1,7 @@
 """Edge cases of the HIP paths against the FP64 oracle or a closed form:
 columns carrying more units than a wavefront has lanes (the strided unit
-loop), a batch of one instance (padded to a full tile) against the
+loop) and a column block with more units than the batched unit pass
+evaluates at once, a batch of one instance (padded to a full tile) against the
 single-instance path, the congestion-free case where DCOPF is economic
 dispatch (lambda* by bisection, mu stays 0), a two-bus batch with a
 single panel column, and a panel too large for the last-level cache (the
@@ -19,11 +20,12 @@ def _abi():
     return _abi
 
 
-def crowded_columns():
-    """The 300-bus network with 200 QP units on three buses (150, 30, 20)."""
+def crowded_columns(counts=((17, 150), (40, 30), (123, 20))):
+    """The 300-bus network with QP units crowded on a few buses (default: 200
+    units on three buses, 150, 30 and 20)."""
     _, p = synth.make_network("geo300", 7)
     rng = np.random.default_rng(11)
-    gen_bus = np.array([17] * 150 + [40] * 30 + [123] * 20, np.int32)
+    gen_bus = np.array([b for b, n in counts for _ in range(n)], np.int32)
     pmax = rng.uniform(10.0, 60.0, gen_bus.size)
     return p.replace(gen_bus=gen_bus, c=rng.uniform(10.0, 60.0, gen_bus.size),
                      q=rng.uniform(0.005, 0.05, gen_bus.size), p_min=np.zeros(gen_bus.size),
@@ -64,6 +66,32 @@ def test_units_beyond_a_wavefront_batched():
         o = D.ascent(D.canonical(p.replace(d=Dm[i], c=Cc[i], q=Q[i])), 150, alpha=1e-4, rho=0.99)
         rel = np.abs(g[:, i] - o.gammas) / np.maximum(np.abs(o.gammas), 1.0)
         assert rel.max() <= 1e-4
+
+
+def test_units_beyond_a_chunk_batched():
+    # 1000 units in one column block: the batched unit pass evaluates them in
+    # chunks of 768, and the second column's 300 units straddle the boundary
+    A = _abi()
+    p = crowded_columns(((17, 500), (40, 300), (123, 150), (200, 50)))
+    # enough generation for the load: the 1000 units share the same total
+    # capacity scaled to the network's load
+    p = p.replace(p_max=p.p_max * (1.6 * p.d.sum() / p.p_max.sum()))
+    B = 2
+    rng = np.random.default_rng(13)
+    Dm = np.tile(p.d, (B, 1)) * rng.uniform(0.9, 1.1, (B, 1))
+    Cc = np.tile(p.c, (B, 1)) * rng.uniform(0.95, 1.05, (B, p.n_gen))
+    Q = np.tile(p.q, (B, 1))
+    net = A.BatchNetwork(p, Dm, Cc, Q, alpha=1e-4, rho=0.99)
+    with A.BatchSolver([net]) as b:
+        b.step(150)
+        g = b.gammas(0, 150)
+        lam, mu_p, mu_m = b.get_multipliers(0)
+    for i in range(B):
+        o = D.ascent(D.canonical(p.replace(d=Dm[i], c=Cc[i], q=Q[i])), 150, alpha=1e-4, rho=0.99)
+        rel = np.abs(g[:, i] - o.gammas) / np.maximum(np.abs(o.gammas), 1.0)
+        print(f"instance {i}: worst relative gamma deviation {rel.max():.2e}", flush=True)
+        assert rel.max() <= 1e-4
+        assert abs(lam[i] - o.state.lam) <= 1e-4 * max(abs(o.state.lam), 1.0)
 
 
 @pytest.mark.usefixtures("both_schemes")
