@@ -530,6 +530,10 @@ __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ net
 // ---------------------------------------------------------------------------
 // rows of an accumulator whose state is loaded before any of it is stored
 constexpr int kEpiChunk = 8;
+// row stride (doubles) of the line-term buffer: 33 keeps the half-wavefront
+// row writes and the quarter-row reads on few shared banks
+constexpr int kTermStride = 33;
+static_assert(4 * 16 * kTermStride * 8 <= (int)sizeof(TileLds<32, 128>), "LDS");
 
 
 template <int BM, int BN, int WM, int WN, bool LOLO>
@@ -574,6 +578,11 @@ __device__ __forceinline__ void fgemm_body(const BNet &N, int4 t, const BScal *s
   __bf16 *__restrict__ vhi = N.V_hi;
   __bf16 *__restrict__ vlo = N.V_lo;
   const bool need_v = prm.rule != DCOPF_RULE_ADAGRAD, need_s = prm.rule != DCOPF_RULE_GDM;
+  // the line terms of a chunk's 16 instance rows (8 per half-wavefront) go
+  // through this wavefront's [16][33] FP64 buffer in the tile's LDS, free
+  // once every wavefront has left the K loop
+  __syncthreads();
+  double *tb = reinterpret_cast<double *>(lds) + wave * 16 * kTermStride;
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     const int nsub = n0 + (wn * TN + j) * 32;  // first line of this 32-line tile
@@ -672,11 +681,21 @@ __device__ __forceinline__ void fgemm_body(const BNet &N, int4 t, const BScal *s
           st_at(vhi, bo >> 1, hi);
           st_at(vlo, bo >> 1, lo);
         }
-        // line terms of instance i summed over the 32 lines of this tile
         if (!ok) term = 0.0;
+        tb[(c + 8 * (lane >> 5)) * kTermStride + (lane & 31)] = term;
+      }
+      // line terms of each instance row summed over the 32 lines of this
+      // tile: lane (row r, quarter q) adds lines 8q .. 8q + 7 in order, then
+      // the four quarters are added (in the same order on every lane)
+      {
+        const int r = lane & 15, q = lane >> 4;
+        double sum = 0.0;
 #pragma unroll
-        for (int off = 16; off > 0; off >>= 1) term += __shfl_xor(term, off, kWave);
-        if ((lane & 31) == 0 && i < N.B) N.linepart[(size_t)(nsub / 32) * N.Bp + i] = term;
+        for (int x = 0; x < 8; ++x) sum += tb[r * kTermStride + q * 8 + x];
+        sum += __shfl_xor(sum, 16, kWave);
+        sum += __shfl_xor(sum, 32, kWave);
+        const int i = mb + mfma32_row(h + (r & 7), (r >> 3) * 32);
+        if (q == 0 && i < N.B) N.linepart[(size_t)(nsub / 32) * N.Bp + i] = sum;
       }
       }
     }
