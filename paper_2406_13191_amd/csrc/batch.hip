@@ -387,7 +387,9 @@ __global__ __launch_bounds__(256) void wgemm_kernel(const BNet *__restrict__ net
 // Unit pass: workgroup (instance i, column block cb) handles the columns
 // jb = cb kUnitCols .. je - 1, kUnitCPT per thread (columns jb + t and
 // jb + t + 256), and their units ub .. ue - 1 (unit data are stored
-// column-sorted, so a block's units are contiguous).  Every load that does
+// column-sorted, so a block's units are contiguous; the workgroup's entry of
+// the unit table carries ub and ue, so no unit load waits for a boundary
+// lookup).  Every load that does
 // not depend on lambda is issued first: for the thread's columns the K-split
 // partials of w and the unit boundaries, for its units (one per thread and
 // round, consecutive threads on consecutive units) their data and column.
@@ -410,10 +412,9 @@ __global__ __launch_bounds__(256) void units_kernel(const BNet *__restrict__ net
   __shared__ double pch[kUnitChunk], phch[kUnitChunk];
   __shared__ double red[2 * 4];
   const int4 e = unit_tab[blockIdx.x];
-  const BNet &N = nets[e.x];
-  const int i = e.y, cb = e.z;
+  const BNet &N = nets[e.x & 0xffff];
+  const int i = e.y, cb = e.x >> 16, ub = e.z, ue = e.w;
   const int jb = cb * kUnitCols, je = min(N.n_c, jb + kUnitCols);
-  const int ub = ldg(N.seg + jb), ue = ldg(N.seg + je);
   // loads are issued unconditionally from clamped (in-range) indices and
   // masked afterwards, so that none of them waits for another
   int jj[kUnitCPT], u0[kUnitCPT], u1[kUnitCPT];
@@ -1283,6 +1284,7 @@ namespace {
 struct HostNet {
   BNet d{};  // device pointers (owned) and shapes
   std::vector<int> gperm;  // unit t of the column order is generator gperm[t]
+  std::vector<int> seg;    // units of column j: seg[j] .. seg[j+1]-1
   int n_bus = 0;
   // primal repair buffers (allocated by the network's first repair)
   struct Repair {
@@ -1319,7 +1321,8 @@ struct dcopf_batch_s {
   BNet *d_nets = nullptr;
   int4 *d_wtiles = nullptr, *d_ftiles = nullptr;
   int2 *d_inst = nullptr;   // (network, instance) per instance
-  int4 *d_units = nullptr;  // (network, instance, column block) per unit-pass workgroup
+  int4 *d_units = nullptr;  // per unit-pass workgroup: (network | column block << 16,
+                            // instance, first unit, end of its units)
   int n_wtiles = 0, n_ftiles = 0, n_total = 0, n_units = 0;
   BScal *sc = nullptr;
   double *gam = nullptr;
@@ -1680,6 +1683,7 @@ dcopf_status setup_net(dcopf_batch_s *b, HostNet &hn, const dcopf_batch_network 
     for (int u = seg[j]; u < seg[j + 1]; ++u) ucol[u] = j;
   hn.n_bus = nb;
   hn.gperm = gperm;
+  hn.seg = seg;
   N.n_l = nl;
   N.n_c = nc;
   N.n_g = ng;
@@ -1900,7 +1904,11 @@ dcopf_status dcopf_batch_create(const dcopf_batch_network *nets, int32_t n_nets,
   for (int k = 0; k < n_nets; ++k)
     for (int i = 0; i < nets[k].n_inst; ++i) {
       inst.push_back(make_int2(k, i));
-      for (int cb = 0; cb < b->nets[k].d.ncb; ++cb) units.push_back(make_int4(k, i, cb, 0));
+      for (int cb = 0; cb < b->nets[k].d.ncb; ++cb) {
+        // network and column block packed (k < 64, cb < 2^15), the block's units
+        const int jb = cb * kUnitCols, je = std::min(b->nets[k].d.n_c, jb + kUnitCols);
+        units.push_back(make_int4(k | (cb << 16), i, b->nets[k].seg[jb], b->nets[k].seg[je]));
+      }
     }
   b->n_units = (int)units.size();
   b->gcap = o.gamma_cap;
