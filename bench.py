@@ -447,10 +447,12 @@ def batch_phase_bytes(shapes, splits):
     w = u = f = 0
     for (_, nl, nc, ng, B), S in zip(shapes, splits):
         ntl = (nl + 31) // 32
-        # W: P^T hi/lo, V hi/lo read; FP32 split-K partials written
-        w += 4 * nl * nc + 4 * B * nl + 4 * S * B * nc
-        # units: partials, costs, generator bounds read; X hi/lo written
-        u += 4 * S * B * nc + 16 * B * ng + 16 * ng + 4 * B * nc + 8 * B * ntl
+        # W: P^T hi/lo, V hi/lo read; FP32 split-K partials written; the
+        # fold of the previous iteration reads its line terms
+        w += 4 * nl * nc + 4 * B * nl + 4 * S * B * nc + 8 * B * ntl
+        # units: partials, costs, generator bounds and columns read; X hi/lo
+        # written
+        u += 4 * S * B * nc + 16 * B * ng + 20 * ng + 4 * B * nc
         # F: P hi/lo, X hi/lo, f_max read; f_d, mu+-, velocity+- read,
         # mu+-, velocity+-, V hi/lo written (40 bytes per line and instance)
         f += 4 * nl * nc + 4 * B * nc + 4 * nl + 40 * B * nl + 8 * B * ntl
