@@ -221,13 +221,32 @@ inline hipError_t launch_k(void (*kernel)(KA...), dim3 grid, dim3 block, unsigne
 // 4 (m + 1) + 8 solves, each a Cholesky factorisation (ridge of ridge times
 // the largest diagonal) and two triangular solves.  Returns false when a
 // pivot was not positive.
+//
+// The factorisation is right-looking in blocks of kWsNb columns: a block's
+// panel (its columns, rows k0 .. n-1) is factored in LDS column by column,
+// with the forward substitution riding along, then the
+// trailing lower triangle in global memory takes the block's kWsNb updates
+// in column order.  The back substitution runs in blocks of kWsNb rows from
+// the bottom (a block's rows of L in LDS, its triangle by one wavefront, the
+// rows above updated in descending column order).  Every element of the
+// factor and of the solution sees the same operations in the same order as
+// in the unblocked algorithm, so the result is the same to the last bit;
+// what changes is that a column step works on the panel in LDS instead of
+// passing over the whole trailing matrix in global memory.
 // ---------------------------------------------------------------------------
+constexpr int kWsNb = 16;
+constexpr int kWsPan = kWsNb + 1;  // row stride (doubles) of the panel in LDS
+constexpr int kWsRow = 257;        // row stride (doubles) of a row block in LDS
 struct WsShared {
   int wm[256];      // working mask of rows 0..m-1
   int sidx[256];    // working rows in order, then the balance row
-  double v[256];    // right-hand side / solution, then the join test
+  double v[256];    // right-hand side (reduced in place), then the solution, then the join test
+  double z[256];    // forward, then back substitution
   double col[256];  // the factor's current column (scaled)
   double red[16];
+  // the factor's panel [256][kWsPan] while factoring, its row block
+  // [kWsNb][kWsRow] during the back substitution
+  double buf[256 * kWsPan > kWsNb * kWsRow ? 256 * kWsPan : kWsNb * kWsRow];
   int ns, pick;
 };
 
@@ -268,63 +287,83 @@ __device__ bool ws_solve(const double *G, const double *t, const int *sg, int m,
         l(a, b) = gl(sh.sidx[a], sh.sidx[b]) + (a == b ? ridge * dm : 0.0);
     for (int a = tid; a < n; a += nt) sh.v[a] = t[sh.sidx[a]];
     __syncthreads();
-    // right-looking Cholesky: every thread takes the pivot and its square
-    // root itself; the scaled column also goes to LDS for the update, and
-    // the pivot is stored once every thread has read it
-    for (int k = 0; k < n; ++k) {
-      const double d = l(k, k);
-      if (!(d > 0.0)) return false;
-      const double dk = sqrt(d);
-      for (int a = k + 1 + tid; a < n; a += nt) {
-        const double q = l(a, k) / dk;
-        l(a, k) = q;
-        sh.col[a] = q;
+    // blocked right-looking Cholesky with the forward substitution L z = v
+    double *pan = sh.buf;
+    for (int k0 = 0; k0 < n; k0 += kWsNb) {
+      const int kw = min(kWsNb, n - k0), pr = n - k0;
+      for (int e = tid; e < pr * kw; e += nt) {
+        const int a = k0 + e / kw, c = e % kw;
+        pan[(a - k0) * kWsPan + c] = (k0 + c <= a) ? l(a, k0 + c) : 0.0;
       }
       __syncthreads();
-      if (tid == 0) l(k, k) = dk;
-      for (int a = k + 1 + ty; a < n; a += ny) {
-        const double qa = sh.col[a];
-        for (int b = k + 1 + tx; b <= a; b += 32) l(a, b) -= qa * sh.col[b];
+      for (int c = 0; c < kw; ++c) {
+        const int k = k0 + c;
+        const double d = pan[c * kWsPan + c];
+        if (!(d > 0.0)) return false;  // the same value in every thread
+        const double dk = sqrt(d);
+        for (int a = k + 1 + tid; a < n; a += nt) {
+          const double q = pan[(a - k0) * kWsPan + c] / dk;
+          pan[(a - k0) * kWsPan + c] = q;
+          sh.col[a] = q;
+        }
+        __syncthreads();
+        // every thread has read the pivot and the right-hand side's row k
+        const double zk = sh.v[k] / dk;
+        if (tid == 0) {
+          pan[c * kWsPan + c] = dk;
+          sh.z[k] = zk;
+        }
+        for (int a = k + 1 + tid; a < n; a += nt) sh.v[a] -= sh.col[a] * zk;
+        // the panel's later columns b (k < b < k0 + kw), rows a >= b
+        const int cr = kw - 1 - c;  // columns left in the panel
+        for (int e = tid; e < (n - k - 1) * cr; e += nt) {
+          const int a = k + 1 + e / cr, b = k + 1 + e % cr;
+          if (b <= a) pan[(a - k0) * kWsPan + (b - k0)] -= sh.col[a] * sh.col[b];
+        }
+        __syncthreads();
+      }
+      for (int e = tid; e < pr * kw; e += nt) {
+        const int a = k0 + e / kw, c = e % kw;
+        if (k0 + c <= a) l(a, k0 + c) = pan[(a - k0) * kWsPan + c];
+      }
+      // trailing lower triangle: the block's columns in order
+      const int t0 = k0 + kw;
+      for (int a = t0 + ty; a < n; a += ny)
+        for (int b = t0 + tx; b <= a; b += 32) {
+          double acc = l(a, b);
+          for (int c = 0; c < kw; ++c)
+            acc -= pan[(a - k0) * kWsPan + c] * pan[(b - k0) * kWsPan + c];
+          l(a, b) = acc;
+        }
+      __syncthreads();
+    }
+    // back substitution L^T y = z in row blocks from the bottom
+    double *rows = sh.buf;
+    for (int k1 = n; k1 > 0; k1 -= kWsNb) {
+      const int k0 = max(0, k1 - kWsNb), kw = k1 - k0;
+      for (int e = tid; e < kw * k1; e += nt) {
+        const int r = e / k1, a = e % k1;
+        rows[r * kWsRow + a] = (a <= k0 + r) ? l(k0 + r, a) : 0.0;
+      }
+      __syncthreads();
+      if (tid < kWave) {  // the block's triangle: lane r holds z[k0 + r]
+        double zr = tid < kw ? sh.z[k0 + tid] : 0.0;
+        for (int k = k1 - 1; k >= k0; --k) {
+          const double zk = __shfl(zr, k - k0, kWave) / rows[(k - k0) * kWsRow + k];
+          if (tid == k - k0) zr = zk;
+          else if (tid < k - k0) zr -= rows[(k - k0) * kWsRow + k0 + tid] * zk;
+        }
+        if (tid < kw) sh.z[k0 + tid] = zr;
+      }
+      __syncthreads();
+      for (int a = tid; a < k0; a += nt) {
+        double acc = sh.z[a];
+        for (int k = k1 - 1; k >= k0; --k) acc -= rows[(k - k0) * kWsRow + a] * sh.z[k];
+        sh.z[a] = acc;
       }
       __syncthreads();
     }
-    // L z = t, then L^T y = z, by the first wavefront with the vector in
-    // registers (row a in slot a / 64 of lane a % 64; n <= 256)
-    if (tid < kWave) {
-      double z[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int a = q * kWave + tid;
-        z[q] = a < n ? sh.v[a] : 0.0;
-      }
-      auto pick_slot = [&](int k) {
-        const int q = k / kWave;
-        return q == 0 ? z[0] : (q == 1 ? z[1] : (q == 2 ? z[2] : z[3]));
-      };
-      for (int k = 0; k < n; ++k) {
-        const double zk = __shfl(pick_slot(k), k % kWave, kWave) / l(k, k);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int a = q * kWave + tid;
-          if (a == k) z[q] = zk;
-          else if (a > k && a < n) z[q] -= l(a, k) * zk;
-        }
-      }
-      for (int k = n - 1; k >= 0; --k) {
-        const double zk = __shfl(pick_slot(k), k % kWave, kWave) / l(k, k);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int a = q * kWave + tid;
-          if (a == k) z[q] = zk;
-          else if (a < k) z[q] -= l(k, a) * zk;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int a = q * kWave + tid;
-        if (a < n) sh.v[a] = z[q];
-      }
-    }
+    for (int a = tid; a < n; a += nt) sh.v[a] = sh.z[a];
     __syncthreads();
     for (int r = tid; r <= m; r += nt) y[r] = 0.0;
     __syncthreads();
