@@ -195,9 +195,9 @@ dcopf_status dcopf_batch_set_tiles(dcopf_batch_t b, int32_t net, const int32_t *
 
 /* Measurement: run n_iters >= 1 real iterations (they advance the batch)
  * with events attached to each dispatch (start and end of that kernel
- * alone); ms_out[0..2] = average ms of the W product, the unit pass (inner
- * minimiser, lambda step of the previous iteration) and the F product with
- * the mu step.  Synchronises.                                              */
+ * alone); ms_out[0..2] = average ms of the W product (with the lambda
+ * step of the previous iteration), the unit pass (inner minimiser) and the
+ * F product with the mu step.  Synchronises.                               */
 dcopf_status dcopf_batch_time_phases(dcopf_batch_t b, int64_t n_iters, double *ms_out);
 
 void dcopf_batch_destroy(dcopf_batch_t b);   /* NULL is a no-op              */

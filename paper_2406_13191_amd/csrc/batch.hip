@@ -9,12 +9,14 @@
 //   W product   W^T = V^T P   (M = instances, N = panel columns, K = lines)
 //               split-BF16 v_mfma_f32_32x32x16_bf16, FP32 accumulation,
 //               optional split over K for long-K / few-instance networks;
-//   unit pass   one workgroup per instance: w = sum of the K splits, reduced
-//               costs r = c - lambda + w (FP64), the closed-form inner
-//               minimiser (Sections 3.1 / 3.2), the column injections X
-//               (written as BF16 hi/lo), sum p* and sum phi, and the lambda
-//               step with the balance residual (FP64).  It also finishes the
-//               previous iteration's monitor value gamma;
+//               workgroups after the tiles fold the previous iteration: the
+//               lambda step with its balance residual (FP64) and its monitor
+//               value gamma;
+//   unit pass   one workgroup per instance and 512 columns: w = sum of the
+//               K splits, reduced costs r = c - lambda + w (FP64), the
+//               closed-form inner minimiser (Sections 3.1 / 3.2), the
+//               column injections X (written as BF16 hi/lo), sum p* and
+//               sum phi;
 //   F product   F^T = X^T P^T (M = instances, N = lines, K = columns), whose
 //               epilogue forms F - f_d, the residuals +-F - f_max, the mu
 //               step and projection (FP32 state), the next V (BF16 hi/lo) and
@@ -1566,7 +1568,10 @@ float time_iters(dcopf_batch_s *b, int reps) {
 // fixed, timing whole iterations of the full batch (so tail effects of the
 // shared launches count).  A candidate replaces the incumbent only when it
 // is at least 2 % faster, which keeps the choice stable against timing noise.
-// The iterate is disturbed; the caller resets it.
+// The iterate is disturbed; the caller resets it.  Each timing is the best
+// of three runs of kTuneReps iterations (shorter runs let timing noise pick
+// a slower W tile for the 10,000-bus network now and then).
+constexpr int kTuneReps = 20;
 hipError_t autotune(dcopf_batch_s *b) {
   const int splits[] = {1, 2, 4, 8, 16, 32};
   auto apply = [&]() -> hipError_t {
@@ -1578,7 +1583,7 @@ hipError_t autotune(dcopf_batch_s *b) {
   for (size_t k = 0; k < b->nets.size(); ++k) req_split[k] = b->nets[k].d.S;
   hipError_t e = apply();
   if (e != hipSuccess) return e;
-  float best = time_iters(b, 5);
+  float best = time_iters(b, kTuneReps);
   for (int sweep = 0; sweep < 2; ++sweep) {
     for (size_t k = 0; k < b->nets.size(); ++k) {
       BNet &N = b->nets[k].d;
@@ -1590,7 +1595,7 @@ hipError_t autotune(dcopf_batch_s *b) {
           N.cfg_w = c;
           set_split(N, S);
           if ((e = apply()) != hipSuccess) return e;
-          const float t = time_iters(b, 5);
+          const float t = time_iters(b, kTuneReps);
           if (t < 0.98f * best) best = t, bw = c, bs = S;
         }
       N.cfg_w = bw;
@@ -1601,7 +1606,7 @@ hipError_t autotune(dcopf_batch_s *b) {
         if (c == bf) continue;
         N.cfg_f = c;
         if ((e = apply()) != hipSuccess) return e;
-        const float t = time_iters(b, 5);
+        const float t = time_iters(b, kTuneReps);
         if (t < 0.98f * best) best = t, bf = c;
       }
       N.cfg_f = bf;
