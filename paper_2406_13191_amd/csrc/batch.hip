@@ -1587,9 +1587,13 @@ hipError_t autotune(dcopf_batch_s *b) {
   for (int sweep = 0; sweep < 2; ++sweep) {
     for (size_t k = 0; k < b->nets.size(); ++k) {
       BNet &N = b->nets[k].d;
+      // tile shapes whose M extent exceeds the instances (rounded up to 32)
+      // only multiply padding: not candidates
+      auto fits = [&](int c) { return kTileBM[c] <= (N.B + 31) / 32 * 32; };
       int bw = N.cfg_w, bs = req_split[k];
       for (int c = 0; c < 3; ++c)
         for (int S : splits) {
+          if (!fits(c)) continue;
           if (S > 1 && N.ldl / S < 256) continue;
           if (c == bw && S == bs) continue;
           N.cfg_w = c;
@@ -1603,7 +1607,7 @@ hipError_t autotune(dcopf_batch_s *b) {
       req_split[k] = bs;
       int bf = N.cfg_f;
       for (int c = 0; c < 3; ++c) {
-        if (c == bf) continue;
+        if (c == bf || !fits(c)) continue;
         N.cfg_f = c;
         if ((e = apply()) != hipSuccess) return e;
         const float t = time_iters(b, kTuneReps);
