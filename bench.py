@@ -252,8 +252,9 @@ def bench_mixed(args, stream, nets, log):
             single[n["name"]] = 2000 / (time.perf_counter() - t0)
     t_single = sum(n["B"] / single[n["name"]] for n in nets)
     t_batch = ms / args.steps / 1e3
-    phases = {"w": ("W product (W^T = V^T P, split-BF16 MFMA)", ms_w, bw),
-              "units": ("unit pass (reduced costs, inner minimiser, lambda step)", ms_u, bu),
+    phases = {"w": ("W product (W^T = V^T P, split-BF16 MFMA; lambda step of the previous "
+                    "iteration)", ms_w, bw),
+              "units": ("unit pass (reduced costs, inner minimiser)", ms_u, bu),
               "f": ("F product (F^T = X^T P^T, split-BF16 MFMA, mu step)", ms_f, bf)}
     key = max(phases, key=lambda k: phases[k][1])
     kname, kms, kbytes = phases[key]

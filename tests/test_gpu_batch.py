@@ -237,6 +237,34 @@ def test_split_calls_and_timed_iterations_match_one_call():
         np.testing.assert_array_equal(a.gammas(0, 13), c.gammas(0, 13))
 
 
+def test_subset_carried_into_a_new_batch_continues_bitwise():
+    # a subset of instances carried into a new batch with their whole state
+    # (get_state / set_state, the same tiles and K split) continues exactly
+    # as it would have in the full batch: every step is per instance
+    A = _abi()
+    n1, (base, Dm, Cc, Q) = batch_net("geo300q", 7, 24, 5200)
+    n2, _ = batch_net("geo300", 7, 8, 5300)
+    sel = [1, 5, 6, 17, 23]
+    with A.BatchSolver([n1, n2], graph_iters=4) as full, \
+            A.BatchSolver([n1, n2], graph_iters=4) as b:
+        tiles = [full.info(k) for k in range(2)]
+        full.step(30)
+        b.step(30)
+        st = b.split_state(0, b.get_state(0))
+        keep = {f: (v[sel] if f != "k" else v) for f, v in st.items()}
+        r = synth.STEP_RULES["geo300q"]
+        sub = A.BatchNetwork(base, Dm[sel], Cc[sel], Q[sel], alpha=r["alpha"], rho=r["rho"])
+        with A.BatchSolver([sub], graph_iters=20) as nb:
+            t = tiles[0]
+            nb.set_tiles(0, (32, 128), t["w_split"], (32, 128))
+            nb.set_state(0, A.BatchSolver.pack_state(**keep))
+            full.step(40)
+            nb.step(40)
+            np.testing.assert_array_equal(nb.bound(), full.bound()[sel])
+            for x, y in zip(nb.get_multipliers(0), full.get_multipliers(0)):
+                np.testing.assert_array_equal(x, y[sel])
+
+
 def test_set_multipliers_keeps_other_networks():
     # after an odd number of iterations, a warm start of network 1 leaves
     # network 0's iterate and optimiser state as they were
