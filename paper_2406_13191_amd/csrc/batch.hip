@@ -739,6 +739,8 @@ __global__ __launch_bounds__(256) void bfinal_kernel(const BNet *__restrict__ ne
 // Mp multiple of 64, Np multiple of 16, ld multiple of 4.  Four wavefronts
 // per workgroup along M, 16 x 16 tiles, v_mfma_f64_16x16x4f64.
 // ---------------------------------------------------------------------------
+constexpr int kDgemmAhead = 16;
+
 __global__ __launch_bounds__(256) void dgemm_nt_kernel(const double *__restrict__ A,
                                                        const double *__restrict__ Bm,
                                                        double *__restrict__ C, int ld,
@@ -750,7 +752,22 @@ __global__ __launch_bounds__(256) void dgemm_nt_kernel(const double *__restrict_
   const double *a = A + (size_t)(m0 + r) * ld + kk;
   const double *b = Bm + (size_t)(n0 + r) * ld + kk;
   f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int k = 0; k < ld; k += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k], b[k], acc, 0, 0, 0);
+  // kDgemmAhead K steps of operands are loaded before their products, so a
+  // wavefront waits once per kDgemmAhead steps instead of once per step; the
+  // products are accumulated in the same K order either way
+  int k = 0;
+  for (; k + 4 * kDgemmAhead <= ld; k += 4 * kDgemmAhead) {
+    double av[kDgemmAhead], bv[kDgemmAhead];
+#pragma unroll
+    for (int u = 0; u < kDgemmAhead; ++u) {
+      av[u] = a[k + 4 * u];
+      bv[u] = b[k + 4 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < kDgemmAhead; ++u)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+  }
+  for (; k < ld; k += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k], b[k], acc, 0, 0, 0);
   // register j of lane l holds row 4 j + l / 16, column l % 16
 #pragma unroll
   for (int j = 0; j < 4; ++j) C[(size_t)(m0 + 4 * j + kk) * ldo + n0 + r] = acc[j];
