@@ -773,53 +773,6 @@ __global__ __launch_bounds__(256) void dgemm_nt_kernel(const double *__restrict_
   for (int j = 0; j < 4; ++j) C[(size_t)(m0 + 4 * j + kk) * ldo + n0 + r] = acc[j];
 }
 
-// The same product with every wavefront computing 16 rows x 64 columns:
-// four 16 x 16 accumulators share each A operand, so the operands cross the
-// L2 about 2.5 times less often.  Np must be a multiple of 64 (grid.x =
-// Np / 64); every 16 x 16 block sees the same MFMA sequence as in
-// dgemm_nt_kernel, so the results are the same to the last bit.
-__global__ __launch_bounds__(256) void dgemm_nt64_kernel(const double *__restrict__ A,
-                                                         const double *__restrict__ Bm,
-                                                         double *__restrict__ C, int ld,
-                                                         int ldo, int Mp) {
-  constexpr int U = 8;  // K steps whose operands are loaded before their products
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int m0 = (blockIdx.y * 4 + wave) * 16, n0 = blockIdx.x * 64;
-  if (m0 >= Mp) return;
-  const int r = lane & 15, kk = lane >> 4;
-  const double *a = A + (size_t)(m0 + r) * ld + kk;
-  const double *b = Bm + (size_t)(n0 + r) * ld + kk;
-  const size_t bt = (size_t)16 * ld;  // the next 16-column block of B
-  f64x4 acc[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-  int k = 0;
-  for (; k + 4 * U <= ld; k += 4 * U) {
-    double av[U], bv[4][U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      av[u] = a[k + 4 * u];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) bv[t][u] = b[t * bt + k + 4 * u];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[t][u], acc[t], 0, 0, 0);
-  }
-  for (; k < ld; k += 4) {
-    const double x = a[k];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, b[t * bt + k], acc[t], 0, 0, 0);
-  }
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) C[(size_t)(m0 + 4 * j + kk) * ldo + n0 + 16 * t + r] = acc[t][j];
-}
-
 // V64[i][l] = mu+ - mu- (FP64 from the FP32 state) for the exact bound.
 __global__ void make_v64_kernel(const float *mu_p, const float *mu_m, int B, int n_l, int ldl,
                                 double *V64) {
@@ -1917,8 +1870,8 @@ dcopf_status eval_bounds(dcopf_batch_s *b) {
     const BNet &N = hn.d;
     dim3 vg((unsigned)std::min(64, (N.n_l + 255) / 256), (unsigned)N.B);
     make_v64_kernel<<<vg, 256, 0, s>>>(N.mu_p, N.mu_m, N.B, N.n_l, N.ldl, N.V64);
-    dim3 dg((unsigned)(N.ncp / 64), (unsigned)(N.Bp / 64));  // ncp: a multiple of 128
-    dgemm_nt64_kernel<<<dg, 256, 0, s>>>(N.V64, N.P64T, N.W64, N.ldl, N.ncp, N.Bp);
+    dim3 dg((unsigned)(N.ncp / 16), (unsigned)(N.Bp / 64));
+    dgemm_nt_kernel<<<dg, 256, 0, s>>>(N.V64, N.P64T, N.W64, N.ldl, N.ncp, N.Bp);
     bound_inst_kernel<<<N.B, 256, 0, s>>>(N, (int)(b->iters & 1));
   }
   DCOPF_HIP_TRY(hipGetLastError());
@@ -2344,8 +2297,8 @@ dcopf_status dcopf_batch_primal(dcopf_batch_t b, int32_t net, dcopf_primal *out,
   const int gc = std::max(1, std::min(kPrimalColBlocks, (N.ldc + 255) / 256));
   double *part = N.ppart, *res = N.ppart + (size_t)N.B * 2 * kPrimalColBlocks;
   bprimal_cols_kernel<<<dim3((unsigned)gc, (unsigned)N.B), 256, 0, s>>>(N, b->sc, part);
-  dim3 dg((unsigned)(N.nlp / 64), (unsigned)(N.Bp / 64));  // nlp: a multiple of 128
-  dgemm_nt64_kernel<<<dg, 256, 0, s>>>(N.X64, N.P64, N.F64, N.ldc, N.nlp, N.Bp);
+  dim3 dg((unsigned)(N.nlp / 16), (unsigned)(N.Bp / 64));
+  dgemm_nt_kernel<<<dg, 256, 0, s>>>(N.X64, N.P64, N.F64, N.ldc, N.nlp, N.Bp);
   bprimal_inst_kernel<<<N.B, 256, 0, s>>>(N, b->sc, part, gc, res);
   DCOPF_HIP_TRY(hipGetLastError());
   std::vector<double> r((size_t)N.B * 5), pb;
@@ -2422,11 +2375,11 @@ dcopf_status dcopf_batch_repair(dcopf_batch_t b, int32_t net, const double *p_in
   brep_init_kernel<<<dim3((unsigned)gi, (unsigned)B), 256, 0, s>>>(N, src, R.p, R.p0c, R.pos,
                                                                    R.st);
   std::vector<BRepState> hs(B);
-  const dim3 dg((unsigned)(N.nlp / 64), (unsigned)(N.Bp / 64));  // nlp: a multiple of 128
+  const dim3 dg((unsigned)(N.nlp / 16), (unsigned)(N.Bp / 64));
   const int ccb = (N.ldc + 255) / 256;
   for (;;) {
     brep_cols_kernel<<<dim3((unsigned)gc, (unsigned)B), 256, 0, s>>>(N, R.p, R.W, R.part);
-    dgemm_nt64_kernel<<<dg, 256, 0, s>>>(N.X64, N.P64, N.F64, N.ldc, N.nlp, N.Bp);
+    dgemm_nt_kernel<<<dg, 256, 0, s>>>(N.X64, N.P64, N.F64, N.ldc, N.nlp, N.Bp);
     brep_active_kernel<<<B, 256, 0, s>>>(N, R.part, gc, max_rounds, R.pos, R.rows, R.sgn, R.t,
                                          R.st);
     DCOPF_HIP_TRY(hipGetLastError());
