@@ -526,6 +526,68 @@ def _cached_optima(tag, jobs):
     return opts
 
 
+SCREENING = [("bus2000", 2000), ("bus2000_raw", 2000), ("bus4600", 4600), ("bus4600_raw", 4600)]
+
+
+def prep_screening(log, n_inst=32):
+    """Host-side inputs of the screening comparison: the 2000- and 4600-bus
+    networks with their default limits and with the unscreened recipe (any
+    heavily loaded line may be tightened, no limit price capped), n_inst
+    load and cost scenarios of each, and every instance's HiGHS optimum."""
+    from paper_2406_13191_amd import synth
+    with _pool(len(SCREENING)) as pool:
+        made = pool.map(_make_net, SCREENING)
+        _finish(pool)
+    nets, jobs, owner = [], [], []
+    for k, ((name, _), (topo, base, dt)) in enumerate(zip(SCREENING, made)):
+        log(f"network {name}: {dt:.1f} s")
+        Dm, Cc, Q = synth.make_scenarios(base, 7_000_000, n_inst, 0.1, 0.1)
+        nets.append(dict(name=name, topo=topo, base=base, D=Dm, C=Cc, B=n_inst))
+        light = base.replace(H=None)
+        for i in range(n_inst):
+            jobs.append((topo, light.replace(d=Dm[i], c=Cc[i])))
+            owner.append((k, i))
+    log(f"HiGHS optima for {len(jobs)} LP instances")
+    opts = _cached_optima("screening", jobs)
+    import numpy as np
+    for n in nets:
+        n["opt"] = np.full(n["B"], np.nan)
+    for (k, i), o in zip(owner, opts):
+        nets[k]["opt"][i] = o
+    return nets
+
+
+def bench_screening(args, stream, nets, log):
+    """Iterations to an exact bound within 0.1 % of the HiGHS optimum, per
+    instance, for each network of prep_screening run alone as a batch (GDM
+    with the network's frozen rule, bound checked every TTB_CHECK
+    iterations, capped at --ttb-cap)."""
+    import numpy as np
+
+    from paper_2406_13191_amd import _abi, synth
+    out = {}
+    for n in nets:
+        r = synth.STEP_RULES[n["name"]]
+        net = _abi.BatchNetwork(n["base"], n["D"], n["C"], None, alpha=r["alpha"], rho=r["rho"])
+        has = np.isfinite(n["opt"])
+        hit = np.full(n["B"], -1)
+        with _abi.BatchSolver([net], stream=stream.cuda_stream, graph_iters=20,
+                              gamma_cap=64) as b:
+            it = 0
+            while it < args.ttb_cap and np.any(hit[has] < 0):
+                b.step(TTB_CHECK)
+                it += TTB_CHECK
+                v = b.bound()
+                hit[has & (hit < 0) & (n["opt"] - v <= 1e-3 * np.abs(n["opt"]))] = it
+        h = hit[has]
+        out[n["name"]] = dict(instances=int(has.sum()),
+                              median_iterations=float(np.median(np.where(h >= 0, h, args.ttb_cap))),
+                              max_iterations=int(h.max()) if np.all(h >= 0) else None,
+                              reached=round(float((h >= 0).mean()), 3))
+        log(f"{n['name']}: median {out[n['name']]['median_iterations']:.0f} iterations")
+    return out
+
+
 def prep_warmstart(args, log):
     """Host-side inputs of the warm-start workload, before any GPU call: the
     2000-bus network, training and held-out load scenarios, and the HiGHS
@@ -914,7 +976,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="mixed",
                     help="mixed (default) | bus2000 | bus4600 | bus10000 | warmstart | ptdf | "
-                         "rules | qpdual | copy")
+                         "rules | qpdual | screening | copy")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--panel", default="genbus", choices=["genbus", "allbus"])
     ap.add_argument("--ttb-cap", type=int, default=20000,
@@ -944,6 +1006,7 @@ def main():
     # point forks or spawns processes once the GPU is in use
     nets = prep_mixed(log) if args.workload == "mixed" else None
     wprep = prep_warmstart(args, log) if args.workload == "warmstart" else None
+    sprep = prep_screening(log) if args.workload == "screening" else None
 
     from paper_2406_13191_amd import _abi, synth  # noqa: F401  (loads the library)
 
@@ -980,6 +1043,24 @@ def main():
             "config": {"workload": "10,000-bus single instance with quadratic costs (12,700 "
                                    "lines, 2500 generators), FP32 products, exact FP64 bound "
                                    "every 100 iterations", **r},
+            "roofline": None, "cpu_baseline": None,
+        }
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "screening":
+        res = bench_screening(args, stream, sprep, log)
+        out = {
+            "metric": "median iterations to an exact bound within 0.1% of the FP64 optimum, "
+                      "default against unscreened line limits",
+            "value": res["bus4600_raw"]["median_iterations"], "unit": "iterations",
+            "n_gpus": 1, "steps": args.ttb_cap, "warmup": 0, "ms_per_step": None,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3",
+            "data": "synthetic",
+            "config": {"workload": "2000- and 4600-bus networks, 32 load and cost scenarios "
+                                   "each, with the default limits and with the unscreened "
+                                   "recipe; each network alone as a batch, GDM with its frozen "
+                                   "rule, exact bound every 100 iterations",
+                       "networks": res},
             "roofline": None, "cpu_baseline": None,
         }
         print(json.dumps(out), flush=True)

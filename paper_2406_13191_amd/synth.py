@@ -360,17 +360,19 @@ def _widen_for_scenarios(net, gen_bus, p_min, p_max, d, f_max, rng, sigma=0.15,
     return f
 
 
-def _place_targets(net, gen_bus, p_min, p_max, d, f_max, F0, order, n_target):
+def _place_targets(net, gen_bus, p_min, p_max, d, f_max, F0, order, n_target, screen=True):
     """Tighten the first ``n_target`` candidate lines of ``order`` to 0.8 |F0|
     and make the instance feasible with one LP.
 
     Bridge lines and lines that no dispatch can relieve on their own are not
-    candidates.  The dispatch of least total violation is then computed; every
+    candidates (unless screen is False).  The dispatch of least total
+    violation is then computed; every
     limit it still violates is raised to REPAIR_MARGIN x that dispatch's flow,
     so that dispatch is feasible and the instance is feasible by construction.
     """
-    order = order[~_bridges(net.n_bus, net.fbus, net.tbus)[order]]
-    order = order[_relievable(net, gen_bus, p_min, p_max, d, F0, order)]
+    if screen:
+        order = order[~_bridges(net.n_bus, net.fbus, net.tbus)[order]]
+        order = order[_relievable(net, gen_bus, p_min, p_max, d, F0, order)]
     target = order[:n_target]
     f = f_max.copy()
     f[target] = 0.8 * F0[target]
@@ -402,6 +404,13 @@ NET_SPECS = {
     "bus10000": dict(recipe="geo", n_bus=10000, n_line=12700, n_gen=2500, qp=True,
                      c=(5.0, 60.0), q=(0.001, 0.05), load_frac=0.75, bind_frac=0.02),
 }
+# The same networks and loads with limits that keep what the default recipe
+# screens out: any of the upper half of lines by base flow may be tightened
+# (bridges and lines no dispatch can relieve included) and no limit price is
+# capped.  Feasibility is still made by construction, so each instance has
+# an optimum; used to measure how much the screening eases the ascent.
+for _n in ("bus2000", "bus4600"):
+    NET_SPECS[_n + "_raw"] = dict(NET_SPECS[_n], raw=True)
 
 
 def _cache_path(name: str, seed: int):
@@ -498,10 +507,12 @@ def _make_network(name: str, seed: int):
         top = np.argsort(-F0, kind="stable")[: nl // 2]
         order = rng.permutation(top)
         f_max = np.maximum(2.0 * F0, 0.5 * np.median(F0))
+        raw = spec.get("raw", False)
         f_max = _place_targets(net, gen_bus, p_min, p_max, d, f_max, F0, order,
-                               n_target)
-        f_max = _cap_prices(net, gen_bus, c, p_min, p_max, d, f_max,
-                            cap=PRICE_CAP)
+                               n_target, screen=not raw)
+        if not raw:
+            f_max = _cap_prices(net, gen_bus, c, p_min, p_max, d, f_max,
+                                cap=PRICE_CAP)
         f_max = _widen_for_scenarios(net, gen_bus, p_min, p_max, d, f_max, rng)
     net._H = None
     prob = Problem(H=H, gen_bus=gen_bus, c=c, q=q, p_min=p_min, p_max=p_max,
@@ -549,6 +560,7 @@ STEP_RULES = {
     "bus4600": dict(alpha=3e-5, rho=0.99),
     "bus10000": dict(alpha=1e-4, rho=0.99),
 }
+STEP_RULES.update({n + "_raw": STEP_RULES[n] for n in ("bus2000", "bus4600")})
 
 
 def config_problem(name: str) -> Problem:
